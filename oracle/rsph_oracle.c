@@ -1,0 +1,1034 @@
+/*
+ * rsph_oracle.c -- plain, slow, FP64 CPU oracle for the Riemann-SPH multiphase
+ * surface-tension method of Zhang, Lourenco and Hu, "Multiphase SPH for surface
+ * tension: resolving zero-surface-energy modes and achieving high Reynolds number
+ * simulations" (arXiv 2503.16082).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code, header,
+ * table or constant with the HIP library: every quantity below is computed here
+ * from the paper's equations, one function per equation, in the paper's order.
+ *
+ * Conventions (paper section 3.1): r_ij = r_i - r_j (periodic minimum image),
+ * e_ij = r_ij / |r_ij| points from j to i, grad_i W_ij = dW/dr(r_ij) e_ij.
+ * Two fluids: phase 0 is fluid k (the droplet), phase 1 is fluid l.
+ *
+ * Readings of passages that are ambiguous or garbled (each is also listed in
+ * the design notes of the repository):
+ *  - continuity (Eq. 6 with Eqs. 8-10): the Riemann axis is the i->j direction,
+ *    so (v_i - v*) . e_ij = v_i . e_ij + U*;
+ *  - dissipation limiter (Eq. 11): the pressures in the numerator are read as
+ *    densities, which makes the limiter dimensionless;
+ *  - Eq. 13 and Eqs. 26/33 are read as accelerations (force per unit mass);
+ *  - position shift (Eq. 14) carries a minus sign so that it regularises;
+ *  - unit normal (Eq. 21) is zero where the colour gradient vanishes;
+ *  - penalty tensor (Eq. 30): the outer product between A/|A| and A is read as
+ *    the matrix product (reading R1); reading R3 is available behind a flag;
+ *  - kernel values and gradients are frozen over one advection step (section
+ *    3.3); volumes V = m / rho always use the current density;
+ *  - density is re-initialised by a normalised summation at every advection
+ *    step (the paper evolves it by Eq. 6 only; flag ORC_NO_DENSITY_SUMMATION).
+ *
+ * Compiled with -ffp-contract=off so that the neighbour predicate and the cell
+ * keys are evaluated with one rounding per operation, as written.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+#define ORC_NO_PENALTY 1u
+#define ORC_NO_SHIFT 2u
+#define ORC_NO_DENSITY_SUMMATION 4u
+#define ORC_GBAR_SINGLE_FIELD 8u
+#define ORC_PENALTY_R3 16u
+#define ORC_NO_SURFACE 32u
+
+typedef struct {
+    int32_t dim;
+    int32_t reserved;
+    double box[3];
+    double dp;
+    double h_over_dp;
+    double rho0[2];
+    double eta[2];
+    double c0;
+    double gamma;
+    double xi; /* < 0: 1.3 n + 0.6 with density ratio 10^n (section 4.2) */
+    double alpha_shift;
+    double cfl_ad;
+    double cfl_ac;
+    double gravity[3];
+    uint32_t flags;
+    uint32_t reserved2;
+} orc_params;
+
+/* Per-system scalar record advanced by orc_step. */
+typedef struct {
+    double t;
+    double dt_ad;
+    double dt_ac;
+    double n_outer;
+    double n_sub;
+    double vmax[2];
+} orc_clock;
+
+/* ------------------------------------------------------------------------- */
+/* Kernel: 5th-order Wendland (Wendland C2), h = 1.3 dp, support 2h (section 5) */
+/* ------------------------------------------------------------------------- */
+
+static double wendland_alpha(int dim, double h)
+{
+    /* normalisation so that the kernel integrates to one over its support */
+    if (dim == 2) return 7.0 / (4.0 * M_PI * h * h);
+    return 21.0 / (16.0 * M_PI * h * h * h);
+}
+
+double orc_W(int dim, double h, double r)
+{
+    double q = r / h;
+    if (q >= 2.0) return 0.0;
+    double a = 1.0 - 0.5 * q;
+    return wendland_alpha(dim, h) * a * a * a * a * (1.0 + 2.0 * q);
+}
+
+/* dW/dr, the radial derivative used in grad_i W_ij = dW/dr e_ij (section 3.1) */
+double orc_dW(int dim, double h, double r)
+{
+    double q = r / h;
+    if (q >= 2.0) return 0.0;
+    double a = 1.0 - 0.5 * q;
+    return -5.0 * wendland_alpha(dim, h) * q * a * a * a / h;
+}
+
+/* Kernel sum of a perfect lattice of spacing dp, self included: the reference
+ * number density used to normalise the density summation. */
+double orc_sigma0(int dim, double h, double dp)
+{
+    int reach = (int)ceil(2.0 * h / dp) + 1;
+    double s = 0.0;
+    for (int a = -reach; a <= reach; ++a)
+        for (int b = -reach; b <= reach; ++b) {
+            if (dim == 2) {
+                s += orc_W(dim, h, dp * sqrt((double)(a * a + b * b)));
+            } else {
+                for (int c = -reach; c <= reach; ++c)
+                    s += orc_W(dim, h, dp * sqrt((double)(a * a + b * b + c * c)));
+            }
+        }
+    return s;
+}
+
+/* Penalty coefficient xi = 1.3 n + 0.6 for a density ratio of 10^n (section 4.2) */
+double orc_xi_auto(double rho_a, double rho_b)
+{
+    double n = fabs(log10(rho_a / rho_b));
+    return 1.3 * n + 0.6;
+}
+
+static double param_xi(const orc_params* P)
+{
+    return P->xi < 0.0 ? orc_xi_auto(P->rho0[0], P->rho0[1]) : P->xi;
+}
+
+static double param_h(const orc_params* P) { return P->h_over_dp * P->dp; }
+
+/* ------------------------------------------------------------------------- */
+/* Cell grid, periodic wrap, cell keys and the counting sort                  */
+/* ------------------------------------------------------------------------- */
+
+/* Cells of edge >= 2h: n_c = floor(L / 2h) per axis. Returns 0 if any axis has
+ * fewer than three cells (the stencil would then visit a cell twice). */
+int orc_grid(const orc_params* P, int32_t* ncell)
+{
+    double h = param_h(P);
+    int ok = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < P->dim) {
+            ncell[a] = (int32_t)floor(P->box[a] / (2.0 * h));
+            if (ncell[a] < 3) ok = 0;
+        } else {
+            ncell[a] = 1;
+        }
+    }
+    return ok;
+}
+
+/* One periodic correction per axis: x < 0 -> x + L, x >= L -> x - L. */
+void orc_wrap_positions(const orc_params* P, int64_t n, double* pos)
+{
+    int d = P->dim;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a) {
+            double L = P->box[a];
+            double x = pos[i * d + a];
+            if (x < 0.0) x = x + L;
+            if (x >= L) x = x - L;
+            pos[i * d + a] = x;
+        }
+}
+
+/* key = cx + nx (cy + ny cz), cx = floor(x * (nx / L)) clamped to [0, nx-1] */
+void orc_cell_keys(const orc_params* P, int64_t n, const double* pos, uint32_t* key)
+{
+    int32_t nc[3];
+    orc_grid(P, nc);
+    int d = P->dim;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+            double inv_cell = (double)nc[a] / P->box[a];
+            int64_t k = (int64_t)floor(pos[i * d + a] * inv_cell);
+            if (k < 0) k = 0;
+            if (k > nc[a] - 1) k = nc[a] - 1;
+            c[a] = k;
+        }
+        key[i] = (uint32_t)(c[0] + (int64_t)nc[0] * (c[1] + (int64_t)nc[1] * c[2]));
+    }
+}
+
+/* Stable counting sort of particle indices by cell key (ties keep index order).
+ * perm[k] is the index of the k-th particle in cell order; cell_start has
+ * n_cells + 1 entries. */
+void orc_bin(const orc_params* P, int64_t n, const uint32_t* key, int64_t* perm,
+             int64_t* cell_start)
+{
+    int32_t nc[3];
+    orc_grid(P, nc);
+    int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+    for (int64_t c = 0; c <= ncells; ++c) cell_start[c] = 0;
+    for (int64_t i = 0; i < n; ++i) cell_start[key[i] + 1] += 1;
+    for (int64_t c = 0; c < ncells; ++c) cell_start[c + 1] += cell_start[c];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ncells > 0 ? ncells : 1));
+    for (int64_t c = 0; c < ncells; ++c) fill[c] = cell_start[c];
+    for (int64_t i = 0; i < n; ++i) perm[fill[key[i]]++] = i;
+    free(fill);
+}
+
+/* Periodic minimum image of r_i - r_j along each axis, then |r_ij|^2 summed in
+ * axis order. Returns |r_ij|^2 and writes r_ij (zero-padded to 3). */
+static double min_image(const orc_params* P, const double* pos, int64_t i, int64_t j,
+                        double* rij)
+{
+    int d = P->dim;
+    double r2 = 0.0;
+    rij[0] = rij[1] = rij[2] = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double L = P->box[a];
+        double dx = pos[i * d + a] - pos[j * d + a];
+        double k = round(dx / L);
+        double x = dx - k * L;
+        rij[a] = x;
+        r2 = r2 + x * x;
+    }
+    return r2;
+}
+
+/* Neighbour predicate: j != i and |r_ij|^2 < (2h)^2 (strict). */
+static int is_neighbour(const orc_params* P, const double* pos, int64_t i, int64_t j,
+                        double* rij, double* r2out)
+{
+    if (i == j) return 0;
+    double h = param_h(P);
+    double cut2 = (2.0 * h) * (2.0 * h);
+    double r2 = min_image(P, pos, i, j, rij);
+    *r2out = r2;
+    return r2 < cut2;
+}
+
+/* Brute-force O(N^2) neighbour lists, CSR, each list ascending in j.
+ * Returns the total number of pairs, or -1 if cap is exceeded. */
+int64_t orc_neighbours_brute(const orc_params* P, int64_t n, const double* pos,
+                             int64_t* start, int64_t* idx, int64_t cap)
+{
+    int64_t total = 0;
+    double rij[3], r2;
+    start[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            if (is_neighbour(P, pos, i, j, rij, &r2)) {
+                if (total >= cap) return -1;
+                idx[total++] = j;
+            }
+        }
+        start[i + 1] = total;
+    }
+    return total;
+}
+
+/* ---- cell list used by the oracle's own neighbour search ---------------- */
+
+typedef struct {
+    int32_t nc[3];
+    int64_t ncells;
+    int64_t* cell_start;
+    int64_t* perm;
+} cells_t;
+
+static void cells_build(const orc_params* P, int64_t n, const double* pos, cells_t* C)
+{
+    orc_grid(P, C->nc);
+    C->ncells = (int64_t)C->nc[0] * C->nc[1] * C->nc[2];
+    uint32_t* key = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    C->cell_start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(C->ncells + 1));
+    C->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    orc_cell_keys(P, n, pos, key);
+    orc_bin(P, n, key, C->perm, C->cell_start);
+    free(key);
+}
+
+static void cells_free(cells_t* C)
+{
+    free(C->cell_start);
+    free(C->perm);
+}
+
+static int cmp_i64(const void* a, const void* b)
+{
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Candidates of particle i: all particles in the 3^d cells around its cell.
+ * Writes the neighbours (ascending j) into out, returns their number or -1 if
+ * cap is exceeded. Positions must already be wrapped into the box. */
+static int64_t cell_neighbours(const orc_params* P, const cells_t* C, const double* pos,
+                               int64_t i, int64_t* out, int64_t cap)
+{
+    int d = P->dim;
+    int64_t ci[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) {
+        double inv_cell = (double)C->nc[a] / P->box[a];
+        int64_t k = (int64_t)floor(pos[i * d + a] * inv_cell);
+        if (k < 0) k = 0;
+        if (k > C->nc[a] - 1) k = C->nc[a] - 1;
+        ci[a] = k;
+    }
+    int64_t cnt = 0;
+    double rij[3], r2;
+    int zr = (d == 3) ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int64_t cx = (ci[0] + dx + C->nc[0]) % C->nc[0];
+                int64_t cy = (ci[1] + dy + C->nc[1]) % C->nc[1];
+                int64_t cz = (ci[2] + dz + C->nc[2]) % C->nc[2];
+                int64_t c = cx + (int64_t)C->nc[0] * (cy + (int64_t)C->nc[1] * cz);
+                for (int64_t k = C->cell_start[c]; k < C->cell_start[c + 1]; ++k) {
+                    int64_t j = C->perm[k];
+                    if (is_neighbour(P, pos, i, j, rij, &r2)) {
+                        if (cnt >= cap) return -1;
+                        out[cnt++] = j;
+                    }
+                }
+            }
+    qsort(out, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    return cnt;
+}
+
+/* Same output as orc_neighbours_brute, found through the cell list. Positions
+ * must already be wrapped. */
+int64_t orc_neighbours_cells(const orc_params* P, int64_t n, const double* pos,
+                             int64_t* start, int64_t* idx, int64_t cap)
+{
+    cells_t C;
+    cells_build(P, n, pos, &C);
+    int64_t total = 0;
+    start[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = cell_neighbours(P, &C, pos, i, idx + total, cap - total);
+        if (c < 0) {
+            cells_free(&C);
+            return -1;
+        }
+        total += c;
+        start[i + 1] = total;
+    }
+    cells_free(&C);
+    return total;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Frozen pair geometry (section 3.3: neighbour list, kernel values and       */
+/* gradients are refreshed once per advection step)                           */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t n;       /* neighbours of this particle */
+    int64_t* j;      /* ascending */
+    double* rij;     /* 3 per pair: r_i - r_j */
+    double* r;       /* |r_ij| */
+    double* W;       /* W(r_ij) */
+    double* dW;      /* dW/dr(r_ij) */
+} nb_t;
+
+#define MAX_NB 4096
+
+static void nb_fill(const orc_params* P, const cells_t* C, const double* pos, int64_t i,
+                    nb_t* nb, int* overflow)
+{
+    int64_t tmp[MAX_NB];
+    int64_t c = cell_neighbours(P, C, pos, i, tmp, MAX_NB);
+    if (c < 0) {
+        *overflow = 1;
+        c = 0;
+    }
+    double h = param_h(P);
+    nb->n = c;
+    nb->j = (int64_t*)malloc(sizeof(int64_t) * (size_t)(c > 0 ? c : 1));
+    nb->rij = (double*)malloc(sizeof(double) * 3 * (size_t)(c > 0 ? c : 1));
+    nb->r = (double*)malloc(sizeof(double) * (size_t)(c > 0 ? c : 1));
+    nb->W = (double*)malloc(sizeof(double) * (size_t)(c > 0 ? c : 1));
+    nb->dW = (double*)malloc(sizeof(double) * (size_t)(c > 0 ? c : 1));
+    for (int64_t k = 0; k < c; ++k) {
+        double rij[3];
+        double r2 = min_image(P, pos, i, tmp[k], rij);
+        double r = sqrt(r2);
+        nb->j[k] = tmp[k];
+        nb->rij[3 * k + 0] = rij[0];
+        nb->rij[3 * k + 1] = rij[1];
+        nb->rij[3 * k + 2] = rij[2];
+        nb->r[k] = r;
+        nb->W[k] = orc_W(P->dim, h, r);
+        nb->dW[k] = orc_dW(P->dim, h, r);
+    }
+}
+
+static void nb_free(nb_t* nb)
+{
+    if (!nb->j) return;
+    free(nb->j);
+    free(nb->rij);
+    free(nb->r);
+    free(nb->W);
+    free(nb->dW);
+    memset(nb, 0, sizeof(*nb));
+}
+
+/* e_ij = r_ij / r_ij */
+static void unit(const nb_t* nb, int64_t k, double* e)
+{
+    for (int a = 0; a < 3; ++a) e[a] = nb->rij[3 * k + a] / nb->r[k];
+}
+
+/* ------------------------------------------------------------------------- */
+/* One function per equation                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Density summation rho_i = rho0_i sigma_i / sigma0 with sigma_i = W(0) + sum_j W_ij
+ * (number-density form, valid across the interface). Returns sigma_i. */
+static double kernel_sum(const orc_params* P, const nb_t* nb)
+{
+    double s = orc_W(P->dim, param_h(P), 0.0);
+    for (int64_t k = 0; k < nb->n; ++k) s += nb->W[k];
+    return s;
+}
+
+/* Eq. 13: viscous acceleration
+ *   a^v_i = (2/rho_i) sum_j [2 eta_i eta_j/(eta_i+eta_j)] (v_i - v_j)/r_ij dW_ij V_j */
+static void viscous_acc(const orc_params* P, const nb_t* nb, int64_t i, const double* vel,
+                        const double* rho, const double* mass, const int32_t* phase,
+                        double* av)
+{
+    int d = P->dim;
+    double eta_i = P->eta[phase[i]];
+    double s[3] = {0, 0, 0};
+    for (int64_t k = 0; k < nb->n; ++k) {
+        int64_t j = nb->j[k];
+        double eta_j = P->eta[phase[j]];
+        double eta_bar = (eta_i + eta_j) > 0.0 ? 2.0 * eta_i * eta_j / (eta_i + eta_j) : 0.0;
+        double Vj = mass[j] / rho[j];
+        double f = eta_bar * nb->dW[k] / nb->r[k] * Vj;
+        for (int a = 0; a < d; ++a) s[a] += f * (vel[i * d + a] - vel[j * d + a]);
+    }
+    for (int a = 0; a < 3; ++a) av[a] = a < d ? 2.0 / rho[i] * s[a] : 0.0;
+}
+
+/* d x d inverse by the adjugate; identity if the matrix is singular. */
+static void invert(int d, const double* M, double* out)
+{
+    if (d == 2) {
+        double det = M[0] * M[3] - M[1] * M[2];
+        if (det == 0.0 || !isfinite(det)) {
+            out[0] = 1; out[1] = 0; out[2] = 0; out[3] = 1;
+            return;
+        }
+        out[0] = M[3] / det;
+        out[1] = -M[1] / det;
+        out[2] = -M[2] / det;
+        out[3] = M[0] / det;
+        return;
+    }
+    double c00 = M[4] * M[8] - M[5] * M[7];
+    double c01 = M[5] * M[6] - M[3] * M[8];
+    double c02 = M[3] * M[7] - M[4] * M[6];
+    double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    if (det == 0.0 || !isfinite(det)) {
+        for (int k = 0; k < 9; ++k) out[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    out[0] = c00 / det;
+    out[3] = c01 / det;
+    out[6] = c02 / det;
+    out[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+    out[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+    out[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+    out[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+    out[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+    out[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+}
+
+/* Eq. 15: B_i = -( sum_j r_ij (x) grad_i W_ij V_j )^{-1}; stored row-major d x d. */
+static void correction_matrix(const orc_params* P, const nb_t* nb, const double* rho,
+                              const double* mass, double* B)
+{
+    int d = P->dim;
+    double M[9] = {0};
+    for (int64_t k = 0; k < nb->n; ++k) {
+        int64_t j = nb->j[k];
+        double Vj = mass[j] / rho[j];
+        double e[3];
+        unit(nb, k, e);
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                M[a * d + b] += nb->rij[3 * k + a] * nb->dW[k] * e[b] * Vj;
+    }
+    double inv[9];
+    invert(d, M, inv);
+    for (int k = 0; k < d * d; ++k) B[k] = -inv[k];
+}
+
+/* Eq. 14 (with the regularising sign): dr_i = -alpha h^2 sum_j (B_i + B_j) grad_i W_ij V_j */
+static void position_shift(const orc_params* P, const nb_t* nb, int64_t i, const double* B,
+                           const double* rho, const double* mass, double* dr)
+{
+    int d = P->dim;
+    double h = param_h(P);
+    double s[3] = {0, 0, 0};
+    for (int64_t k = 0; k < nb->n; ++k) {
+        int64_t j = nb->j[k];
+        double Vj = mass[j] / rho[j];
+        double e[3];
+        unit(nb, k, e);
+        for (int a = 0; a < d; ++a) {
+            double row = 0.0;
+            for (int b = 0; b < d; ++b)
+                row += (B[i * d * d + a * d + b] + B[j * d * d + a * d + b]) * e[b];
+            s[a] += row * nb->dW[k] * Vj;
+        }
+    }
+    for (int a = 0; a < 3; ++a) dr[a] = a < d ? -P->alpha_shift * h * h * s[a] : 0.0;
+}
+
+/* Eq. 23: phi_i = rho0_i / (rho0_i + rho0_j) */
+static double phi_of(const orc_params* P, int pi, int pj)
+{
+    return P->rho0[pi] / (P->rho0[pi] + P->rho0[pj]);
+}
+
+/* Eq. 22: grad C_i = sum_j 2 phi_i C_ij grad_i W_ij V_j, C_ij = 1 across phases,
+ * 0 within a phase (the colour is relative to the target particle). */
+static void colour_gradient(const orc_params* P, const nb_t* nb, int64_t i, const double* rho,
+                            const double* mass, const int32_t* phase, double* g)
+{
+    int d = P->dim;
+    g[0] = g[1] = g[2] = 0.0;
+    for (int64_t k = 0; k < nb->n; ++k) {
+        int64_t j = nb->j[k];
+        double Cij = (phase[j] != phase[i]) ? 1.0 : 0.0;
+        double phi_i = phi_of(P, phase[i], phase[j]);
+        double Vj = mass[j] / rho[j];
+        double e[3];
+        unit(nb, k, e);
+        for (int a = 0; a < d; ++a) g[a] += 2.0 * phi_i * Cij * nb->dW[k] * e[a] * Vj;
+    }
+}
+
+/* Eq. 21 and Eq. 24: unit normal (zero when |grad C| = 0), N = n n^T, T = I - N,
+ * surface stress Pi = gamma T |grad C|.  All d x d row-major. */
+static void stress_of(const orc_params* P, const double* g, double* N, double* T, double* Pi)
+{
+    int d = P->dim;
+    double gn = 0.0;
+    for (int a = 0; a < d; ++a) gn += g[a] * g[a];
+    gn = sqrt(gn);
+    double n[3] = {0, 0, 0};
+    if (gn > 0.0)
+        for (int a = 0; a < d; ++a) n[a] = g[a] / gn;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            N[a * d + b] = n[a] * n[b];
+            T[a * d + b] = (a == b ? 1.0 : 0.0) - N[a * d + b];
+            Pi[a * d + b] = P->gamma * T[a * d + b] * gn;
+        }
+}
+
+static void matvec(int d, const double* M, const double* x, double* y)
+{
+    for (int a = 0; a < d; ++a) {
+        y[a] = 0.0;
+        for (int b = 0; b < d; ++b) y[a] += M[a * d + b] * x[b];
+    }
+}
+
+/* Eqs. 7-12 (pressure) and Eqs. 24, 27, 30, 33 (surface stress with projected
+ * penalty). Writes the pressure acceleration ap and the surface acceleration
+ * as (stress divergence plus penalty). gradC holds grad C for every particle
+ * that appears in this neighbourhood. */
+static void momentum_rates(const orc_params* P, const nb_t* nb, int64_t i, const double* vel,
+                           const double* rho, const double* p, const double* mass,
+                           const int32_t* phase, const double* gradC, double* ap, double* as)
+{
+    int d = P->dim;
+    double xi = param_xi(P);
+    double gamma = P->gamma;
+    int no_pen = (P->flags & ORC_NO_PENALTY) != 0;
+    int no_surf = (P->flags & ORC_NO_SURFACE) != 0;
+    double sp[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+    double Ni[9], Ti[9], Pii[9];
+    stress_of(P, gradC + 3 * i, Ni, Ti, Pii);
+    for (int64_t k = 0; k < nb->n; ++k) {
+        int64_t j = nb->j[k];
+        double Vj = mass[j] / rho[j];
+        double e[3];
+        unit(nb, k, e);
+        double dW = nb->dW[k];
+        double r = nb->r[k];
+        /* Eq. 10: left and right states along e_ij */
+        double rhoL = rho[i], rhoR = rho[j];
+        double UL = 0.0, UR = 0.0;
+        for (int a = 0; a < d; ++a) {
+            UL -= vel[i * d + a] * e[a];
+            UR -= vel[j * d + a] * e[a];
+        }
+        double cL = P->c0, cR = P->c0;
+        double ZL = rhoL * cL, ZR = rhoR * cR;
+        /* Eq. 11, numerator pressures read as densities */
+        double lim = (rhoL + rhoR) * (UL - UR) / (ZL + ZR);
+        double beta = fmin(3.0 * fmax(lim, 0.0), 1.0);
+        /* Eq. 12: density-weighted pressure average */
+        double pbar = (rho[i] * p[j] + rho[j] * p[i]) / (rho[i] + rho[j]);
+        /* Eq. 8: star pressure */
+        double Pstar = pbar + beta * ZL * ZR * (UL - UR) / (ZL + ZR);
+        /* Eq. 7 */
+        for (int a = 0; a < d; ++a) sp[a] += Pstar * dW * e[a] * Vj;
+
+        if (no_surf) continue;
+        /* Eqs. 33 with Eq. 24 */
+        int same = phase[i] == phase[j];
+        double Nj[9], Tj[9], Pij[9];
+        stress_of(P, gradC + 3 * j, Nj, Tj, Pij);
+        double phi_i = phi_of(P, phase[i], phase[j]);
+        double phi_j = phi_of(P, phase[j], phase[i]);
+        double S[9];
+        for (int q = 0; q < d * d; ++q)
+            S[q] = same ? (Pii[q] + Pij[q]) : (2.0 * phi_j * Pii[q] + 2.0 * phi_i * Pij[q]);
+        double gW[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) gW[a] = dW * e[a];
+        double Sg[3];
+        matvec(d, S, gW, Sg);
+        for (int a = 0; a < d; ++a) ss[a] += Sg[a] * Vj;
+
+        if (no_pen) continue;
+        /* Eq. 27 and Eq. 30 (reading R1): Chat_ij grad W = dW [C_ij e - (gbar . r_ij) gbar/|gbar|] */
+        double Cij = same ? 0.0 : 1.0;
+        double gbar[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+            double gj = gradC[3 * j + a];
+            if ((P->flags & ORC_GBAR_SINGLE_FIELD) && !same) gj = -gj;
+            gbar[a] = 0.5 * (gradC[3 * i + a] + gj);
+        }
+        double gnorm = 0.0, gdotr = 0.0;
+        for (int a = 0; a < d; ++a) {
+            gnorm += gbar[a] * gbar[a];
+            gdotr += gbar[a] * nb->rij[3 * k + a];
+        }
+        gnorm = sqrt(gnorm);
+        double q[3] = {0, 0, 0};
+        if (P->flags & ORC_PENALTY_R3) {
+            /* reading R3: dW [C_ij - (gbar . r)^2 / (|gbar| r)] e */
+            double s = Cij - (gnorm > 0.0 ? gdotr * gdotr / (gnorm * r) : 0.0);
+            for (int a = 0; a < d; ++a) q[a] = dW * s * e[a];
+        } else {
+            for (int a = 0; a < d; ++a)
+                q[a] = dW * (Cij * e[a] - (gnorm > 0.0 ? gdotr * gbar[a] / gnorm : 0.0));
+        }
+        /* projections: Tbar within a phase, Nbar across phases (Eq. 33) */
+        double Mbar[9];
+        for (int t = 0; t < d * d; ++t)
+            Mbar[t] = same ? 0.5 * (Ti[t] + Tj[t]) : 0.5 * (Ni[t] + Nj[t]);
+        double Mq[3];
+        matvec(d, Mbar, q, Mq);
+        double coef = same ? xi * gamma / r : -4.0 * phi_i * phi_j * xi * gamma / r;
+        for (int a = 0; a < d; ++a) ss[a] += coef * Mq[a] * Vj;
+    }
+    for (int a = 0; a < 3; ++a) {
+        ap[a] = a < d ? -2.0 / rho[i] * sp[a] : 0.0;
+        as[a] = a < d ? 1.0 / rho[i] * ss[a] : 0.0;
+    }
+}
+
+/* Eq. 6 with Eq. 9 and the i->j Riemann axis:
+ *   drho_i/dt = 2 rho_i sum_j (v_i . e_ij + U*) dW_ij V_j */
+static double continuity_rate(const orc_params* P, const nb_t* nb, int64_t i, const double* vel,
+                              const double* rho, const double* p, const double* mass,
+                              const int32_t* phase)
+{
+    (void)phase;
+    int d = P->dim;
+    double s = 0.0;
+    for (int64_t k = 0; k < nb->n; ++k) {
+        int64_t j = nb->j[k];
+        double Vj = mass[j] / rho[j];
+        double e[3];
+        unit(nb, k, e);
+        double UL = 0.0, UR = 0.0, vie = 0.0;
+        for (int a = 0; a < d; ++a) {
+            UL -= vel[i * d + a] * e[a];
+            UR -= vel[j * d + a] * e[a];
+            vie += vel[i * d + a] * e[a];
+        }
+        double ZL = rho[i] * P->c0, ZR = rho[j] * P->c0;
+        double Ustar = (ZL * UL + ZR * UR + p[i] - p[j]) / (ZL + ZR);
+        s += (vie + Ustar) * nb->dW[k] * Vj;
+    }
+    return 2.0 * rho[i] * s;
+}
+
+/* Eq. 3 */
+static double eos(const orc_params* P, double rho, int ph)
+{
+    return P->c0 * P->c0 * (rho - P->rho0[ph]);
+}
+
+/* Eqs. 16-18; |v|_max = 0 gives h / 0 = infinity. */
+double orc_dt_advection(const orc_params* P, const double* vmax)
+{
+    double h = param_h(P);
+    double dt = INFINITY;
+    for (int f = 0; f < 2; ++f) {
+        double a = vmax[f] > 0.0 ? h / vmax[f] : INFINITY;
+        double b = P->eta[f] > 0.0 ? P->rho0[f] * h * h / P->eta[f] : INFINITY;
+        dt = fmin(dt, P->cfl_ad * fmin(a, b));
+    }
+    return dt;
+}
+
+double orc_dt_acoustic(const orc_params* P, const double* vmax)
+{
+    double h = param_h(P);
+    double dt = INFINITY;
+    for (int f = 0; f < 2; ++f) {
+        double a = h / (P->c0 + vmax[f]);
+        double b = P->gamma > 0.0 ? sqrt(P->rho0[f] * h * h * h / (2.0 * M_PI * P->gamma))
+                                  : INFINITY;
+        dt = fmin(dt, P->cfl_ac * fmin(a, b));
+    }
+    return dt;
+}
+
+static void phase_vmax(const orc_params* P, int64_t n, const double* vel, const int32_t* phase,
+                       double* vmax)
+{
+    int d = P->dim;
+    vmax[0] = vmax[1] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int a = 0; a < d; ++a) s += vel[i * d + a] * vel[i * d + a];
+        s = sqrt(s);
+        if (s > vmax[phase[i]]) vmax[phase[i]] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Single evaluation of all rates at a given state                            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double* gradC;   /* 3 per target */
+    double* acc;     /* 3: total acceleration a^p + a^s + a^v + g */
+    double* acc_p;   /* 3 */
+    double* acc_s;   /* 3: stress divergence plus penalty */
+    double* acc_v;   /* 3 */
+    double* drho;    /* 1 */
+    double* B;       /* 9: row-major d x d */
+    double* dr;      /* 3: position shift (not applied) */
+    double* sigma;   /* 1: W(0) + sum_j W_ij */
+    int64_t* nnb;    /* 1: neighbour count */
+} orc_rates;
+
+/* Evaluates, at the state given (density as given, positions wrapped by the
+ * caller), the neighbour geometry, the kernel sum, the viscous acceleration,
+ * B and the position shift, the colour gradient, the full acceleration and the
+ * continuity rate, for each target particle. targets == NULL means all.
+ * Returns 0, or -1 on neighbour overflow. */
+int orc_eval_rates(const orc_params* P, int64_t n, const double* pos, const double* vel,
+                   const double* rho, const double* mass, const int32_t* phase,
+                   int64_t ntargets, const int64_t* targets, orc_rates* out)
+{
+    int d = P->dim;
+    cells_t C;
+    cells_build(P, n, pos, &C);
+    /* which particles need a neighbourhood: targets and their neighbours */
+    char* need = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    nb_t* nb = (nb_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(nb_t));
+    int64_t nt = targets ? ntargets : n;
+    int overflow = 0;
+    for (int64_t t = 0; t < nt; ++t) need[targets ? targets[t] : t] = 1;
+    if (targets) {
+        for (int64_t t = 0; t < nt; ++t) {
+            int64_t i = targets[t];
+            if (!nb[i].j) nb_fill(P, &C, pos, i, &nb[i], &overflow);
+            for (int64_t k = 0; k < nb[i].n; ++k) need[nb[i].j[k]] = 1;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int ov = 0;
+        if (need[i] && !nb[i].j) nb_fill(P, &C, pos, i, &nb[i], &ov);
+        if (ov) overflow = 1;
+    }
+    double* p = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) p[i] = eos(P, rho[i], phase[i]);
+    double* gradC = (double*)calloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
+    double* B = (double*)calloc(9 * (size_t)(n > 0 ? n : 1), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!need[i]) continue;
+        colour_gradient(P, &nb[i], i, rho, mass, phase, gradC + 3 * i);
+        correction_matrix(P, &nb[i], rho, mass, B + (size_t)d * d * i);
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        double ap[3], as[3], av[3], dr[3];
+        momentum_rates(P, &nb[i], i, vel, rho, p, mass, phase, gradC, ap, as);
+        viscous_acc(P, &nb[i], i, vel, rho, mass, phase, av);
+        position_shift(P, &nb[i], i, B, rho, mass, dr);
+        for (int a = 0; a < 3; ++a) {
+            double g = a < d ? P->gravity[a] : 0.0;
+            if (out->gradC) out->gradC[3 * t + a] = gradC[3 * i + a];
+            if (out->acc) out->acc[3 * t + a] = ap[a] + as[a] + av[a] + g;
+            if (out->acc_p) out->acc_p[3 * t + a] = ap[a];
+            if (out->acc_s) out->acc_s[3 * t + a] = as[a];
+            if (out->acc_v) out->acc_v[3 * t + a] = av[a];
+            if (out->dr) out->dr[3 * t + a] = dr[a];
+        }
+        if (out->B)
+            for (int q = 0; q < 9; ++q) out->B[9 * t + q] = q < d * d ? B[(size_t)d * d * i + q] : 0.0;
+        if (out->drho) out->drho[t] = continuity_rate(P, &nb[i], i, vel, rho, p, mass, phase);
+        if (out->sigma) out->sigma[t] = kernel_sum(P, &nb[i]);
+        if (out->nnb) out->nnb[t] = nb[i].n;
+    }
+    for (int64_t i = 0; i < n; ++i) nb_free(&nb[i]);
+    free(nb);
+    free(need);
+    free(p);
+    free(gradC);
+    free(B);
+    cells_free(&C);
+    return overflow ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dual-criteria time integration (section 3.3)                               */
+/* ------------------------------------------------------------------------- */
+
+/* Advances n_outer advection steps. One advection step: wrap and rebuild the
+ * frozen geometry, density summation, advection time step, viscous
+ * acceleration, correction matrix and position shift; then acoustic substeps
+ * (half density and position update, colour gradient and stress, momentum
+ * rates, kick, half position update, continuity with the new velocity, half
+ * density update) until the advection step is covered exactly.
+ * Returns 0, -1 on neighbour overflow, -2 on a non-finite state. */
+int orc_step(const orc_params* P, int64_t n, double* pos, double* vel, double* rho, double* drho,
+             const double* mass, const int32_t* phase, orc_clock* clk, int64_t n_outer)
+{
+    int d = P->dim;
+    double h = param_h(P);
+    double sigma0 = orc_sigma0(d, h, P->dp);
+    double* p = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gradC = (double*)calloc(3 * (size_t)n, sizeof(double));
+    double* B = (double*)calloc(9 * (size_t)n, sizeof(double));
+    double* av = (double*)calloc(3 * (size_t)n, sizeof(double));
+    double* acc = (double*)calloc(3 * (size_t)n, sizeof(double));
+    double* dr = (double*)calloc(3 * (size_t)n, sizeof(double));
+    nb_t* nb = (nb_t*)calloc((size_t)n, sizeof(nb_t));
+    int status = 0;
+    for (int64_t step = 0; step < n_outer && status == 0; ++step) {
+        /* frozen geometry for this advection step */
+        orc_wrap_positions(P, n, pos);
+        cells_t C;
+        cells_build(P, n, pos, &C);
+        int overflow = 0;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int ov = 0;
+            nb_free(&nb[i]);
+            nb_fill(P, &C, pos, i, &nb[i], &ov);
+            if (ov) overflow = 1;
+        }
+        cells_free(&C);
+        if (overflow) {
+            status = -1;
+            break;
+        }
+        /* density summation */
+        if (!(P->flags & ORC_NO_DENSITY_SUMMATION)) {
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i)
+                rho[i] = P->rho0[phase[i]] * kernel_sum(P, &nb[i]) / sigma0;
+        }
+        /* Eq. 16, Eq. 18 */
+        double vmax[2];
+        phase_vmax(P, n, vel, phase, vmax);
+        double dt_ad = orc_dt_advection(P, vmax);
+        /* no motion and no viscosity leave Eq. 16 unbounded: one acoustic step
+         * then spans the advection step */
+        if (!isfinite(dt_ad)) dt_ad = orc_dt_acoustic(P, vmax);
+        /* Eq. 13, held over the advection step */
+#pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i)
+            viscous_acc(P, &nb[i], i, vel, rho, mass, phase, av + 3 * i);
+        /* Eq. 15 then Eq. 14 */
+        if (!(P->flags & ORC_NO_SHIFT)) {
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i)
+                correction_matrix(P, &nb[i], rho, mass, B + (size_t)d * d * i);
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i) position_shift(P, &nb[i], i, B, rho, mass, dr + 3 * i);
+            for (int64_t i = 0; i < n; ++i)
+                for (int a = 0; a < d; ++a) pos[i * d + a] += dr[3 * i + a];
+        }
+        /* acoustic substeps */
+        double tau = 0.0;
+        while (tau < dt_ad * (1.0 - 1e-12)) {
+            phase_vmax(P, n, vel, phase, vmax);
+            double dt = fmin(orc_dt_acoustic(P, vmax), dt_ad - tau);
+            clk->dt_ac = dt;
+            for (int64_t i = 0; i < n; ++i) {
+                rho[i] += 0.5 * dt * drho[i];
+                p[i] = eos(P, rho[i], phase[i]);
+                for (int a = 0; a < d; ++a) pos[i * d + a] += 0.5 * dt * vel[i * d + a];
+            }
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i) colour_gradient(P, &nb[i], i, rho, mass, phase, gradC + 3 * i);
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i) {
+                double ap[3], as[3];
+                momentum_rates(P, &nb[i], i, vel, rho, p, mass, phase, gradC, ap, as);
+                for (int a = 0; a < d; ++a)
+                    acc[3 * i + a] = ap[a] + as[a] + av[3 * i + a] + P->gravity[a];
+            }
+            for (int64_t i = 0; i < n; ++i)
+                for (int a = 0; a < d; ++a) {
+                    vel[i * d + a] += dt * acc[3 * i + a];
+                    pos[i * d + a] += 0.5 * dt * vel[i * d + a];
+                }
+#pragma omp parallel for
+            for (int64_t i = 0; i < n; ++i)
+                drho[i] = continuity_rate(P, &nb[i], i, vel, rho, p, mass, phase);
+            int bad = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                rho[i] += 0.5 * dt * drho[i];
+                if (!(rho[i] > 0.0) || !isfinite(rho[i])) bad = 1;
+                for (int a = 0; a < d; ++a)
+                    if (!isfinite(vel[i * d + a])) bad = 1;
+            }
+            tau += dt;
+            clk->t += dt;
+            clk->n_sub += 1.0;
+            if (bad) {
+                status = -2;
+                break;
+            }
+        }
+        clk->dt_ad = dt_ad;
+        clk->n_outer += 1.0;
+        phase_vmax(P, n, vel, phase, clk->vmax);
+    }
+    for (int64_t i = 0; i < n; ++i) nb_free(&nb[i]);
+    free(nb);
+    free(p);
+    free(gradC);
+    free(B);
+    free(av);
+    free(acc);
+    free(dr);
+    return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Observables                                                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double momentum[3];
+    double kinetic;
+    double mass[2];
+    double volume[2];
+    double vmax[2];
+    double centroid[3];     /* phase 0, mass weighted, raw coordinates */
+    double moment2[9];      /* phase 0, mass weighted, about the centroid */
+    double r_eq;            /* from the phase 0 volume */
+    double p_in, p_out;     /* mean pressure deep inside / outside phase 0 */
+    double n_in, n_out;
+} orc_obs;
+
+void orc_observables(const orc_params* P, int64_t n, const double* pos, const double* vel,
+                     const double* rho, const double* mass, const int32_t* phase, orc_obs* o)
+{
+    int d = P->dim;
+    double h = param_h(P);
+    memset(o, 0, sizeof(*o));
+    for (int64_t i = 0; i < n; ++i) {
+        double v2 = 0.0;
+        for (int a = 0; a < d; ++a) {
+            o->momentum[a] += mass[i] * vel[i * d + a];
+            v2 += vel[i * d + a] * vel[i * d + a];
+        }
+        o->kinetic += 0.5 * mass[i] * v2;
+        o->mass[phase[i]] += mass[i];
+        o->volume[phase[i]] += mass[i] / rho[i];
+        if (sqrt(v2) > o->vmax[phase[i]]) o->vmax[phase[i]] = sqrt(v2);
+        if (phase[i] == 0)
+            for (int a = 0; a < d; ++a) o->centroid[a] += mass[i] * pos[i * d + a];
+    }
+    if (o->mass[0] > 0.0)
+        for (int a = 0; a < d; ++a) o->centroid[a] /= o->mass[0];
+    for (int64_t i = 0; i < n; ++i) {
+        if (phase[i] != 0) continue;
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                o->moment2[a * 3 + b] += mass[i] * (pos[i * d + a] - o->centroid[a]) *
+                                         (pos[i * d + b] - o->centroid[b]);
+    }
+    if (d == 2)
+        o->r_eq = sqrt(o->volume[0] / M_PI);
+    else
+        o->r_eq = cbrt(3.0 * o->volume[0] / (4.0 * M_PI));
+    for (int64_t i = 0; i < n; ++i) {
+        double r2 = 0.0;
+        for (int a = 0; a < d; ++a) {
+            double x = pos[i * d + a] - o->centroid[a];
+            r2 += x * x;
+        }
+        double r = sqrt(r2);
+        double p = eos(P, rho[i], phase[i]);
+        if (phase[i] == 0 && r < o->r_eq - 3.0 * h) {
+            o->p_in += p;
+            o->n_in += 1.0;
+        }
+        if (phase[i] == 1 && r > o->r_eq + 3.0 * h) {
+            o->p_out += p;
+            o->n_out += 1.0;
+        }
+    }
+    if (o->n_in > 0) o->p_in /= o->n_in;
+    if (o->n_out > 0) o->p_out /= o->n_out;
+}

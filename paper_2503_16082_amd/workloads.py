@@ -1,0 +1,189 @@
+"""Seeded synthetic droplet workloads (inputs only).
+
+This module builds initial particle sets and parameter dictionaries for the
+workloads the method is exercised on: a lattice of spacing dp in a periodic box,
+seeded uniform jitter of 0.05 dp, a phase assigned from the unjittered lattice
+point, and zero or prescribed velocity.  It holds none of the method's
+arithmetic: it draws random numbers and lays out lattices, nothing more, so it
+can feed both the HIP library and the CPU oracle with identical arrays.
+
+Phase 0 is fluid k (the droplet or pool), phase 1 is fluid l.  The sound speed
+follows the paper's rule c0 = 10 U (section 2), with U the larger of the initial
+speed and the capillary velocity sqrt((d-1) gamma / (rho_k R)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+H_OVER_DP = 1.3
+
+
+def lattice(dim, counts, dp):
+    """Cell-centred lattice ((i + 1/2) dp, ...), x fastest."""
+    axes = [(np.arange(c) + 0.5) * dp for c in counts]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")
+    pts = np.stack([g.ravel() for g in grids[::-1]], axis=1)
+    return pts.astype(np.float64)
+
+
+def jitter(rng, pts, dp, amp=0.05):
+    return pts + rng.uniform(-amp * dp, amp * dp, size=pts.shape)
+
+
+def base_params(dim, box, dp, rho0, eta, gamma, c0, **kw):
+    p = {
+        "dim": dim,
+        "box": [float(b) for b in box],
+        "dp": float(dp),
+        "h_over_dp": H_OVER_DP,
+        "rho0": [float(rho0[0]), float(rho0[1])],
+        "eta": [float(eta[0]), float(eta[1])],
+        "gamma": float(gamma),
+        "c0": float(c0),
+        "xi": -1.0,
+        "alpha_shift": 0.2,
+        "cfl_ad": 0.1,
+        "cfl_ac": 0.6,
+        "gravity": [0.0, 0.0, 0.0],
+    }
+    p.update(kw)
+    return p
+
+
+def capillary_c0(dim, gamma, rho_k, R, umax=0.0):
+    return 10.0 * max(umax, math.sqrt((dim - 1) * gamma / (rho_k * R)))
+
+
+def static_droplet_2d(n_side=50, R=0.2, seed=0, rho=(1000.0, 1.0), eta=(0.1, 1e-3),
+                      gamma=1.0, amp=0.05):
+    """Disc of radius R centred in the periodic unit square (2,500 particles at
+    n_side = 50)."""
+    dp = 1.0 / n_side
+    pts0 = lattice(2, (n_side, n_side), dp)
+    phase = np.where(np.linalg.norm(pts0 - 0.5, axis=1) < R, 0, 1).astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    vel = np.zeros_like(pos)
+    p = base_params(2, (1.0, 1.0), dp, rho, eta, gamma, capillary_c0(2, gamma, rho[0], R))
+    return {"name": "static_droplet_2d", "params": p, "pos": pos, "vel": vel, "phase": phase,
+            "R": R}
+
+
+def square_droplet_2d(n_side=200, side=0.4, seed=0, rho=(1000.0, 1.0), eta=(0.1, 1e-3),
+                      gamma=1.0, amp=0.05):
+    """Square of the given side centred in the periodic unit square (40,000
+    particles at n_side = 200)."""
+    dp = 1.0 / n_side
+    pts0 = lattice(2, (n_side, n_side), dp)
+    inside = np.max(np.abs(pts0 - 0.5), axis=1) < 0.5 * side
+    phase = np.where(inside, 0, 1).astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    vel = np.zeros_like(pos)
+    R = side / math.sqrt(math.pi)
+    p = base_params(2, (1.0, 1.0), dp, rho, eta, gamma, capillary_c0(2, gamma, rho[0], R))
+    return {"name": "square_droplet_2d", "params": p, "pos": pos, "vel": vel, "phase": phase,
+            "R": R}
+
+
+def static_droplet_3d(n_side=64, R=0.25, seed=0, rho=(1000.0, 1.0), eta=(0.1, 1e-3),
+                      gamma=1.0, amp=0.05):
+    """Sphere of radius R centred in the periodic unit cube (262,144 particles at
+    n_side = 64)."""
+    dp = 1.0 / n_side
+    pts0 = lattice(3, (n_side, n_side, n_side), dp)
+    phase = np.where(np.linalg.norm(pts0 - 0.5, axis=1) < R, 0, 1).astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    vel = np.zeros_like(pos)
+    p = base_params(3, (1.0, 1.0, 1.0), dp, rho, eta, gamma,
+                    capillary_c0(3, gamma, rho[0], R))
+    return {"name": "static_droplet_3d", "params": p, "pos": pos, "vel": vel, "phase": phase,
+            "R": R, "n_side": n_side}
+
+
+def subset_indices_3d(n_side, lo, hi):
+    """Indices of the lattice block lo <= (ix, iy, iz) < hi (x fastest)."""
+    ix = np.arange(lo[0], hi[0])
+    iy = np.arange(lo[1], hi[1])
+    iz = np.arange(lo[2], hi[2])
+    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+    return (X + n_side * (Y + n_side * Z)).ravel().astype(np.int64)
+
+
+def oscillating_ellipse_2d(n_particles, aspect, ratio, gamma, seed, R=0.2, rho_k=1000.0,
+                           eta_k=0.1, amp=0.05):
+    """One served job: an ellipse of semi-axes R sqrt(AR), R / sqrt(AR) in the
+    periodic unit square, round(sqrt(N)) particles per side."""
+    n_side = max(3, int(round(math.sqrt(n_particles))))
+    dp = 1.0 / n_side
+    pts0 = lattice(2, (n_side, n_side), dp)
+    a = R * math.sqrt(aspect)
+    b = R / math.sqrt(aspect)
+    x = (pts0[:, 0] - 0.5) / a
+    y = (pts0[:, 1] - 0.5) / b
+    phase = np.where(x * x + y * y < 1.0, 0, 1).astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    vel = np.zeros_like(pos)
+    rho = (rho_k, rho_k / ratio)
+    eta = (eta_k, eta_k / min(ratio, 100.0))
+    p = base_params(2, (1.0, 1.0), dp, rho, eta, gamma, capillary_c0(2, gamma, rho_k, R))
+    return {"name": "oscillating_ellipse_2d", "params": p, "pos": pos, "vel": vel,
+            "phase": phase, "R": R}
+
+
+def served_mix(n_jobs=256, seed=0, n_min=2000, n_max=200000):
+    """Job descriptions of the served mix: log-uniform particle counts,
+    aspect ratio U(1.1, 1.5), density ratio from {10, 100, 1000}, gamma U(0.5, 2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for k in range(n_jobs):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        jobs.append({
+            "job": k,
+            "n": n,
+            "aspect": float(rng.uniform(1.1, 1.5)),
+            "ratio": float(rng.choice([10.0, 100.0, 1000.0])),
+            "gamma": float(rng.uniform(0.5, 2.0)),
+            "seed": k,
+        })
+    return jobs
+
+
+def droplet_impact_3d(n_per_unit=32, seed=0, U0=50.0, amp=0.05, box=(8.0, 8.0, 4.0),
+                      pool_depth=2.0, D=1.0):
+    """Droplet of diameter D with velocity (0, 0, -U0) just above a pool of depth
+    pool_depth in a fully periodic air-filled box (8,388,608 particles at 32
+    per unit length)."""
+    dp = 1.0 / n_per_unit
+    counts = tuple(int(round(b / dp)) for b in box)
+    pts0 = lattice(3, counts, dp)
+    centre = np.array([box[0] / 2, box[1] / 2, pool_depth + D / 2 + 2 * dp])
+    in_drop = np.linalg.norm(pts0 - centre, axis=1) < D / 2
+    in_pool = pts0[:, 2] < pool_depth
+    phase = np.where(in_drop | in_pool, 0, 1).astype(np.int32)
+    del pts0
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = lattice(3, counts, dp)
+    pos += rng.uniform(-amp * dp, amp * dp, size=pos.shape)
+    vel = np.zeros_like(pos)
+    vel[in_drop, 2] = -U0
+    p = base_params(3, box, dp, (1.0, 1e-3), (5e-3, 5e-5), 0.1, 10.0 * U0)
+    return {"name": "droplet_impact_3d", "params": p, "pos": pos, "vel": vel, "phase": phase,
+            "R": D / 2}
+
+
+def acoustic_wave_2d(n_side=24, amp_v=1e-3, seed=0):
+    """Single-phase periodic box with a sinusoidal velocity perturbation, used
+    to check that the Riemann dissipation damps acoustic energy."""
+    dp = 1.0 / n_side
+    pos = lattice(2, (n_side, n_side), dp)
+    vel = np.zeros_like(pos)
+    vel[:, 0] = amp_v * np.sin(2 * math.pi * pos[:, 0])
+    phase = np.zeros(pos.shape[0], np.int32)
+    p = base_params(2, (1.0, 1.0), dp, (1.0, 1.0), (0.0, 0.0), 0.0, 0.1)
+    return {"name": "acoustic_wave_2d", "params": p, "pos": pos, "vel": vel, "phase": phase,
+            "R": 0.0}
