@@ -1,0 +1,245 @@
+/*
+ * rsph.h -- C-ABI of the MI355X (gfx950) Riemann-SPH multiphase surface-tension
+ * library (librsph.so).
+ *
+ * Method: Zhang, Lourenco and Hu, "Multiphase SPH for surface tension: resolving
+ * zero-surface-energy modes and achieving high Reynolds number simulations",
+ * arXiv 2503.16082.  Two immiscible weakly compressible fluids k (phase 0) and
+ * l (phase 1), each with a reference density rho0 and a dynamic viscosity eta,
+ * a common sound speed c0 and one surface-tension coefficient gamma (section 2);
+ * Riemann-SPH continuity and pressure terms (section 3.1, Eqs. 6-12); viscous
+ * acceleration (Eq. 13); transport-velocity position correction (section 3.2,
+ * Eqs. 14-15); surface stress and its divergence with the projected,
+ * momentum-conserving penalty force (section 4, Eqs. 19-33); dual-criteria time
+ * stepping (section 3.3, Eqs. 16-18); 5th-order Wendland kernel with h = 1.3 dp
+ * and cut-off 2h (section 5).  Domains are fully periodic boxes.
+ *
+ * Conventions used by every call:
+ *  - every pointer argument named in a signature is a HOST pointer; the library
+ *    copies inputs before returning and never keeps a caller pointer;
+ *  - particle arrays are row-major (n, dim) float64 in the caller's particle
+ *    order; the library keeps each particle's original index and returns
+ *    particle data in that order;
+ *  - the library owns all device memory of a system or pool and frees it in
+ *    rsph_destroy_system / rsph_pool_release / rsph_pool_destroy;
+ *  - a hip_stream passed in (a hipStream_t cast to void*) stays owned by the
+ *    caller and must outlive the system; NULL makes the library create its own;
+ *  - no call throws; every call returns an rsph_status and records a message
+ *    retrievable with rsph_last_error;
+ *  - a system (or a pool) may be used by one host thread at a time.
+ */
+#ifndef RSPH_H
+#define RSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsph_system rsph_system; /* opaque, library-owned */
+typedef struct rsph_pool rsph_pool;     /* opaque, library-owned */
+
+typedef enum {
+    RSPH_OK = 0,
+    RSPH_EINVAL = -1,   /* invalid argument: nothing was changed */
+    RSPH_ENOMEM = -2,   /* device allocation failed */
+    RSPH_EDEVICE = -3,  /* HIP runtime error */
+    RSPH_ESTATE = -4,   /* call not valid in the current state (no particles, faulted) */
+    RSPH_ENUMERIC = -5, /* a health check tripped during stepping: the system is faulted */
+    RSPH_EBUSY = -6     /* pool admission refused: HBM budget exhausted */
+} rsph_status;
+
+/* arithmetic form of the pair loops */
+enum {
+    RSPH_FP64 = 0, /* every operation in FP64: the reference form */
+    RSPH_MIXED = 1 /* FP32 pair loops on split (cell index + FP32 offset) positions,
+                      FP64 state, integrator, reductions and diagnostics */
+};
+
+/* method switches (rsph_params.flags) */
+#define RSPH_NO_PENALTY 1u             /* Eq. 26 instead of Eq. 33 */
+#define RSPH_NO_SHIFT 2u               /* no transport-velocity position correction (Eq. 14) */
+#define RSPH_NO_DENSITY_SUMMATION 4u   /* density by the continuity equation only */
+#define RSPH_GBAR_SINGLE_FIELD 8u      /* cross-phase mean colour gradient (grad C_i - grad C_j)/2 */
+#define RSPH_PENALTY_R3 16u            /* alternative reading of the penalty tensor (Eq. 30) */
+#define RSPH_NO_SURFACE 32u            /* no surface stress and no penalty */
+
+typedef struct {
+    int32_t dim;        /* 2 or 3 */
+    int32_t precision;  /* RSPH_FP64 or RSPH_MIXED */
+    double box[3];      /* periodic box lengths (box[2] unused in 2D) */
+    double dp;          /* initial particle spacing */
+    double h_over_dp;   /* smoothing length over dp [1.3] */
+    double rho0[2];     /* reference densities of fluids k and l */
+    double eta[2];      /* dynamic viscosities of fluids k and l (>= 0) */
+    double c0;          /* common artificial sound speed (> 0) */
+    double gamma;       /* surface-tension coefficient (>= 0) */
+    double xi;          /* penalty coefficient; < 0: 1.3 n + 0.6 for a density ratio 10^n */
+    double alpha_shift; /* position-correction coefficient alpha of Eq. 14 [0.2] */
+    double cfl_ad;      /* advection time-step factor of Eq. 16 [0.1] */
+    double cfl_ac;      /* acoustic time-step factor of Eq. 17 [0.6] */
+    double gravity[3];  /* body force g of Eq. 2 [0] */
+    uint32_t flags;     /* RSPH_NO_* switches [0] */
+    uint32_t reserved;
+} rsph_params;
+
+/* Observables of one system, all FP64, reduced on the device in a fixed order. */
+typedef struct {
+    double t;             /* simulated time */
+    int64_t n_outer;      /* advection steps taken */
+    int64_t n_sub;        /* acoustic substeps taken */
+    double dt_ad;         /* last advection step (Eqs. 16, 18) */
+    double dt_ac;         /* last acoustic substep (Eqs. 17, 18, clipped to the advection step) */
+    double momentum[3];   /* sum m v */
+    double kinetic;       /* sum m |v|^2 / 2 */
+    double mass[2];       /* per fluid */
+    double volume[2];     /* per fluid, sum m / rho */
+    double vmax[2];       /* per fluid max |v| */
+    double centroid[3];   /* fluid k, mass weighted, box coordinates */
+    double moment2[9];    /* fluid k, mass-weighted second moment about the centroid */
+    double r_eq;          /* equivalent radius of the fluid-k volume */
+    double p_in;          /* mean pressure of fluid k with |r - centroid| < r_eq - 3h */
+    double p_out;         /* mean pressure of fluid l with |r - centroid| > r_eq + 3h */
+    double n_in, n_out;   /* particle counts of the two means */
+    uint32_t health;      /* RSPH_HEALTH_* bits */
+    uint32_t reserved;
+} rsph_observables;
+
+#define RSPH_HEALTH_NONFINITE 1u  /* NaN or Inf in velocity, density or acceleration */
+#define RSPH_HEALTH_DENSITY 2u    /* rho <= 0 */
+#define RSPH_HEALTH_NEIGHBOURS 4u /* more neighbours than the list holds */
+#define RSPH_HEALTH_COINCIDENT 8u /* two neighbours closer than 1e-9 h */
+#define RSPH_HEALTH_DT 32u        /* acoustic step collapsed below 1e-12 of its no-flow value */
+
+/* particle fields readable with rsph_read_particles, and their width per particle */
+enum {
+    RSPH_FIELD_POS = 0,    /* dim */
+    RSPH_FIELD_VEL = 1,    /* dim */
+    RSPH_FIELD_RHO = 2,    /* 1 */
+    RSPH_FIELD_P = 3,      /* 1: c0^2 (rho - rho0) */
+    RSPH_FIELD_DRHO = 4,   /* 1: last continuity rate */
+    RSPH_FIELD_MASS = 5,   /* 1 */
+    RSPH_FIELD_PHASE = 6,  /* 1 (0.0 or 1.0) */
+    /* rates of the last rsph_eval_rates: */
+    RSPH_FIELD_ACC = 7,    /* dim: a^p + a^s + a^v + g */
+    RSPH_FIELD_ACC_P = 8,  /* dim: Riemann pressure acceleration (Eq. 7) */
+    RSPH_FIELD_ACC_S = 9,  /* dim: surface stress divergence plus penalty (Eq. 33) */
+    RSPH_FIELD_ACC_V = 10, /* dim: viscous acceleration (Eq. 13) */
+    RSPH_FIELD_GRADC = 11, /* dim: colour gradient (Eq. 22) */
+    RSPH_FIELD_RATE_DRHO = 12, /* 1: continuity rate (Eq. 6) */
+    RSPH_FIELD_B = 13,     /* dim*dim: correction matrix (Eq. 15), row-major */
+    RSPH_FIELD_DR = 14,    /* dim: position correction (Eq. 14), not applied */
+    RSPH_FIELD_SIGMA = 15, /* 1: W(0) + sum_j W_ij */
+    RSPH_FIELD_NNB = 16,   /* 1: neighbour count */
+    RSPH_FIELD_COUNT = 17
+};
+
+/* Fills *p with the documented defaults (2D, FP64, unit box, dp = 0.02, ...). */
+void rsph_params_default(rsph_params* p);
+
+/* Creates an empty system (no particles yet). Validates params: dim in {2,3};
+ * dp, rho0, c0 > 0; eta, gamma >= 0; at least 3 cells of edge >= 2h per axis and
+ * at most 1024; all values finite. EINVAL otherwise. */
+rsph_status rsph_create_system(const rsph_params* params, void* hip_stream, rsph_system** out);
+
+/* Sets (or resets) all particles: pos, vel (n x dim), phase (n, in {0,1}),
+ * mass (n, NULL -> rho0[phase] / sigma0 with sigma0 the lattice kernel sum, so a
+ * perfect lattice has rho = rho0), rho (n, NULL -> rho0[phase]).  Positions are
+ * wrapped into the box.  Resets t, counters, density rates and the fault state
+ * unless opts has RSPH_KEEP_CLOCK (then t and counters are kept: resume).
+ * EINVAL (nothing changed) on n < 1, NaN/Inf, a phase outside {0,1}, mass or
+ * rho <= 0, or two particles closer than 1e-3 dp. */
+#define RSPH_KEEP_CLOCK 1u
+rsph_status rsph_set_particles(rsph_system* sys, int64_t n, const double* pos, const double* vel,
+                               const int32_t* phase, const double* mass, const double* rho,
+                               uint32_t opts);
+
+/* Restores the continuity rates (n doubles, caller order) after
+ * rsph_set_particles(..., RSPH_KEEP_CLOCK), for a bitwise resume. */
+rsph_status rsph_set_drho(rsph_system* sys, int64_t n, const double* drho);
+
+/* Advances n_outer advection steps of the dual-criteria scheme (section 3.3),
+ * each with its own data-dependent number of acoustic substeps; returns when
+ * they are done (synchronises the stream). ENUMERIC if a health check trips
+ * (the system is then faulted and later steps return ESTATE). */
+rsph_status rsph_step(rsph_system* sys, int64_t n_outer);
+
+/* One evaluation, at the current state and with no update, of the neighbour
+ * geometry, kernel sum, viscous acceleration, correction matrix, position
+ * correction, colour gradient, accelerations and continuity rate (density as
+ * set, pressure c0^2 (rho - rho0)); read them with rsph_read_particles. */
+rsph_status rsph_eval_rates(rsph_system* sys);
+
+/* Reduces the observables on the device and copies them to *out. */
+rsph_status rsph_read_observables(rsph_system* sys, rsph_observables* out);
+
+/* Copies one field (RSPH_FIELD_*) of all n particles, caller order, into out
+ * (n * width doubles).  EINVAL if n differs from the system's particle count. */
+rsph_status rsph_read_particles(rsph_system* sys, int32_t field, int64_t n, double* out);
+
+/* Binning of the last rebuild: per particle (caller order) its cell key
+ * cx + nx (cy + ny cz) and its rank in cell order (cells ascending, then caller
+ * index ascending). */
+rsph_status rsph_read_binning(rsph_system* sys, int64_t n, uint32_t* key, int64_t* rank);
+
+/* Neighbour lists of the last rebuild in caller indices: start has n + 1
+ * entries, idx up to cap entries, each list in the library's stencil order.
+ * EINVAL if cap is too small. */
+rsph_status rsph_read_neighbours(rsph_system* sys, int64_t n, int64_t cap, int64_t* start,
+                                 int64_t* idx);
+
+/* Kernel timing: when enabled, every launch of the pair kernels is bracketed by
+ * HIP events on the system's stream; rsph_read_kernel_timing returns, per kernel
+ * (RSPH_KERNEL_*), the number of launches that did work and their summed
+ * duration in milliseconds since the last reset. */
+enum {
+    RSPH_KERNEL_BIN = 0,
+    RSPH_KERNEL_NEIGHBOURS = 1,
+    RSPH_KERNEL_ADVECTION = 2,
+    RSPH_KERNEL_SHIFT = 3,
+    RSPH_KERNEL_COLOUR = 4,
+    RSPH_KERNEL_FORCE = 5,
+    RSPH_KERNEL_CONTINUITY = 6,
+    RSPH_KERNEL_COUNT = 7
+};
+rsph_status rsph_set_kernel_timing(rsph_system* sys, int32_t enable);
+rsph_status rsph_read_kernel_timing(rsph_system* sys, int64_t* launches, double* ms);
+
+/* Frees the system and its device memory.  NULL is ignored. */
+void rsph_destroy_system(rsph_system* sys);
+
+const char* rsph_status_string(rsph_status s);
+/* Last error message of a system (or of the library when sys is NULL). */
+const char* rsph_last_error(const rsph_system* sys);
+
+/* ---- serving: many systems packed in one device array ------------------- */
+
+/* A pool packs the particles of many systems of one dimension and one
+ * precision into shared device arrays and steps them together in the same
+ * launches, each system with its own parameters and time steps.  hbm_budget
+ * bounds the device memory the pool may hold. */
+rsph_status rsph_pool_create(int32_t dim, int32_t precision, size_t hbm_budget_bytes,
+                             void* hip_stream, rsph_pool** out);
+/* Admits a system with its particles (as rsph_set_particles).  EBUSY if the
+ * budget cannot hold it now; EINVAL on bad input.  The returned system is
+ * owned by the pool: read it with the rsph_read_* calls, release it with
+ * rsph_pool_release. */
+rsph_status rsph_pool_admit(rsph_pool* pool, const rsph_params* params, int64_t n,
+                            const double* pos, const double* vel, const int32_t* phase,
+                            const double* mass, rsph_system** out);
+/* Advances each of the count systems by n_outer[k] advection steps; all of them
+ * progress in the same launches until each has done its own count. */
+rsph_status rsph_pool_step(rsph_pool* pool, rsph_system* const* systems, const int64_t* n_outer,
+                           int32_t count);
+/* Bytes of device memory the pool holds now. */
+size_t rsph_pool_bytes(const rsph_pool* pool);
+rsph_status rsph_pool_release(rsph_pool* pool, rsph_system* sys);
+void rsph_pool_destroy(rsph_pool* pool);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSPH_H */

@@ -1,0 +1,1290 @@
+// rsph_host.hip -- host side of librsph.so: parameter validation, packed
+// multi-system device layout, the dual-criteria step driver (section 3.3 of
+// arXiv 2503.16082) with device-side time-step control, observables and the
+// C-ABI declared in include/rsph.h.
+//
+// A standalone system is a pool holding one system, so every path below is the
+// served path with a batch of one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rsph.h"
+#include "rsph_internal.h"
+
+using namespace rsph;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHECK(expr)                                        \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) throw HipError{_e, #expr};      \
+    } while (0)
+
+struct StatusError {
+    rsph_status s;
+    std::string msg;
+};
+
+[[noreturn]] void fail(rsph_status s, const std::string& msg) { throw StatusError{s, msg}; }
+
+// Wendland C2 normalisation and the lattice kernel sum (self included) of a
+// perfect lattice of spacing dp: the reference number density of the
+// normalised density summation.
+double kernel_alpha(int dim, double h)
+{
+    return dim == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+}
+
+double kernel_w(int dim, double h, double r)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double a = 1.0 - 0.5 * q;
+    return kernel_alpha(dim, h) * a * a * a * a * (1.0 + 2.0 * q);
+}
+
+double lattice_sigma0(int dim, double h, double dp)
+{
+    const int reach = (int)std::ceil(2.0 * h / dp) + 1;
+    double s = 0.0;
+    for (int a = -reach; a <= reach; ++a)
+        for (int b = -reach; b <= reach; ++b)
+            for (int c = (dim == 3 ? -reach : 0); c <= (dim == 3 ? reach : 0); ++c)
+                s += kernel_w(dim, h, dp * std::sqrt((double)(a * a + b * b + c * c)));
+    return s;
+}
+
+struct TimedLaunch {
+    int kind;
+    int64_t substep;  // -1: not a substep kernel
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct rsph_pool {
+    int dim = 2;
+    int precision = RSPH_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    bool standalone = false;
+    std::vector<rsph_system*> systems;  // index == device table row
+    DevArrays A{};
+    int64_t P_cap = 0, C_cap = 0;
+    int S_cap = 0;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+    int32_t* d_flag = nullptr;  // [any active, health]
+    int32_t* h_flag = nullptr;  // pinned
+    int32_t* d_mask = nullptr;
+    std::string err;
+    // kernel timing
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    int64_t t_launches[RSPH_KERNEL_COUNT] = {};
+    double t_ms[RSPH_KERNEL_COUNT] = {};
+};
+
+struct rsph_system {
+    rsph_pool* pool = nullptr;
+    bool owns_pool = false;
+    rsph_params prm{};
+    SysConst sc{};
+    int64_t n = 0;
+    int64_t p_off = 0, p_cap = 0;
+    int64_t c_off = 0, ncells = 0;
+    int row = -1;
+    bool has_particles = false;
+    bool faulted = false;
+    bool rates_valid = false;
+    std::string err;
+};
+
+namespace {
+
+Launch launch_of(const rsph_pool* P)
+{
+    return Launch{P->stream, P->dim, P->precision == RSPH_FP64 ? 1 : 0};
+}
+
+int kmax_of(int dim) { return dim == 2 ? kKmax2 : kKmax3; }
+
+size_t slot_bytes(int dim, int precision)
+{
+    const size_t r4 = precision == RSPH_FP64 ? 32 : 16;
+    size_t b = 0;
+    b += 2 * (3 * 8 + 3 * 8 + 8 + 8 + 8 + 4 + 4);  // state, twice
+    b += 4 + 4 + 4;                              // key rank perm
+    b += 9 * r4;                                 // geo vbuf[2] th[2] col av bm[2]
+    b += 1 + 4 + (size_t)kmax_of(dim) * 4;       // flags ncount nbr
+    b += 5 * 24 + 8 + 72 + 24 + 8;               // rates
+    b += 16 * 8 / 64 + 4 / 64 + 1;               // observables partials, wave table
+    return b;
+}
+
+void validate_params(const rsph_params* p)
+{
+    if (!p) fail(RSPH_EINVAL, "params is NULL");
+    if (p->dim != 2 && p->dim != 3) fail(RSPH_EINVAL, "dim must be 2 or 3");
+    if (p->precision != RSPH_FP64 && p->precision != RSPH_MIXED)
+        fail(RSPH_EINVAL, "precision must be RSPH_FP64 or RSPH_MIXED");
+    const double vals[] = {p->dp, p->h_over_dp, p->rho0[0], p->rho0[1], p->eta[0], p->eta[1],
+                           p->c0, p->gamma, p->xi, p->alpha_shift, p->cfl_ad, p->cfl_ac,
+                           p->gravity[0], p->gravity[1], p->gravity[2]};
+    for (double v : vals)
+        if (!std::isfinite(v)) fail(RSPH_EINVAL, "parameters must be finite");
+    if (!(p->dp > 0) || !(p->h_over_dp > 0)) fail(RSPH_EINVAL, "dp and h_over_dp must be > 0");
+    if (!(p->rho0[0] > 0) || !(p->rho0[1] > 0)) fail(RSPH_EINVAL, "rho0 must be > 0");
+    if (p->eta[0] < 0 || p->eta[1] < 0) fail(RSPH_EINVAL, "eta must be >= 0");
+    if (!(p->c0 > 0)) fail(RSPH_EINVAL, "c0 must be > 0");
+    if (p->gamma < 0) fail(RSPH_EINVAL, "gamma must be >= 0");
+    if (!(p->cfl_ad > 0) || !(p->cfl_ac > 0)) fail(RSPH_EINVAL, "CFL factors must be > 0");
+    const double h = p->h_over_dp * p->dp;
+    for (int a = 0; a < p->dim; ++a) {
+        if (!std::isfinite(p->box[a]) || !(p->box[a] > 0)) fail(RSPH_EINVAL, "box must be > 0");
+        const double nc = std::floor(p->box[a] / (2.0 * h));
+        if (nc < 3) fail(RSPH_EINVAL, "box must hold at least 3 cells of edge 2h per axis");
+        if (nc > kMaxCellsPerAxis) fail(RSPH_EINVAL, "at most 1024 cells per axis");
+    }
+}
+
+SysConst make_const(const rsph_params& p)
+{
+    SysConst S{};
+    S.dim = p.dim;
+    S.flags = p.flags;
+    const double h = p.h_over_dp * p.dp;
+    S.h = h;
+    S.inv_h = 1.0 / h;
+    S.cut2 = (2.0 * h) * (2.0 * h);
+    for (int a = 0; a < 3; ++a) {
+        if (a < p.dim) {
+            S.ncell[a] = (int32_t)std::floor(p.box[a] / (2.0 * h));
+            S.box[a] = p.box[a];
+        } else {
+            S.ncell[a] = 1;
+            S.box[a] = 1.0;
+        }
+        S.half_box[a] = 0.5 * S.box[a];
+        S.inv_cell[a] = (double)S.ncell[a] / S.box[a];
+        S.cell[a] = S.box[a] / (double)S.ncell[a];
+        S.grav[a] = a < p.dim ? p.gravity[a] : 0.0;
+    }
+    S.ncells = (int64_t)S.ncell[0] * S.ncell[1] * S.ncell[2];
+    S.w_alpha = kernel_alpha(p.dim, h);
+    S.w0 = S.w_alpha;
+    S.dw_coef = -5.0 * S.w_alpha / h;
+    S.sigma0 = lattice_sigma0(p.dim, h, p.dp);
+    for (int f = 0; f < 2; ++f) {
+        S.rho0[f] = p.rho0[f];
+        S.eta[f] = p.eta[f];
+        S.dtad_visc[f] = p.eta[f] > 0 ? p.cfl_ad * (p.rho0[f] * h * h / p.eta[f]) : INFINITY;
+        S.dtac_surf[f] = p.gamma > 0
+                             ? p.cfl_ac * std::sqrt(p.rho0[f] * h * h * h / (2.0 * M_PI * p.gamma))
+                             : INFINITY;
+    }
+    S.c0 = p.c0;
+    S.inv_c0 = 1.0 / p.c0;
+    S.c0sq = p.c0 * p.c0;
+    S.gamma = p.gamma;
+    S.xi = p.xi >= 0 ? p.xi : 1.3 * std::fabs(std::log10(p.rho0[0] / p.rho0[1])) + 0.6;
+    S.alpha_h2 = p.alpha_shift * h * h;
+    S.cfl_ad = p.cfl_ad;
+    S.cfl_ac = p.cfl_ac;
+    S.coincident2 = (1e-9 * h) * (1e-9 * h);
+    S.close2 = (1e-3 * p.dp) * (1e-3 * p.dp);
+    return S;
+}
+
+template <typename T>
+T* dev_alloc(rsph_pool* P, size_t count)
+{
+    void* p = nullptr;
+    size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(RSPH_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    P->allocs.push_back(p);
+    P->bytes += b;
+    return (T*)p;
+}
+
+void free_arrays(rsph_pool* P)
+{
+    for (void* p : P->allocs) (void)hipFree(p);
+    P->allocs.clear();
+    P->bytes = 0;
+    P->A = DevArrays{};
+    P->P_cap = P->C_cap = 0;
+    P->S_cap = 0;
+}
+
+// Allocates every device array for the capacities given (contents undefined).
+void alloc_arrays(rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
+{
+    DevArrays& A = P->A;
+    A = DevArrays{};
+    const size_t r4 = P->precision == RSPH_FP64 ? 32 : 16;
+    A.P = Pc;
+    A.C = Cc;
+    A.kmax = kmax_of(P->dim);
+    for (int a = 0; a < 3; ++a) {
+        A.pos[a] = dev_alloc<double>(P, Pc);
+        A.vel[a] = dev_alloc<double>(P, Pc);
+        A.pos2[a] = dev_alloc<double>(P, Pc);
+        A.vel2[a] = dev_alloc<double>(P, Pc);
+    }
+    A.rho = dev_alloc<double>(P, Pc);
+    A.drho = dev_alloc<double>(P, Pc);
+    A.mass = dev_alloc<double>(P, Pc);
+    A.id = dev_alloc<int32_t>(P, Pc);
+    A.phase = dev_alloc<int32_t>(P, Pc);
+    A.rho2 = dev_alloc<double>(P, Pc);
+    A.drho2 = dev_alloc<double>(P, Pc);
+    A.mass2 = dev_alloc<double>(P, Pc);
+    A.id2 = dev_alloc<int32_t>(P, Pc);
+    A.phase2 = dev_alloc<int32_t>(P, Pc);
+    A.key = dev_alloc<uint32_t>(P, Pc);
+    A.rank = dev_alloc<int32_t>(P, Pc);
+    A.perm = dev_alloc<int32_t>(P, Pc);
+    A.cell_cnt = dev_alloc<int32_t>(P, Cc);
+    A.cell_start = dev_alloc<int32_t>(P, Cc + 1);
+    A.cell_sys = dev_alloc<int32_t>(P, Cc);
+    A.scan_part = dev_alloc<int32_t>(P, 2048);
+    A.wave_sys = dev_alloc<int32_t>(P, Pc / kWave);
+    A.geo = dev_alloc<char>(P, Pc * r4);
+    for (int k = 0; k < 2; ++k) {
+        A.vbuf[k] = dev_alloc<char>(P, Pc * r4);
+        A.th[k] = dev_alloc<char>(P, Pc * r4);
+        A.bm[k] = dev_alloc<char>(P, Pc * r4);
+    }
+    A.col = dev_alloc<char>(P, Pc * r4);
+    A.av = dev_alloc<char>(P, Pc * r4);
+    A.flags = dev_alloc<uint8_t>(P, Pc);
+    A.nbr = dev_alloc<uint32_t>(P, Pc * (size_t)A.kmax);
+    A.ncount = dev_alloc<int32_t>(P, Pc);
+    A.r_acc = dev_alloc<double>(P, 3 * Pc);
+    A.r_accp = dev_alloc<double>(P, 3 * Pc);
+    A.r_accs = dev_alloc<double>(P, 3 * Pc);
+    A.r_accv = dev_alloc<double>(P, 3 * Pc);
+    A.r_gradc = dev_alloc<double>(P, 3 * Pc);
+    A.r_drho = dev_alloc<double>(P, Pc);
+    A.r_b = dev_alloc<double>(P, 9 * Pc);
+    A.r_dr = dev_alloc<double>(P, 3 * Pc);
+    A.r_sigma = dev_alloc<double>(P, Pc);
+    A.obs_part = dev_alloc<double>(P, (Pc / kWave) * kObsPart);
+    A.obs_out = dev_alloc<double>(P, (size_t)Sc * kObsOut);
+    A.sc = dev_alloc<SysConst>(P, Sc);
+    A.sd = dev_alloc<SysDyn>(P, Sc);
+    P->d_flag = dev_alloc<int32_t>(P, 2);
+    P->d_mask = dev_alloc<int32_t>(P, Sc);
+    P->P_cap = Pc;
+    P->C_cap = Cc;
+    P->S_cap = Sc;
+}
+
+struct Layout {
+    std::vector<int64_t> p_off, p_cap, c_off;
+    int64_t P = 0, C = 0;
+};
+
+Layout plan(const std::vector<rsph_system*>& sys, const rsph_system* extra)
+{
+    Layout L;
+    auto add = [&](const rsph_system* s) {
+        int64_t cap = (s->n + kWave - 1) / kWave * kWave;
+        L.p_off.push_back(L.P);
+        L.p_cap.push_back(cap);
+        L.c_off.push_back(L.C);
+        L.P += cap;
+        L.C += s->sc.ncells;
+    };
+    for (auto* s : sys) add(s);
+    if (extra) add(extra);
+    L.P = std::max<int64_t>((L.P + kBlock - 1) / kBlock * kBlock, kBlock);
+    L.C = std::max<int64_t>(L.C, 1);
+    if (L.C > kMaxCells) fail(RSPH_EINVAL, "more than 2048*2048 cells in one pool");
+    if (L.P > (int64_t)INT32_MAX / 2) fail(RSPH_EINVAL, "too many particle slots");
+    return L;
+}
+
+size_t estimate_bytes(const rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
+{
+    return (size_t)Pc * slot_bytes(P->dim, P->precision) + (size_t)Cc * 12 +
+           (size_t)Sc * (sizeof(SysConst) + sizeof(SysDyn) + kObsOut * 8 + 4) + (1 << 16);
+}
+
+// Re-packs the pool's persistent particle state after systems were added or
+// removed: every member keeps its particles, t and counters; slot ranges,
+// cell ranges and the device tables are rebuilt.
+void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
+{
+    const hipStream_t st = P->stream;
+    Layout L = plan(members, nullptr);
+    const int S = (int)members.size();
+    // download the dynamic scalars of the current members
+    std::vector<SysDyn> dyn_old(P->systems.size());
+    if (!P->systems.empty() && P->A.sd) {
+        HIPCHECK(hipMemcpyAsync(dyn_old.data(), P->A.sd, sizeof(SysDyn) * P->systems.size(),
+                                hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    const bool grow = L.P > P->P_cap || L.C > P->C_cap || S > P->S_cap;
+    DevArrays old = P->A;
+    std::vector<void*> old_allocs;
+    size_t old_bytes = P->bytes;
+    if (grow) {
+        const int64_t Pc = std::max<int64_t>(L.P, P->P_cap + P->P_cap / 2 / kBlock * kBlock);
+        const int64_t Cc = std::max<int64_t>(L.C, P->C_cap + P->C_cap / 2);
+        const int Sc = std::max(S, P->S_cap + P->S_cap / 2 + 1);
+        const int64_t Pg = P->standalone ? L.P : Pc;
+        const int64_t Cg = P->standalone ? L.C : Cc;
+        const int Sg = P->standalone ? S : Sc;
+        if (P->budget && estimate_bytes(P, Pg, Cg, Sg) > P->budget)
+            fail(RSPH_EBUSY, "pool HBM budget exhausted");
+        old_allocs.swap(P->allocs);
+        P->bytes = 0;
+        try {
+            alloc_arrays(P, Pg, Cg, Sg);
+        } catch (...) {
+            for (void* p : P->allocs) (void)hipFree(p);
+            P->allocs.swap(old_allocs);
+            P->bytes = old_bytes;
+            P->A = old;
+            throw;
+        }
+    }
+    DevArrays& A = P->A;
+    // copy each member's persistent state from its old range into the
+    // second buffer (new capacity, new offsets), then make that current
+    double** dst_d[] = {&A.pos2[0], &A.pos2[1], &A.pos2[2], &A.vel2[0], &A.vel2[1], &A.vel2[2],
+                        &A.rho2, &A.drho2, &A.mass2};
+    double* src_d[] = {old.pos[0], old.pos[1], old.pos[2], old.vel[0], old.vel[1], old.vel[2],
+                       old.rho, old.drho, old.mass};
+    int32_t** dst_i[] = {&A.id2, &A.phase2};
+    int32_t* src_i[] = {old.id, old.phase};
+    for (int k = 0; k < S; ++k) {
+        rsph_system* s = members[k];
+        if (!s->has_particles || s->row < 0) continue;
+        for (int q = 0; q < 9; ++q)
+            HIPCHECK(hipMemcpyAsync(*dst_d[q] + L.p_off[k], src_d[q] + s->p_off,
+                                    sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
+        for (int q = 0; q < 2; ++q)
+            HIPCHECK(hipMemcpyAsync(*dst_i[q] + L.p_off[k], src_i[q] + s->p_off,
+                                    sizeof(int32_t) * s->n, hipMemcpyDeviceToDevice, st));
+    }
+    for (int a = 0; a < 3; ++a) {
+        std::swap(A.pos[a], A.pos2[a]);
+        std::swap(A.vel[a], A.vel2[a]);
+    }
+    std::swap(A.rho, A.rho2);
+    std::swap(A.drho, A.drho2);
+    std::swap(A.mass, A.mass2);
+    std::swap(A.id, A.id2);
+    std::swap(A.phase, A.phase2);
+    // tables
+    std::vector<SysConst> sc(S);
+    std::vector<SysDyn> sd(S);
+    std::vector<int32_t> wave(A.P / kWave, -1);
+    std::vector<int32_t> csys(A.C, -1);
+    for (int k = 0; k < S; ++k) {
+        rsph_system* s = members[k];
+        SysDyn d{};
+        if (s->row >= 0 && s->row < (int)dyn_old.size()) d = dyn_old[s->row];
+        s->p_off = L.p_off[k];
+        s->p_cap = L.p_cap[k];
+        s->c_off = L.c_off[k];
+        s->row = k;
+        s->sc.p_off = s->p_off;
+        s->sc.p_n = s->has_particles ? s->n : 0;
+        s->sc.c_off = s->c_off;
+        sc[k] = s->sc;
+        sd[k] = d;
+        for (int64_t w = s->p_off / kWave; w < (s->p_off + s->p_cap) / kWave; ++w) wave[w] = k;
+        for (int64_t c = s->c_off; c < s->c_off + s->ncells; ++c) csys[c] = k;
+    }
+    A.nsys = S;
+    if (S) {
+        HIPCHECK(hipMemcpyAsync((void*)A.sc, sc.data(), sizeof(SysConst) * S, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(A.sd, sd.data(), sizeof(SysDyn) * S, hipMemcpyHostToDevice, st));
+    }
+    HIPCHECK(hipMemcpyAsync(A.wave_sys, wave.data(), sizeof(int32_t) * wave.size(), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(A.cell_sys, csys.data(), sizeof(int32_t) * csys.size(), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    for (void* p : old_allocs) (void)hipFree(p);
+    P->systems = members;
+    for (auto* s : members) s->rates_valid = false;
+}
+
+// ---- kernel timing ---------------------------------------------------------
+
+hipEvent_t take_event(rsph_pool* P)
+{
+    if (!P->event_pool.empty()) {
+        hipEvent_t e = P->event_pool.back();
+        P->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    return e;
+}
+
+struct TimeScope {
+    rsph_pool* P;
+    int kind;
+    int64_t substep;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimeScope(rsph_pool* P_, int kind_, int64_t sub) : P(P_), kind(kind_), substep(sub)
+    {
+        if (!P->timing) return;
+        a = take_event(P);
+        b = take_event(P);
+        HIPCHECK(hipEventRecord(a, P->stream));
+    }
+    ~TimeScope() noexcept(false)
+    {
+        if (!P->timing) return;
+        HIPCHECK(hipEventRecord(b, P->stream));
+        P->pending.push_back(TimedLaunch{kind, substep, a, b});
+    }
+};
+
+// Folds recorded launches into the totals; substep launches at or beyond
+// `substeps_done` found every system idle and are dropped.
+void collect_timing(rsph_pool* P, int64_t substeps_done)
+{
+    for (auto& t : P->pending) {
+        if (t.substep < 0 || t.substep < substeps_done) {
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, t.start, t.stop));
+            P->t_ms[t.kind] += ms;
+            P->t_launches[t.kind] += 1;
+        }
+        P->event_pool.push_back(t.start);
+        P->event_pool.push_back(t.stop);
+    }
+    P->pending.clear();
+}
+
+// ---- driver ----------------------------------------------------------------
+
+void set_mask(rsph_pool* P, const std::vector<int32_t>& mask)
+{
+    HIPCHECK(hipMemcpyAsync(P->d_mask, mask.data(), sizeof(int32_t) * mask.size(),
+                            hipMemcpyHostToDevice, P->stream));
+    launch_set_stepping(launch_of(P), P->A, P->d_mask);
+}
+
+void rebuild(rsph_pool* P, int mode)
+{
+    const Launch L = launch_of(P);
+    DevArrays& A = P->A;
+    A.mode = mode;
+    {
+        TimeScope t(P, RSPH_KERNEL_BIN, -1);
+        launch_bin(L, A, A.C);
+    }
+    {
+        TimeScope t(P, RSPH_KERNEL_NEIGHBOURS, -1);
+        launch_neighbours(L, A);
+    }
+}
+
+void read_flags(rsph_pool* P, int slot, int32_t* any, uint32_t* health)
+{
+    launch_any_active(launch_of(P), P->A, slot, P->d_flag);
+    HIPCHECK(hipMemcpyAsync(P->h_flag, P->d_flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    *any = P->h_flag[0];
+    *health = (uint32_t)P->h_flag[1];
+}
+
+std::vector<SysDyn> read_dyn(rsph_pool* P)
+{
+    std::vector<SysDyn> d(P->systems.size());
+    if (!d.empty()) {
+        HIPCHECK(hipMemcpyAsync(d.data(), P->A.sd, sizeof(SysDyn) * d.size(), hipMemcpyDeviceToHost, P->stream));
+        HIPCHECK(hipStreamSynchronize(P->stream));
+    }
+    return d;
+}
+
+constexpr uint32_t kFaultBits =
+    kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident | kHealthDtCollapse;
+constexpr int64_t kMaxSubsteps = 1000000;  // per advection step
+
+// One advection step for the systems whose mask entry is 1. Returns the OR of
+// the health bits of all systems afterwards.
+uint32_t outer_step(rsph_pool* P, const std::vector<int32_t>& mask)
+{
+    const Launch L = launch_of(P);
+    DevArrays& A = P->A;
+    set_mask(P, mask);
+    rebuild(P, 0);
+    launch_dt_advection(L, A);
+    {
+        TimeScope t(P, RSPH_KERNEL_ADVECTION, -1);
+        launch_advection(L, A);
+    }
+    {
+        TimeScope t(P, RSPH_KERNEL_SHIFT, -1);
+        launch_shift(L, A);
+    }
+    // substep count predicted from the first acoustic step of each system
+    std::vector<SysDyn> d0 = read_dyn(P);
+    int64_t predicted = 1;
+    std::vector<long long> nsub0(d0.size());
+    for (size_t s = 0; s < d0.size(); ++s) {
+        nsub0[s] = d0[s].n_sub;
+        if (!mask[s] || !d0[s].active[0]) continue;
+        const double r = d0[s].dt_ad / d0[s].dt[0];
+        predicted = std::max<int64_t>(predicted, (int64_t)std::ceil(r * (1.0 + 1e-9)));
+    }
+    int64_t k = 0;
+    int64_t chunk = std::min<int64_t>(predicted, 4096);
+    uint32_t health = 0;
+    for (;;) {
+        for (int64_t q = 0; q < chunk; ++q, ++k) {
+            const int slot = (int)(k & 1);
+            {
+                TimeScope t(P, RSPH_KERNEL_COLOUR, k);
+                launch_colour(L, A, slot);
+            }
+            {
+                TimeScope t(P, RSPH_KERNEL_FORCE, k);
+                launch_force(L, A, slot);
+            }
+            launch_dt_substep(L, A, slot);
+            {
+                TimeScope t(P, RSPH_KERNEL_CONTINUITY, k);
+                launch_continuity(L, A, slot);
+            }
+        }
+        int32_t any = 0;
+        read_flags(P, (int)(k & 1), &any, &health);
+        if (!any || (health & kFaultBits)) break;
+        if (k >= kMaxSubsteps) fail(RSPH_ENUMERIC, "more than 1e6 acoustic substeps in one advection step");
+        chunk = std::min<int64_t>(4096, std::max<int64_t>(1, (chunk + 7) / 8));
+    }
+    if (P->timing) {
+        std::vector<SysDyn> d1 = read_dyn(P);
+        int64_t done = 0;
+        for (size_t s = 0; s < d1.size(); ++s) done = std::max<int64_t>(done, d1[s].n_sub - nsub0[s]);
+        collect_timing(P, done);
+    }
+    return health;
+}
+
+template <typename F>
+rsph_status guarded(std::string* err, F&& f)
+{
+    try {
+        f();
+        return RSPH_OK;
+    } catch (const StatusError& e) {
+        if (err) *err = e.msg;
+        g_last_error = e.msg;
+        return e.s;
+    } catch (const HipError& e) {
+        std::string m = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+        if (err) *err = m;
+        g_last_error = m;
+        return RSPH_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        if (err) *err = "host allocation failed";
+        g_last_error = "host allocation failed";
+        return RSPH_ENOMEM;
+    } catch (...) {
+        if (err) *err = "unexpected error";
+        g_last_error = "unexpected error";
+        return RSPH_EDEVICE;
+    }
+}
+
+void validate_particles(const rsph_params& p, int64_t n, const double* pos, const double* vel,
+                        const int32_t* phase, const double* mass, const double* rho)
+{
+    if (n < 1) fail(RSPH_EINVAL, "n must be >= 1");
+    if (n > (int64_t)INT32_MAX / 2) fail(RSPH_EINVAL, "too many particles");
+    if (!pos || !vel || !phase) fail(RSPH_EINVAL, "pos, vel and phase are required");
+    const int d = p.dim;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!std::isfinite(pos[i]) || !std::isfinite(vel[i])) fail(RSPH_EINVAL, "non-finite position or velocity");
+    for (int64_t i = 0; i < n; ++i)
+        if (phase[i] != 0 && phase[i] != 1) fail(RSPH_EINVAL, "phase must be 0 or 1");
+    if (mass)
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(mass[i]) || !(mass[i] > 0)) fail(RSPH_EINVAL, "mass must be finite and > 0");
+    if (rho)
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(rho[i]) || !(rho[i] > 0)) fail(RSPH_EINVAL, "rho must be finite and > 0");
+}
+
+// Uploads particles into the system's (already planned) slot range.
+void upload_particles(rsph_system* s, const double* pos, const double* vel, const int32_t* phase,
+                      const double* mass, const double* rho)
+{
+    rsph_pool* P = s->pool;
+    const int64_t n = s->n;
+    const int d = s->prm.dim;
+    std::vector<double> buf(n);
+    auto put = [&](double* dst) {
+        HIPCHECK(hipMemcpy(dst + s->p_off, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    };
+    for (int a = 0; a < 3; ++a) {
+        for (int64_t i = 0; i < n; ++i) {
+            double x = a < d ? pos[i * d + a] : 0.0;
+            if (a < d) {
+                const double L = s->prm.box[a];
+                x = x - L * std::floor(x / L);
+                if (x >= L) x -= L;
+            }
+            buf[i] = x;
+        }
+        put(P->A.pos[a]);
+        for (int64_t i = 0; i < n; ++i) buf[i] = a < d ? vel[i * d + a] : 0.0;
+        put(P->A.vel[a]);
+    }
+    for (int64_t i = 0; i < n; ++i) buf[i] = mass ? mass[i] : s->prm.rho0[phase[i]] / s->sc.sigma0;
+    put(P->A.mass);
+    for (int64_t i = 0; i < n; ++i) buf[i] = rho ? rho[i] : s->prm.rho0[phase[i]];
+    put(P->A.rho);
+    for (int64_t i = 0; i < n; ++i) buf[i] = 0.0;
+    put(P->A.drho);
+    std::vector<int32_t> ib(n);
+    for (int64_t i = 0; i < n; ++i) ib[i] = (int32_t)i;
+    HIPCHECK(hipMemcpy(P->A.id + s->p_off, ib.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(P->A.phase + s->p_off, phase, sizeof(int32_t) * n, hipMemcpyHostToDevice));
+}
+
+void reset_dyn(rsph_system* s, bool keep_clock)
+{
+    rsph_pool* P = s->pool;
+    SysDyn d{};
+    if (keep_clock) {
+        HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
+    }
+    d.health = 0;
+    d.vmax_acc[0] = d.vmax_acc[1] = 0;
+    d.active[0] = d.active[1] = 0;
+    d.stepping = 0;
+    if (!keep_clock) {
+        d.t = d.tau = d.dt_ad = d.dt_last = 0.0;
+        d.n_sub = d.n_outer = 0;
+        d.dt[0] = d.dt[1] = 0.0;
+        d.vmax[0] = d.vmax[1] = 0.0;
+    }
+    HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
+}
+
+// Rebuilds the neighbourhood of one system without changing its state and
+// rejects inputs with particles closer than 1e-3 dp or overflowing lists.
+void check_spacing(rsph_system* s)
+{
+    rsph_pool* P = s->pool;
+    std::vector<int32_t> mask(P->systems.size(), 0);
+    mask[s->row] = 1;
+    set_mask(P, mask);
+    rebuild(P, 1);
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    SysDyn d;
+    HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
+    const uint32_t bad = d.health;
+    d.health = 0;
+    d.vmax_acc[0] = d.vmax_acc[1] = 0;
+    d.stepping = 0;
+    HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
+    if (bad & (kHealthClose | kHealthCoincident))
+        fail(RSPH_EINVAL, "two particles are closer than 1e-3 dp");
+    if (bad & kHealthNeighbours) fail(RSPH_EINVAL, "a particle has more neighbours than the list holds");
+}
+
+void make_pool(rsph_pool* P, int dim, int precision, size_t budget, void* stream)
+{
+    P->dim = dim;
+    P->precision = precision;
+    P->budget = budget;
+    if (stream) {
+        P->stream = (hipStream_t)stream;
+        P->own_stream = false;
+    } else {
+        HIPCHECK(hipStreamCreate(&P->stream));
+        P->own_stream = true;
+    }
+    HIPCHECK(hipHostMalloc((void**)&P->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+}
+
+void destroy_pool(rsph_pool* P)
+{
+    if (!P) return;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    for (auto& t : P->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : P->event_pool) (void)hipEventDestroy(e);
+    free_arrays(P);
+    if (P->h_flag) (void)hipHostFree(P->h_flag);
+    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+}
+
+// particle -> field readers
+int field_width(int field, int d)
+{
+    switch (field) {
+    case RSPH_FIELD_POS: case RSPH_FIELD_VEL: case RSPH_FIELD_ACC: case RSPH_FIELD_ACC_P:
+    case RSPH_FIELD_ACC_S: case RSPH_FIELD_ACC_V: case RSPH_FIELD_GRADC: case RSPH_FIELD_DR:
+        return d;
+    case RSPH_FIELD_B:
+        return d * d;
+    default:
+        return 1;
+    }
+}
+
+template <typename T>
+std::vector<T> dl(rsph_pool* P, const T* src, int64_t count)
+{
+    std::vector<T> v(count);
+    if (count) HIPCHECK(hipMemcpy(v.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
+    return v;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+
+extern "C" {
+
+void rsph_params_default(rsph_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->dim = 2;
+    p->precision = RSPH_FP64;
+    p->box[0] = p->box[1] = p->box[2] = 1.0;
+    p->dp = 0.02;
+    p->h_over_dp = 1.3;
+    p->rho0[0] = p->rho0[1] = 1.0;
+    p->eta[0] = p->eta[1] = 0.0;
+    p->c0 = 1.0;
+    p->gamma = 0.0;
+    p->xi = -1.0;
+    p->alpha_shift = 0.2;
+    p->cfl_ad = 0.1;
+    p->cfl_ac = 0.6;
+}
+
+const char* rsph_status_string(rsph_status s)
+{
+    switch (s) {
+    case RSPH_OK: return "ok";
+    case RSPH_EINVAL: return "invalid argument";
+    case RSPH_ENOMEM: return "out of device memory";
+    case RSPH_EDEVICE: return "device error";
+    case RSPH_ESTATE: return "invalid state";
+    case RSPH_ENUMERIC: return "numerical fault";
+    case RSPH_EBUSY: return "busy: budget exhausted";
+    }
+    return "unknown status";
+}
+
+const char* rsph_last_error(const rsph_system* sys)
+{
+    return sys ? sys->err.c_str() : g_last_error.c_str();
+}
+
+rsph_status rsph_create_system(const rsph_params* params, void* hip_stream, rsph_system** out)
+{
+    return guarded(nullptr, [&] {
+        if (!out) fail(RSPH_EINVAL, "out is NULL");
+        *out = nullptr;
+        validate_params(params);
+        rsph_pool* P = new rsph_pool();
+        try {
+            make_pool(P, params->dim, params->precision, 0, hip_stream);
+        } catch (...) {
+            destroy_pool(P);
+            throw;
+        }
+        P->standalone = true;
+        rsph_system* s = new rsph_system();
+        s->pool = P;
+        s->owns_pool = true;
+        s->prm = *params;
+        s->sc = make_const(*params);
+        s->ncells = s->sc.ncells;
+        *out = s;
+    });
+}
+
+rsph_status rsph_set_particles(rsph_system* s, int64_t n, const double* pos, const double* vel,
+                               const int32_t* phase, const double* mass, const double* rho,
+                               uint32_t opts)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!s->owns_pool) fail(RSPH_ESTATE, "systems of a served pool take particles at admission");
+        validate_particles(s->prm, n, pos, vel, phase, mass, rho);
+        rsph_pool* P = s->pool;
+        const bool keep = (opts & RSPH_KEEP_CLOCK) && s->has_particles && s->row >= 0;
+        s->has_particles = false;
+        s->n = n;
+        // standalone pool: size the arrays exactly for this system
+        Layout L = plan({}, s);
+        if (L.P != P->P_cap || L.C != P->C_cap) {
+            std::vector<SysDyn> keepd;
+            if (keep) keepd = read_dyn(P);
+            free_arrays(P);
+            alloc_arrays(P, L.P, L.C, 1);
+            s->row = -1;
+            repack(P, {s});
+            if (keep) HIPCHECK(hipMemcpy(P->A.sd, keepd.data(), sizeof(SysDyn), hipMemcpyHostToDevice));
+        } else {
+            repack(P, {s});
+        }
+        s->has_particles = true;
+        s->sc.p_n = n;
+        HIPCHECK(hipMemcpy((void*)(P->A.sc + s->row), &s->sc, sizeof(SysConst), hipMemcpyHostToDevice));
+        upload_particles(s, pos, vel, phase, mass, rho);
+        reset_dyn(s, keep);
+        s->faulted = false;
+        s->rates_valid = false;
+        try {
+            check_spacing(s);
+        } catch (...) {
+            s->has_particles = false;
+            throw;
+        }
+    });
+}
+
+rsph_status rsph_set_drho(rsph_system* s, int64_t n, const double* drho)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        if (n != s->n || !drho) fail(RSPH_EINVAL, "n must equal the particle count");
+        rsph_pool* P = s->pool;
+        std::vector<int32_t> id = dl(P, P->A.id + s->p_off, n);
+        std::vector<double> v(n);
+        for (int64_t k = 0; k < n; ++k) v[k] = drho[id[k]];
+        HIPCHECK(hipMemcpy(P->A.drho + s->p_off, v.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    });
+}
+
+rsph_status rsph_step(rsph_system* s, int64_t n_outer)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (n_outer < 0) fail(RSPH_EINVAL, "n_outer must be >= 0");
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        if (s->faulted) fail(RSPH_ESTATE, "system is faulted; reset it with rsph_set_particles");
+        rsph_pool* P = s->pool;
+        std::vector<int32_t> mask(P->systems.size(), 0);
+        mask[s->row] = 1;
+        s->rates_valid = false;
+        for (int64_t k = 0; k < n_outer; ++k) {
+            uint32_t h = outer_step(P, mask);
+            if (h & kFaultBits) {
+                s->faulted = true;
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "health check tripped (bits 0x%x) in advection step", h);
+                fail(RSPH_ENUMERIC, buf);
+            }
+        }
+        HIPCHECK(hipStreamSynchronize(P->stream));
+    });
+}
+
+rsph_status rsph_eval_rates(rsph_system* s)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        rsph_pool* P = s->pool;
+        const Launch L = launch_of(P);
+        std::vector<int32_t> mask(P->systems.size(), 0);
+        mask[s->row] = 1;
+        set_mask(P, mask);
+        rebuild(P, 1);
+        DevArrays& A = P->A;
+        A.mode = 1;
+        launch_advection(L, A);
+        launch_shift(L, A);
+        launch_colour(L, A, 0);
+        launch_force(L, A, 0);
+        launch_continuity(L, A, 0);
+        A.mode = 0;
+        // the evaluation's |v| max is not an advection-step input
+        SysDyn d;
+        HIPCHECK(hipMemcpyAsync(&d, A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost, P->stream));
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        d.vmax_acc[0] = d.vmax_acc[1] = 0;
+        d.stepping = 0;
+        HIPCHECK(hipMemcpy(A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
+        s->rates_valid = true;
+    });
+}
+
+rsph_status rsph_read_observables(rsph_system* s, rsph_observables* out)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!out) fail(RSPH_EINVAL, "out is NULL");
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        rsph_pool* P = s->pool;
+        const Launch L = launch_of(P);
+        launch_observables(L, P->A, P->A.P / kWave);
+        double o[kObsOut];
+        SysDyn d;
+        HIPCHECK(hipMemcpyAsync(o, P->A.obs_out + (int64_t)s->row * kObsOut, sizeof o, hipMemcpyDeviceToHost, P->stream));
+        HIPCHECK(hipMemcpyAsync(&d, P->A.sd + s->row, sizeof d, hipMemcpyDeviceToHost, P->stream));
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        std::memset(out, 0, sizeof(*out));
+        out->t = d.t;
+        out->n_outer = d.n_outer;
+        out->n_sub = d.n_sub;
+        out->dt_ad = d.dt_ad;
+        out->dt_ac = d.dt_last;
+        for (int a = 0; a < 3; ++a) out->momentum[a] = o[a];
+        out->kinetic = o[3];
+        out->mass[0] = o[4];
+        out->mass[1] = o[5];
+        out->volume[0] = o[6];
+        out->volume[1] = o[7];
+        out->vmax[0] = o[8];
+        out->vmax[1] = o[9];
+        for (int a = 0; a < 3; ++a) out->centroid[a] = o[10 + a];
+        out->r_eq = o[13];
+        const double m2[6] = {o[16], o[17], o[18], o[19], o[20], o[21]};
+        const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+        for (int q = 0; q < 9; ++q) out->moment2[q] = m2[idx[q]];
+        out->n_in = o[23];
+        out->n_out = o[25];
+        out->p_in = o[23] > 0 ? o[22] / o[23] : 0.0;
+        out->p_out = o[25] > 0 ? o[24] / o[25] : 0.0;
+        out->health = d.health;
+    });
+}
+
+rsph_status rsph_read_particles(rsph_system* s, int32_t field, int64_t n, double* out)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!out) fail(RSPH_EINVAL, "out is NULL");
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        if (n != s->n) fail(RSPH_EINVAL, "n must equal the particle count");
+        if (field < 0 || field >= RSPH_FIELD_COUNT) fail(RSPH_EINVAL, "unknown field");
+        if (field >= RSPH_FIELD_ACC && !s->rates_valid)
+            fail(RSPH_ESTATE, "rates are read after rsph_eval_rates");
+        rsph_pool* P = s->pool;
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        const DevArrays& A = P->A;
+        const int d = s->prm.dim;
+        const int w = field_width(field, d);
+        const int64_t o = s->p_off;
+        std::vector<int32_t> id = dl(P, A.id + o, n);
+        std::vector<double> tmp((size_t)n * w);
+        auto soa = [&](double* const* arr) {
+            for (int a = 0; a < d; ++a) {
+                std::vector<double> v = dl(P, arr[a] + o, n);
+                for (int64_t k = 0; k < n; ++k) tmp[(size_t)k * w + a] = v[k];
+            }
+        };
+        auto aos3 = [&](const double* arr) {
+            std::vector<double> v = dl(P, arr + 3 * o, 3 * n);
+            for (int64_t k = 0; k < n; ++k)
+                for (int a = 0; a < d; ++a) tmp[(size_t)k * w + a] = v[3 * k + a];
+        };
+        auto one = [&](const double* arr) {
+            std::vector<double> v = dl(P, arr + o, n);
+            for (int64_t k = 0; k < n; ++k) tmp[k] = v[k];
+        };
+        switch (field) {
+        case RSPH_FIELD_POS: soa(A.pos); break;
+        case RSPH_FIELD_VEL: soa(A.vel); break;
+        case RSPH_FIELD_RHO: one(A.rho); break;
+        case RSPH_FIELD_DRHO: one(A.drho); break;
+        case RSPH_FIELD_MASS: one(A.mass); break;
+        case RSPH_FIELD_P: {
+            std::vector<double> r = dl(P, A.rho + o, n);
+            std::vector<int32_t> ph = dl(P, A.phase + o, n);
+            for (int64_t k = 0; k < n; ++k) tmp[k] = s->sc.c0sq * (r[k] - s->sc.rho0[ph[k]]);
+            break;
+        }
+        case RSPH_FIELD_PHASE: {
+            std::vector<int32_t> ph = dl(P, A.phase + o, n);
+            for (int64_t k = 0; k < n; ++k) tmp[k] = (double)ph[k];
+            break;
+        }
+        case RSPH_FIELD_ACC: aos3(A.r_acc); break;
+        case RSPH_FIELD_ACC_P: aos3(A.r_accp); break;
+        case RSPH_FIELD_ACC_S: aos3(A.r_accs); break;
+        case RSPH_FIELD_ACC_V: aos3(A.r_accv); break;
+        case RSPH_FIELD_GRADC: aos3(A.r_gradc); break;
+        case RSPH_FIELD_DR: aos3(A.r_dr); break;
+        case RSPH_FIELD_RATE_DRHO: one(A.r_drho); break;
+        case RSPH_FIELD_SIGMA: one(A.r_sigma); break;
+        case RSPH_FIELD_B: {
+            std::vector<double> v = dl(P, A.r_b + 9 * o, 9 * n);
+            for (int64_t k = 0; k < n; ++k)
+                for (int q = 0; q < w; ++q) tmp[(size_t)k * w + q] = v[9 * k + q];
+            break;
+        }
+        case RSPH_FIELD_NNB: {
+            std::vector<int32_t> c = dl(P, A.ncount + o, n);
+            for (int64_t k = 0; k < n; ++k) tmp[k] = (double)c[k];
+            break;
+        }
+        }
+        for (int64_t k = 0; k < n; ++k)
+            for (int q = 0; q < w; ++q) out[(size_t)id[k] * w + q] = tmp[(size_t)k * w + q];
+    });
+}
+
+rsph_status rsph_read_binning(rsph_system* s, int64_t n, uint32_t* key, int64_t* rank)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!key || !rank) fail(RSPH_EINVAL, "NULL output");
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        if (n != s->n) fail(RSPH_EINVAL, "n must equal the particle count");
+        rsph_pool* P = s->pool;
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        const int64_t o = s->p_off;
+        std::vector<int32_t> id = dl(P, P->A.id + o, n);
+        std::vector<int32_t> perm = dl(P, P->A.perm + o, n);
+        std::vector<uint32_t> k_old = dl(P, P->A.key, P->A.P);
+        for (int64_t k = 0; k < n; ++k) {
+            key[id[k]] = k_old[perm[k]];
+            rank[id[k]] = k;
+        }
+    });
+}
+
+rsph_status rsph_read_neighbours(rsph_system* s, int64_t n, int64_t cap, int64_t* start, int64_t* idx)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!start || !idx) fail(RSPH_EINVAL, "NULL output");
+        if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
+        if (n != s->n) fail(RSPH_EINVAL, "n must equal the particle count");
+        rsph_pool* P = s->pool;
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        const DevArrays& A = P->A;
+        const int64_t o = s->p_off;
+        std::vector<int32_t> id = dl(P, A.id, A.P);
+        std::vector<int32_t> cnt = dl(P, A.ncount + o, n);
+        const int64_t w0 = o / kWave, w1 = (o + n + kWave - 1) / kWave;
+        std::vector<uint32_t> nb = dl(P, A.nbr + w0 * A.kmax * kWave, (w1 - w0) * A.kmax * kWave);
+        std::vector<int64_t> count(n);
+        for (int64_t k = 0; k < n; ++k) count[id[o + k]] = cnt[k];
+        start[0] = 0;
+        for (int64_t i = 0; i < n; ++i) start[i + 1] = start[i] + count[i];
+        if (start[n] > cap) fail(RSPH_EINVAL, "cap is too small");
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t slot = o + k;
+            const int64_t w = slot / kWave - w0, lane = slot % kWave;
+            const int64_t dst = start[id[slot]];
+            for (int q = 0; q < cnt[k]; ++q)
+                idx[dst + q] = id[nb[(w * A.kmax + q) * kWave + lane]];
+        }
+    });
+}
+
+rsph_status rsph_set_kernel_timing(rsph_system* s, int32_t enable)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        rsph_pool* P = s->pool;
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        collect_timing(P, INT64_MAX);
+        P->timing = enable != 0;
+        for (int k = 0; k < RSPH_KERNEL_COUNT; ++k) {
+            P->t_launches[k] = 0;
+            P->t_ms[k] = 0.0;
+        }
+    });
+}
+
+rsph_status rsph_read_kernel_timing(rsph_system* s, int64_t* launches, double* ms)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (!launches || !ms) fail(RSPH_EINVAL, "NULL output");
+        rsph_pool* P = s->pool;
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        for (int k = 0; k < RSPH_KERNEL_COUNT; ++k) {
+            launches[k] = P->t_launches[k];
+            ms[k] = P->t_ms[k];
+        }
+    });
+}
+
+void rsph_destroy_system(rsph_system* s)
+{
+    if (!s) return;
+    if (s->owns_pool) {
+        destroy_pool(s->pool);
+        delete s;
+        return;
+    }
+    (void)rsph_pool_release(s->pool, s);
+}
+
+// ---- serving ----------------------------------------------------------------
+
+rsph_status rsph_pool_create(int32_t dim, int32_t precision, size_t budget, void* hip_stream, rsph_pool** out)
+{
+    return guarded(nullptr, [&] {
+        if (!out) fail(RSPH_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (dim != 2 && dim != 3) fail(RSPH_EINVAL, "dim must be 2 or 3");
+        if (precision != RSPH_FP64 && precision != RSPH_MIXED) fail(RSPH_EINVAL, "bad precision");
+        rsph_pool* P = new rsph_pool();
+        try {
+            make_pool(P, dim, precision, budget, hip_stream);
+        } catch (...) {
+            destroy_pool(P);
+            throw;
+        }
+        *out = P;
+    });
+}
+
+rsph_status rsph_pool_admit(rsph_pool* P, const rsph_params* params, int64_t n, const double* pos,
+                            const double* vel, const int32_t* phase, const double* mass, rsph_system** out)
+{
+    if (!P) return RSPH_EINVAL;
+    return guarded(&P->err, [&] {
+        if (!out) fail(RSPH_EINVAL, "out is NULL");
+        *out = nullptr;
+        validate_params(params);
+        if (params->dim != P->dim || params->precision != P->precision)
+            fail(RSPH_EINVAL, "system dim and precision must match the pool's");
+        validate_particles(*params, n, pos, vel, phase, mass, nullptr);
+        rsph_system* s = new rsph_system();
+        s->pool = P;
+        s->prm = *params;
+        s->sc = make_const(*params);
+        s->ncells = s->sc.ncells;
+        s->n = n;
+        std::vector<rsph_system*> members = P->systems;
+        members.push_back(s);
+        try {
+            repack(P, members);
+            s->has_particles = true;
+            s->sc.p_n = n;
+            HIPCHECK(hipMemcpy((void*)(P->A.sc + s->row), &s->sc, sizeof(SysConst), hipMemcpyHostToDevice));
+            upload_particles(s, pos, vel, phase, mass, nullptr);
+            reset_dyn(s, false);
+            check_spacing(s);
+        } catch (...) {
+            std::vector<rsph_system*> back(P->systems.begin(), P->systems.end());
+            back.erase(std::remove(back.begin(), back.end(), s), back.end());
+            if (s->row >= 0) {
+                try {
+                    repack(P, back);
+                } catch (...) {
+                }
+            }
+            delete s;
+            throw;
+        }
+        *out = s;
+    });
+}
+
+rsph_status rsph_pool_step(rsph_pool* P, rsph_system* const* systems, const int64_t* n_outer, int32_t count)
+{
+    if (!P) return RSPH_EINVAL;
+    return guarded(&P->err, [&] {
+        if (count < 0 || (count > 0 && (!systems || !n_outer))) fail(RSPH_EINVAL, "bad arguments");
+        std::vector<int64_t> left(P->systems.size(), 0);
+        for (int k = 0; k < count; ++k) {
+            rsph_system* s = systems[k];
+            if (!s || s->pool != P || s->row < 0) fail(RSPH_EINVAL, "system is not in this pool");
+            if (s->faulted) fail(RSPH_ESTATE, "a system of the batch is faulted");
+            if (n_outer[k] < 0) fail(RSPH_EINVAL, "n_outer must be >= 0");
+            left[s->row] += n_outer[k];
+            s->rates_valid = false;
+        }
+        for (;;) {
+            std::vector<int32_t> mask(P->systems.size(), 0);
+            bool any = false;
+            for (size_t r = 0; r < left.size(); ++r)
+                if (left[r] > 0) {
+                    mask[r] = 1;
+                    any = true;
+                }
+            if (!any) break;
+            uint32_t h = outer_step(P, mask);
+            for (size_t r = 0; r < left.size(); ++r)
+                if (left[r] > 0) --left[r];
+            if (h & kFaultBits) {
+                // mark the systems whose own health tripped
+                std::vector<SysDyn> d = read_dyn(P);
+                std::string names;
+                for (size_t r = 0; r < d.size(); ++r)
+                    if (d[r].health & kFaultBits) {
+                        P->systems[r]->faulted = true;
+                        left[r] = 0;
+                        names += " " + std::to_string(r);
+                    }
+                P->err = "health check tripped in pool rows" + names;
+            }
+        }
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        for (int k = 0; k < count; ++k)
+            if (systems[k]->faulted) fail(RSPH_ENUMERIC, P->err);
+    });
+}
+
+size_t rsph_pool_bytes(const rsph_pool* P) { return P ? P->bytes : 0; }
+
+rsph_status rsph_pool_release(rsph_pool* P, rsph_system* s)
+{
+    if (!P || !s) return RSPH_EINVAL;
+    return guarded(&P->err, [&] {
+        if (s->pool != P || s->owns_pool) fail(RSPH_EINVAL, "system is not in this pool");
+        std::vector<rsph_system*> members;
+        for (auto* m : P->systems)
+            if (m != s) members.push_back(m);
+        repack(P, members);
+        delete s;
+    });
+}
+
+void rsph_pool_destroy(rsph_pool* P)
+{
+    if (!P) return;
+    for (auto* s : P->systems) delete s;
+    P->systems.clear();
+    destroy_pool(P);
+}
+
+}  // extern "C"

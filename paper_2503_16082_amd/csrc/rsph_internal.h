@@ -1,0 +1,186 @@
+// rsph_internal.h -- device-side data layout shared by the HIP kernels and the
+// host side of librsph.so.  Not part of the C-ABI.
+//
+// Layout (all systems of a pool packed in one set of arrays):
+//  * particles live in "slots"; each system owns a contiguous slot range that
+//    starts on a multiple of 64, so a wavefront never spans two systems and the
+//    per-wave table wave_sys[] gives the system of every lane;
+//  * within a system's range particles are sorted by cell key, ties by the
+//    caller's particle index (a deterministic, bit-exact order);
+//  * FP64 state is structure-of-arrays; the inputs of the pair loops are packed
+//    per particle into 4-wide records (float4 in the mixed form, double4 in the
+//    FP64 form) so that one neighbour gather is one or two 16-byte loads;
+//  * neighbour lists are stored per wavefront, transposed: entry k of lane l of
+//    wave w is nbr[(w * kmax + k) * 64 + l], so the 64 lanes of a wave read 256
+//    contiguous bytes at every step k.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsph {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lattice)
+constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
+constexpr int kMaxCellsPerAxis = 1024;
+
+// method switches (mirror of the public RSPH_* flags)
+constexpr uint32_t kNoPenalty = 1u;
+constexpr uint32_t kNoShift = 2u;
+constexpr uint32_t kNoDensitySummation = 4u;
+constexpr uint32_t kGbarSingleField = 8u;
+constexpr uint32_t kPenaltyR3 = 16u;
+constexpr uint32_t kNoSurface = 32u;
+
+// health bits (mirror of RSPH_HEALTH_*)
+constexpr uint32_t kHealthNonFinite = 1u;
+constexpr uint32_t kHealthDensity = 2u;
+constexpr uint32_t kHealthNeighbours = 4u;
+constexpr uint32_t kHealthCoincident = 8u;
+constexpr uint32_t kHealthClose = 16u;  // two particles closer than 1e-3 dp (input check only)
+constexpr uint32_t kHealthDtCollapse = 32u;  // acoustic step below 1e-12 of its no-flow value
+constexpr int64_t kMaxCells = 2048LL * 2048LL;  // capacity of the three-phase scan
+
+// per-particle flag bits, rebuilt every advection step
+constexpr uint8_t kFlagInterface = 1;  // has a neighbour of the other fluid
+constexpr uint8_t kFlagNearInterface = 2;  // itself or a neighbour has kFlagInterface
+
+// Per-system constants, device resident, read-only inside the kernels.
+struct SysConst {
+    int32_t dim;
+    uint32_t flags;
+    int32_t ncell[3];
+    int32_t pad0;
+    int64_t p_off;   // first slot
+    int64_t p_n;     // particles
+    int64_t c_off;   // first global cell
+    int64_t ncells;
+    double box[3];
+    double half_box[3];
+    double inv_cell[3];  // ncell / box
+    double cell[3];      // box / ncell
+    double h;
+    double inv_h;
+    double cut2;       // (2h)^2
+    double w_alpha;    // kernel normalisation
+    double w0;         // W(0)
+    double dw_coef;    // -5 alpha / h
+    double sigma0;     // lattice kernel sum (self included)
+    double rho0[2];
+    double eta[2];
+    double c0;
+    double inv_c0;
+    double c0sq;
+    double gamma;
+    double xi;
+    double alpha_h2;   // alpha h^2 of Eq. 14
+    double cfl_ad;
+    double cfl_ac;
+    double dtad_visc[2];  // cfl_ad rho0 h^2 / eta (inf if eta = 0)
+    double dtac_surf[2];  // cfl_ac sqrt(rho0 h^3 / (2 pi gamma)) (inf if gamma = 0)
+    double grav[3];
+    double coincident2;   // (1e-9 h)^2
+    double close2;        // (1e-3 dp)^2
+};
+
+// Per-system dynamic scalars, device resident.
+struct SysDyn {
+    double dt_ad;
+    double tau;
+    double t;
+    double dt[2];                    // substep parity slots
+    double vmax[2];                  // per fluid, of the last velocity update
+    unsigned long long vmax_acc[2];  // atomic max of |v| bit patterns (non-negative doubles)
+    int32_t active[2];               // substep parity slots
+    int32_t stepping;                // 1 while the system takes part in the current advection step
+    uint32_t health;
+    long long n_sub;
+    long long n_outer;
+    double dt_last;
+};
+
+struct DevArrays {
+    int64_t P;       // slot capacity (multiple of 256)
+    int64_t C;       // global cell capacity
+    int32_t kmax;
+    int32_t mode;    // 0 = step, 1 = evaluate rates only
+    // FP64 state, structure of arrays
+    double* pos[3];
+    double* vel[3];
+    double* rho;
+    double* drho;
+    double* mass;
+    int32_t* id;
+    int32_t* phase;
+    // second copy for the counting sort
+    double* pos2[3];
+    double* vel2[3];
+    double* rho2;
+    double* drho2;
+    double* mass2;
+    int32_t* id2;
+    int32_t* phase2;
+    // binning
+    uint32_t* key;
+    int32_t* rank;
+    int32_t* perm;
+    int32_t* cell_cnt;
+    int32_t* cell_start;  // C + 1
+    int32_t* cell_sys;
+    int32_t* scan_part;
+    int32_t* wave_sys;
+    // pair-loop inputs (float4 or double4 records)
+    void* geo;     // frozen positions + tag
+    void* vbuf[2]; // velocity, substep parity
+    void* th[2];   // {rho, V, p, 0}, substep parity
+    void* col;     // {grad C, 1/|grad C|}
+    void* av;      // viscous acceleration
+    void* bm[2];   // correction matrix, 6 unique entries
+    uint8_t* flags;
+    uint32_t* nbr;
+    int32_t* ncount;
+    // rates written by an evaluation (FP64, slot order)
+    double* r_acc;    // 3 * P
+    double* r_accp;
+    double* r_accs;
+    double* r_accv;
+    double* r_gradc;
+    double* r_drho;   // P
+    double* r_b;      // 9 * P
+    double* r_dr;     // 3 * P
+    double* r_sigma;  // P
+    // observables partials
+    double* obs_part;
+    double* obs_out;
+    // system tables
+    const SysConst* sc;
+    SysDyn* sd;
+    int32_t nsys;
+};
+
+// host-callable launchers (rsph_kernels.hip)
+struct Launch {
+    hipStream_t stream;
+    int dim;
+    int fp64;  // 1: FP64 pair loops, 0: mixed
+};
+
+void launch_bin(const Launch& L, DevArrays& A, int64_t ncells_total);
+void launch_neighbours(const Launch& L, const DevArrays& A);
+void launch_dt_advection(const Launch& L, const DevArrays& A);
+void launch_advection(const Launch& L, const DevArrays& A);
+void launch_shift(const Launch& L, const DevArrays& A);
+void launch_colour(const Launch& L, const DevArrays& A, int slot);
+void launch_force(const Launch& L, const DevArrays& A, int slot);
+void launch_dt_substep(const Launch& L, const DevArrays& A, int slot);
+void launch_continuity(const Launch& L, const DevArrays& A, int slot);
+void launch_observables(const Launch& L, const DevArrays& A, int64_t nwaves_used);
+void launch_any_active(const Launch& L, const DevArrays& A, int slot, int32_t* out);
+void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask);
+
+constexpr int kObsPart = 16;  // partial sums per wave and pass
+constexpr int kObsOut = 32;   // reduced values per system
+
+}  // namespace rsph

@@ -1,0 +1,1286 @@
+// rsph_kernels.hip -- HIP kernels for gfx950 (CDNA4) of the Riemann-SPH
+// multiphase surface-tension method (arXiv 2503.16082).
+//
+// One thread per particle slot, wave64, 256-thread blocks.  Blocks are remapped
+// so that each of the 8 XCDs works on one contiguous eighth of the slot range:
+// particles are cell-sorted, so neighbour gathers of a block mostly hit the L2
+// of its own XCD.  Pair loops gather-only: every particle sums its own
+// neighbours in a fixed order, so results are deterministic and no floating
+// point atomics are used (the only atomics are integer cell counters, an
+// integer max over |v| bit patterns and health bits).
+//
+// Precision forms: R = double (FP64 form) or R = float (mixed form: FP32 pair
+// arithmetic on split positions, FP64 state updates).  D = 2 or 3.
+#include <math.h>
+
+#include <utility>
+
+#include "rsph_internal.h"
+
+namespace rsph {
+
+template <typename R>
+struct alignas(4 * sizeof(R)) Q4 {
+    R x, y, z, w;
+};
+
+// ---------------------------------------------------------------------------
+// indexing helpers
+// ---------------------------------------------------------------------------
+
+// Consecutive logical blocks on the same XCD (workgroups are dispatched
+// round-robin over the 8 XCDs); gridDim.x is a multiple of 8.
+__device__ __forceinline__ int64_t logical_block()
+{
+    const int64_t per = gridDim.x >> 3;
+    const int64_t b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
+
+struct Slot {
+    int64_t i;   // slot index
+    int s;       // system (wave-uniform), -1 if none
+    bool lane;   // slot holds a particle
+};
+
+__device__ __forceinline__ Slot slot_of(const DevArrays& A)
+{
+    Slot c;
+    c.i = logical_block() * kBlock + threadIdx.x;
+    c.s = -1;
+    c.lane = false;
+    if (c.i >= A.P) return c;
+    int s = A.wave_sys[c.i >> 6];
+    s = __builtin_amdgcn_readfirstlane(s);
+    c.s = s;
+    if (s < 0) return c;
+    const SysConst& S = A.sc[s];
+    c.lane = c.i < S.p_off + S.p_n;
+    return c;
+}
+
+__device__ __forceinline__ uint32_t nbr_at(const DevArrays& A, int64_t i, int k)
+{
+    const int64_t w = i >> 6;
+    return A.nbr[(w * A.kmax + k) * kWave + (i & 63)];
+}
+
+// ---------------------------------------------------------------------------
+// kernel function (Wendland C2): W = alpha (1 - q/2)^4 (1 + 2q), q = r/h < 2
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R wendland_dw(R q, R coef)
+{
+    R a = R(1) - R(0.5) * q;
+    return coef * q * a * a * a;  // coef = -5 alpha / h
+}
+
+__device__ __forceinline__ double wendland_w(double q, double alpha)
+{
+    double a = 1.0 - 0.5 * q;
+    return alpha * a * a * a * a * (1.0 + 2.0 * q);
+}
+
+// ---------------------------------------------------------------------------
+// frozen geometry records
+//   FP64: {x, y, z, phase}
+//   mixed: {x - cx*cell, y - cy*cell, z - cz*cell, bits(cx | cy<<10 | cz<<20 | phase<<31)}
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct Geo;
+
+template <>
+struct Geo<double> {
+    __device__ static Q4<double> make(const double* x, int ph, const SysConst& S, const int* c)
+    {
+        (void)S;
+        (void)c;
+        return Q4<double>{x[0], x[1], x[2], (double)ph};
+    }
+    __device__ static int phase(const Q4<double>& g) { return (int)g.w; }
+    template <int D>
+    __device__ static void rij(const Q4<double>& gi, const Q4<double>& gj, const SysConst& S,
+                               const double* cellr, double* r)
+    {
+        (void)cellr;
+        double d = gi.x - gj.x;
+        if (d > S.half_box[0]) d -= S.box[0];
+        else if (d < -S.half_box[0]) d += S.box[0];
+        r[0] = d;
+        d = gi.y - gj.y;
+        if (d > S.half_box[1]) d -= S.box[1];
+        else if (d < -S.half_box[1]) d += S.box[1];
+        r[1] = d;
+        if (D == 3) {
+            d = gi.z - gj.z;
+            if (d > S.half_box[2]) d -= S.box[2];
+            else if (d < -S.half_box[2]) d += S.box[2];
+            r[2] = d;
+        } else {
+            r[2] = 0.0;
+        }
+    }
+};
+
+template <>
+struct Geo<float> {
+    __device__ static Q4<float> make(const double* x, int ph, const SysConst& S, const int* c)
+    {
+        float o[3];
+        for (int a = 0; a < 3; ++a) o[a] = (float)(x[a] - (double)c[a] * S.cell[a]);
+        uint32_t tag = (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20) |
+                       ((uint32_t)ph << 31);
+        return Q4<float>{o[0], o[1], o[2], __uint_as_float(tag)};
+    }
+    __device__ static int phase(const Q4<float>& g) { return (int)(__float_as_uint(g.w) >> 31); }
+    template <int D>
+    __device__ static void rij(const Q4<float>& gi, const Q4<float>& gj, const SysConst& S,
+                               const float* cellr, float* r)
+    {
+        const uint32_t ti = __float_as_uint(gi.w), tj = __float_as_uint(gj.w);
+        int dc = (int)(ti & 1023u) - (int)(tj & 1023u);
+        if (dc > 1) dc -= S.ncell[0];
+        else if (dc < -1) dc += S.ncell[0];
+        r[0] = (gi.x - gj.x) + (float)dc * cellr[0];
+        dc = (int)((ti >> 10) & 1023u) - (int)((tj >> 10) & 1023u);
+        if (dc > 1) dc -= S.ncell[1];
+        else if (dc < -1) dc += S.ncell[1];
+        r[1] = (gi.y - gj.y) + (float)dc * cellr[1];
+        if (D == 3) {
+            dc = (int)((ti >> 20) & 1023u) - (int)((tj >> 20) & 1023u);
+            if (dc > 1) dc -= S.ncell[2];
+            else if (dc < -1) dc += S.ncell[2];
+            r[2] = (gi.z - gj.z) + (float)dc * cellr[2];
+        } else {
+            r[2] = 0.0f;
+        }
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_r(R x);
+template <>
+__device__ __forceinline__ double rsqrt_r<double>(double x) { return rsqrt(x); }
+template <>
+__device__ __forceinline__ float rsqrt_r<float>(float x) { return rsqrtf(x); }
+
+template <typename R>
+__device__ __forceinline__ R recip(R x);
+template <>
+__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __frcp_rn(x); }
+
+__device__ __forceinline__ int cell_of(double x, const SysConst& S, int a)
+{
+    int64_t k = (int64_t)floor(__dmul_rn(x, S.inv_cell[a]));
+    if (k < 0) k = 0;
+    if (k > S.ncell[a] - 1) k = S.ncell[a] - 1;
+    return (int)k;
+}
+
+// wave-wide max of non-negative doubles through their bit patterns
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void flag_health(SysDyn& D, uint32_t bits)
+{
+    atomicOr(&D.health, bits);
+}
+
+// ---------------------------------------------------------------------------
+// binning: cell key, counting sort (histogram, scan, scatter), ordering of
+// each cell by the caller's particle index, gather of the state
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* p, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_key(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    if (!A.sd[c.s].stepping) return;
+    const SysConst& S = A.sc[c.s];
+    int ck[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+        double x = A.pos[a][c.i];
+        if (x < 0.0) x = __dadd_rn(x, S.box[a]);
+        if (x >= S.box[a]) x = __dsub_rn(x, S.box[a]);
+        A.pos[a][c.i] = x;
+        ck[a] = cell_of(x, S, a);
+    }
+    uint32_t key = (uint32_t)(ck[0] + S.ncell[0] * (ck[1] + S.ncell[1] * ck[2]));
+    A.key[c.i] = key;
+    A.rank[c.i] = atomicAdd(&A.cell_cnt[S.c_off + key], 1);
+}
+
+// exclusive scan of cell_cnt[0..n) into cell_start[0..n], three phases
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total)
+{
+    // wave inclusive scan by shuffles, then across the 4 waves
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wv] = x;
+    __syncthreads();
+    int off = 0;
+    for (int k = 0; k < wv; ++k) off += lds[k];
+    total = lds[0] + lds[1] + lds[2] + lds[3];
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* in, int64_t n, int32_t* part)
+{
+    __shared__ int lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + (int64_t)k * kBlock + threadIdx.x;
+        if (idx < n) s += in[idx];
+    }
+    int total;
+    block_exclusive_scan(s, lds, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the tile totals (at most kScanTile of them)
+__global__ __launch_bounds__(kBlock) void k_scan_partials(int32_t* part, int64_t nparts)
+{
+    __shared__ int lds[4];
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = (int64_t)threadIdx.x * kScanItems + k;
+        v[k] = idx < nparts ? part[idx] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, lds, total);
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = (int64_t)threadIdx.x * kScanItems + k;
+        if (idx < nparts) part[idx] = ex;
+        ex += v[k];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t* in, int64_t n,
+                                                       const int32_t* part, int32_t* out)
+{
+    __shared__ int lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k;
+        v[k] = idx < n ? in[idx] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, lds, total) + part[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k;
+        if (idx < n) out[idx] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = ex;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    const SysConst& S = A.sc[c.s];
+    if (!A.sd[c.s].stepping) {
+        A.perm[c.i] = (int32_t)c.i;  // frozen system: identity
+        return;
+    }
+    const uint32_t key = A.key[c.i];
+    const int64_t dest = S.p_off + (A.cell_start[S.c_off + key] - A.cell_start[S.c_off]) + A.rank[c.i];
+    A.perm[dest] = (int32_t)c.i;
+}
+
+// Orders each cell's slots by the caller's particle index (insertion sort; cells
+// hold ~7 particles in 2D and ~18 in 3D).  One thread per global cell.
+__global__ __launch_bounds__(kBlock) void k_cellsort(DevArrays A, int64_t ncells)
+{
+    int64_t gc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gc >= ncells) return;
+    int s = A.cell_sys[gc];
+    if (s < 0) return;
+    if (!A.sd[s].stepping) return;
+    const SysConst& S = A.sc[s];
+    const int64_t base = S.p_off - A.cell_start[S.c_off];
+    const int64_t b = base + A.cell_start[gc], e = base + A.cell_start[gc + 1];
+    constexpr int kLocal = 48;
+    if (e - b <= kLocal) {
+        int32_t sl[kLocal];
+        int32_t id[kLocal];
+        int m = (int)(e - b);
+        for (int k = 0; k < m; ++k) {
+            int32_t v = A.perm[b + k];
+            int32_t key = A.id[v];
+            int q = k;
+            while (q > 0 && id[q - 1] > key) {
+                id[q] = id[q - 1];
+                sl[q] = sl[q - 1];
+                --q;
+            }
+            id[q] = key;
+            sl[q] = v;
+        }
+        for (int k = 0; k < m; ++k) A.perm[b + k] = sl[k];
+    } else {
+        for (int64_t k = b + 1; k < e; ++k) {
+            int32_t v = A.perm[k];
+            int32_t key = A.id[v];
+            int64_t q = k;
+            while (q > b && A.id[A.perm[q - 1]] > key) {
+                A.perm[q] = A.perm[q - 1];
+                --q;
+            }
+            A.perm[q] = v;
+        }
+    }
+}
+
+// state gather into the second buffer, plus the per-fluid |v| max for the
+// advection time step
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (c.s < 0) return;
+    unsigned long long m0 = 0, m1 = 0;
+    const bool stepping = A.sd[c.s].stepping;
+    if (c.lane) {
+        const int64_t src = A.perm[c.i];
+        double v2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            A.pos2[a][c.i] = A.pos[a][src];
+            double v = A.vel[a][src];
+            A.vel2[a][c.i] = v;
+            v2 += v * v;
+        }
+        A.rho2[c.i] = A.rho[src];
+        A.drho2[c.i] = A.drho[src];
+        A.mass2[c.i] = A.mass[src];
+        A.id2[c.i] = A.id[src];
+        const int ph = A.phase[src];
+        A.phase2[c.i] = ph;
+        unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
+        if (ph == 0) m0 = bits;
+        else m1 = bits;
+    }
+    if (!stepping) return;  // wave-uniform
+    m0 = wave_max_u64(m0);
+    m1 = wave_max_u64(m1);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&A.sd[c.s].vmax_acc[0], m0);
+        atomicMax(&A.sd[c.s].vmax_acc[1], m1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// neighbour lists (frozen geometry of section 3.3), density summation, and the
+// per-particle inputs of the pair loops
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    SysDyn& Dy = A.sd[c.s];
+    if (!Dy.stepping) return;
+    const SysConst& S = A.sc[c.s];
+    const int64_t i = c.i;
+    const int64_t base = S.p_off - A.cell_start[S.c_off];
+    double xi[3] = {0.0, 0.0, 0.0};
+    int ci[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+        xi[a] = A.pos[a][i];
+        ci[a] = cell_of(xi[a], S, a);
+    }
+    const int ph = A.phase[i];
+    int cnt = 0;
+    bool cross = false, coincident = false, close = false;
+    double wsum = 0.0;
+    uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
+    const int zr = D == 3 ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz) {
+        int cz = ci[2] + dz;
+        double kz = 0.0;
+        if (D == 3) {
+            if (cz < 0) { cz += S.ncell[2]; kz = -S.box[2]; }
+            else if (cz >= S.ncell[2]) { cz -= S.ncell[2]; kz = S.box[2]; }
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int cy = ci[1] + dy;
+            double ky = 0.0;
+            if (cy < 0) { cy += S.ncell[1]; ky = -S.box[1]; }
+            else if (cy >= S.ncell[1]) { cy -= S.ncell[1]; ky = S.box[1]; }
+            for (int dx = -1; dx <= 1; ++dx) {
+                int cx = ci[0] + dx;
+                double kx = 0.0;
+                if (cx < 0) { cx += S.ncell[0]; kx = -S.box[0]; }
+                else if (cx >= S.ncell[0]) { cx -= S.ncell[0]; kx = S.box[0]; }
+                const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
+                const int64_t jb = base + A.cell_start[gc], je = base + A.cell_start[gc + 1];
+                for (int64_t j = jb; j < je; ++j) {
+                    if (j == i) continue;
+                    // the neighbour predicate, one rounding per operation: the
+                    // image shift is the periodic wrap of the stencil cell
+                    // (the minimum image for every pair closer than 2h)
+                    // x_i - x_j, then minus the image shift, squares summed in axis order
+                    double d = __dsub_rn(xi[0], A.pos[0][j]);
+                    if (kx != 0.0) d = __dsub_rn(d, kx);
+                    double r2 = __dmul_rn(d, d);
+                    d = __dsub_rn(xi[1], A.pos[1][j]);
+                    if (ky != 0.0) d = __dsub_rn(d, ky);
+                    r2 = __dadd_rn(r2, __dmul_rn(d, d));
+                    if (D == 3) {
+                        d = __dsub_rn(xi[2], A.pos[2][j]);
+                        if (kz != 0.0) d = __dsub_rn(d, kz);
+                        r2 = __dadd_rn(r2, __dmul_rn(d, d));
+                    }
+                    if (r2 < S.cut2) {
+                        if (cnt < A.kmax) out[(int64_t)cnt * kWave] = (uint32_t)j;
+                        ++cnt;
+                        wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
+                        cross |= A.phase[j] != ph;
+                        coincident |= r2 < S.coincident2;
+                        close |= r2 < S.close2;
+                    }
+                }
+            }
+        }
+    }
+    if (cnt > A.kmax) {
+        flag_health(Dy, kHealthNeighbours);
+        cnt = A.kmax;
+    }
+    if (coincident) flag_health(Dy, kHealthCoincident);
+    if (close) flag_health(Dy, kHealthClose);
+    A.ncount[i] = cnt;
+    A.flags[i] = cross ? kFlagInterface : 0;
+    const double sigma = S.w0 + wsum;
+    double rho = A.rho[i];
+    if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
+        rho = S.rho0[ph] * sigma / S.sigma0;
+        A.rho[i] = rho;
+    }
+    if (A.mode == 1) {
+        A.r_sigma[i] = sigma;
+        for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
+    }
+    const double V = A.mass[i] / rho;
+    const double p = S.c0sq * (rho - S.rho0[ph]);
+    Q4<R>* th = (Q4<R>*)A.th[1];
+    th[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
+    Q4<R>* vb = (Q4<R>*)A.vbuf[0];
+    vb[i] = Q4<R>{(R)A.vel[0][i], (R)A.vel[1][i], D == 3 ? (R)A.vel[2][i] : (R)0, (R)0};
+    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, S, ci);
+    ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
+}
+
+// ---------------------------------------------------------------------------
+// advection-step pair pass 1: viscous acceleration (Eq. 13), correction matrix
+// (Eq. 15), near-interface flag
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    if (!A.sd[c.s].stepping) return;
+    const SysConst& S = A.sc[c.s];
+    const int64_t i = c.i;
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* th = (const Q4<R>*)A.th[1];
+    const Q4<R>* vb = (const Q4<R>*)A.vbuf[0];
+    R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
+    const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
+    const Q4<R> gi = geo[i];
+    const Q4<R> vi = vb[i];
+    const int phi = Geo<R>::phase(gi);
+    const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
+    const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
+    R av[3] = {0, 0, 0};
+    R M[6] = {0, 0, 0, 0, 0, 0};  // 00 01 02 11 12 22
+    uint8_t near = A.flags[i] & kFlagInterface;
+    const int cnt = A.ncount[i];
+    for (int k = 0; k < cnt; ++k) {
+        const uint32_t j = nbr_at(A, i, k);
+        const Q4<R> gj = geo[j];
+        R r[3];
+        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const R inv_r = rsqrt_r<R>(r2);
+        const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
+        const R Vj = th[j].y;
+        const Q4<R> vj = vb[j];
+        const R eta_j = Geo<R>::phase(gj) == phi ? eta_i : eta_o;
+        const R es = eta_i + eta_j;
+        const R eta_bar = es > R(0) ? R(2) * eta_i * eta_j / es : R(0);
+        const R f = eta_bar * dW * inv_r * Vj;
+        av[0] += f * (vi.x - vj.x);
+        av[1] += f * (vi.y - vj.y);
+        if (D == 3) av[2] += f * (vi.z - vj.z);
+        const R g = dW * Vj * inv_r;
+        M[0] += g * r[0] * r[0];
+        M[1] += g * r[0] * r[1];
+        M[3] += g * r[1] * r[1];
+        if (D == 3) {
+            M[2] += g * r[0] * r[2];
+            M[4] += g * r[1] * r[2];
+            M[5] += g * r[2] * r[2];
+        }
+        near |= A.flags[j] & kFlagInterface;
+    }
+    const R two_over_rho = R(2) / th[i].x;
+    Q4<R> a4{two_over_rho * av[0], two_over_rho * av[1], two_over_rho * av[2], (R)0};
+    ((Q4<R>*)A.av)[i] = a4;
+    // B = -M^{-1} (M is symmetric)
+    R B[6];
+    if (D == 2) {
+        const R det = M[0] * M[3] - M[1] * M[1];
+        if (det != R(0) && isfinite((double)det)) {
+            B[0] = -M[3] / det;
+            B[1] = M[1] / det;
+            B[3] = -M[0] / det;
+        } else {
+            B[0] = R(1);
+            B[1] = R(0);
+            B[3] = R(1);
+        }
+        B[2] = B[4] = R(0);
+        B[5] = R(0);
+    } else {
+        const R c00 = M[3] * M[5] - M[4] * M[4];
+        const R c01 = M[2] * M[4] - M[1] * M[5];
+        const R c02 = M[1] * M[4] - M[2] * M[3];
+        const R c11 = M[0] * M[5] - M[2] * M[2];
+        const R c12 = M[1] * M[2] - M[0] * M[4];
+        const R c22 = M[0] * M[3] - M[1] * M[1];
+        const R det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+        if (det != R(0) && isfinite((double)det)) {
+            const R s = R(-1) / det;
+            B[0] = s * c00;
+            B[1] = s * c01;
+            B[2] = s * c02;
+            B[3] = s * c11;
+            B[4] = s * c12;
+            B[5] = s * c22;
+        } else {
+            B[0] = B[3] = B[5] = R(1);
+            B[1] = B[2] = B[4] = R(0);
+        }
+    }
+    ((Q4<R>*)A.bm[0])[i] = Q4<R>{B[0], B[1], B[2], B[3]};
+    ((Q4<R>*)A.bm[1])[i] = Q4<R>{B[4], B[5], (R)0, (R)0};
+    A.flags[i] = (A.flags[i] & kFlagInterface) | (near ? kFlagNearInterface : 0);
+    if (A.mode == 1) {
+        for (int a = 0; a < 3; ++a) A.r_accv[3 * i + a] = a < D ? (double)(&a4.x)[a] : 0.0;
+        const R full[9] = {B[0], B[1], B[2], B[1], B[3], B[4], B[2], B[4], B[5]};
+        for (int q = 0; q < 9; ++q) A.r_b[9 * i + q] = 0.0;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) A.r_b[9 * i + a * D + b] = (double)full[a * 3 + b];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// advection-step pair pass 2: position correction (Eq. 14), then the first
+// half-step of substep 0 (density, pressure by Eq. 3, position)
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    SysDyn& Dy = A.sd[c.s];
+    if (!Dy.stepping) return;
+    const SysConst& S = A.sc[c.s];
+    const int64_t i = c.i;
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* th = (const Q4<R>*)A.th[1];
+    const Q4<R>* b0 = (const Q4<R>*)A.bm[0];
+    const Q4<R>* b1 = (const Q4<R>*)A.bm[1];
+    R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
+    const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
+    const Q4<R> gi = geo[i];
+    const Q4<R> Bi0 = b0[i], Bi1 = b1[i];
+    R s[3] = {0, 0, 0};
+    const int cnt = A.ncount[i];
+    for (int k = 0; k < cnt; ++k) {
+        const uint32_t j = nbr_at(A, i, k);
+        const Q4<R> gj = geo[j];
+        R r[3];
+        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const R inv_r = rsqrt_r<R>(r2);
+        const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * th[j].y * inv_r;  // dW V_j / r
+        const Q4<R> Bj0 = b0[j], Bj1 = b1[j];
+        // (B_i + B_j) r_ij, symmetric storage 00 01 02 11 12 22
+        const R m00 = Bi0.x + Bj0.x, m01 = Bi0.y + Bj0.y, m11 = Bi0.w + Bj0.w;
+        if (D == 2) {
+            s[0] += f * (m00 * r[0] + m01 * r[1]);
+            s[1] += f * (m01 * r[0] + m11 * r[1]);
+        } else {
+            const R m02 = Bi0.z + Bj0.z, m12 = Bi1.x + Bj1.x, m22 = Bi1.y + Bj1.y;
+            s[0] += f * (m00 * r[0] + m01 * r[1] + m02 * r[2]);
+            s[1] += f * (m01 * r[0] + m11 * r[1] + m12 * r[2]);
+            s[2] += f * (m02 * r[0] + m12 * r[1] + m22 * r[2]);
+        }
+    }
+    double dr[3];
+    for (int a = 0; a < 3; ++a) dr[a] = a < D ? -S.alpha_h2 * (double)s[a] : 0.0;
+    Q4<R>* th0 = (Q4<R>*)A.th[0];
+    if (A.mode == 1) {
+        for (int a = 0; a < 3; ++a) A.r_dr[3 * i + a] = dr[a];
+        th0[i] = th[i];
+        return;
+    }
+    if (!(S.flags & kNoShift))
+        for (int a = 0; a < D; ++a) A.pos[a][i] += dr[a];
+    // first half of substep 0
+    const double dt = Dy.dt[0];
+    const int ph = A.phase[i];
+    const double rho = A.rho[i] + 0.5 * dt * A.drho[i];
+    for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt * A.vel[a][i];
+    A.rho[i] = rho;
+    th0[i] = Q4<R>{(R)rho, (R)(A.mass[i] / rho), (R)(S.c0sq * (rho - S.rho0[ph])), (R)0};
+}
+
+// ---------------------------------------------------------------------------
+// time steps (Eqs. 16-18), one thread per system
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double dt_acoustic(const SysConst& S, const double* vmax)
+{
+    double dt = INFINITY;
+    for (int f = 0; f < 2; ++f)
+        dt = fmin(dt, fmin(S.cfl_ac * (S.h / (S.c0 + vmax[f])), S.dtac_surf[f]));
+    return dt;
+}
+
+__global__ void k_dt_advection(DevArrays A)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nsys) return;
+    SysDyn& D = A.sd[s];
+    const SysConst& S = A.sc[s];
+    if (!D.stepping) {
+        D.active[0] = D.active[1] = 0;
+        return;
+    }
+    double vmax[2];
+    for (int f = 0; f < 2; ++f) {
+        vmax[f] = __longlong_as_double((long long)D.vmax_acc[f]);
+        D.vmax[f] = vmax[f];
+        D.vmax_acc[f] = 0ull;
+    }
+    double dt_ad = INFINITY;
+    for (int f = 0; f < 2; ++f) {
+        double a = vmax[f] > 0.0 ? S.h / vmax[f] : INFINITY;
+        dt_ad = fmin(dt_ad, fmin(S.cfl_ad * a, S.dtad_visc[f]));
+    }
+    const double dt_ac = dt_acoustic(S, vmax);
+    // no motion and no viscosity: one acoustic step spans the advection step
+    if (!isfinite(dt_ad)) dt_ad = dt_ac;
+    D.dt_ad = dt_ad;
+    D.tau = 0.0;
+    D.dt[0] = fmin(dt_ac, dt_ad);
+    D.active[0] = 1;
+    D.active[1] = 0;
+    if (!(dt_ac > 1e-12 * S.cfl_ac * S.h * S.inv_c0) || !(dt_ad > 0.0)) {
+        atomicOr(&D.health, kHealthDtCollapse);
+        D.active[0] = 0;
+    }
+}
+
+__global__ void k_dt_substep(DevArrays A, int slot)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nsys) return;
+    SysDyn& D = A.sd[s];
+    const SysConst& S = A.sc[s];
+    if (!D.active[slot]) {
+        D.active[slot ^ 1] = 0;
+        return;
+    }
+    const double dt = D.dt[slot];
+    D.tau += dt;
+    D.t += dt;
+    D.n_sub += 1;
+    D.dt_last = dt;
+    double vmax[2];
+    for (int f = 0; f < 2; ++f) {
+        vmax[f] = __longlong_as_double((long long)D.vmax_acc[f]);
+        D.vmax[f] = vmax[f];
+        D.vmax_acc[f] = 0ull;
+    }
+    const double dt_ac = dt_acoustic(S, vmax);
+    if (!(dt_ac > 1e-12 * S.cfl_ac * S.h * S.inv_c0)) {
+        // time-step collapse (or NaN): stop this system, the host reports a fault
+        atomicOr(&D.health, kHealthDtCollapse);
+        D.active[slot ^ 1] = 0;
+    } else if (D.tau < D.dt_ad * (1.0 - 1e-12)) {
+        D.dt[slot ^ 1] = fmin(dt_ac, D.dt_ad - D.tau);
+        D.active[slot ^ 1] = 1;
+    } else {
+        D.active[slot ^ 1] = 0;
+        D.n_outer += 1;
+    }
+}
+
+__global__ void k_set_stepping(DevArrays A, const int32_t* mask)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < A.nsys) A.sd[s].stepping = mask[s];
+}
+
+__global__ void k_any_active(DevArrays A, int slot, int32_t* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t any = 0;
+    uint32_t health = 0;
+    for (int s = 0; s < A.nsys; ++s) {
+        any |= A.sd[s].active[slot];
+        health |= A.sd[s].health;
+    }
+    out[0] = any;
+    out[1] = (int32_t)health;
+}
+
+// ---------------------------------------------------------------------------
+// substep pair pass 1: colour gradient (Eq. 22) of interface particles
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_colour(DevArrays A, int slot)
+{
+    Slot c = slot_of(A);
+    if (c.s < 0) return;
+    if (!A.sd[c.s].active[slot] && A.mode == 0) return;
+    if (!c.lane) return;
+    const int64_t i = c.i;
+    if (!(A.flags[i] & kFlagInterface)) return;
+    const SysConst& S = A.sc[c.s];
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* th = (const Q4<R>*)A.th[slot];
+    R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
+    const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
+    const Q4<R> gi = geo[i];
+    const int phi = Geo<R>::phase(gi);
+    // 2 phi_i = 2 rho0_i / (rho0_i + rho0_j) for a neighbour of the other fluid
+    const R two_phi = (R)(2.0 * S.rho0[phi] / (S.rho0[0] + S.rho0[1]));
+    R g[3] = {0, 0, 0};
+    const int cnt = A.ncount[i];
+    for (int k = 0; k < cnt; ++k) {
+        const uint32_t j = nbr_at(A, i, k);
+        const Q4<R> gj = geo[j];
+        if (Geo<R>::phase(gj) == phi) continue;
+        R r[3];
+        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const R inv_r = rsqrt_r<R>(r2);
+        const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * th[j].y * inv_r;
+        g[0] += f * r[0];
+        g[1] += f * r[1];
+        if (D == 3) g[2] += f * r[2];
+    }
+    for (int a = 0; a < D; ++a) g[a] *= two_phi;
+    const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const R invg = gg > R(0) ? rsqrt_r<R>(gg) : R(0);
+    ((Q4<R>*)A.col)[i] = Q4<R>{g[0], g[1], g[2], invg};
+    if (A.mode == 1)
+        for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = a < D ? (double)g[a] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// substep pair pass 2: Riemann pressure (Eqs. 7-12), surface stress divergence
+// with the projected penalty (Eqs. 24, 27, 30, 33), kick
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_force(DevArrays A, int slot)
+{
+    Slot c = slot_of(A);
+    if (c.s < 0) return;
+    SysDyn& Dy = A.sd[c.s];
+    if (A.mode == 0 && !Dy.active[slot]) return;  // wave-uniform
+    const SysConst& S = A.sc[c.s];
+    const int64_t i = c.i;
+    unsigned long long m0 = 0, m1 = 0;
+    if (c.lane) {
+        const Q4<R>* geo = (const Q4<R>*)A.geo;
+        const Q4<R>* th = (const Q4<R>*)A.th[slot];
+        const Q4<R>* vin = (const Q4<R>*)A.vbuf[slot];
+        const Q4<R>* col = (const Q4<R>*)A.col;
+        R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
+        const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
+        const R c0 = (R)S.c0, inv_c0 = (R)S.inv_c0;
+        const Q4<R> gi = geo[i];
+        const Q4<R> ti = th[i];
+        const Q4<R> vi = vin[i];
+        const int phi = Geo<R>::phase(gi);
+        const bool surface = (A.flags[i] & kFlagNearInterface) && !(S.flags & kNoSurface);
+        const bool penalty = !(S.flags & kNoPenalty);
+        const bool single = (S.flags & kGbarSingleField) != 0;
+        const bool r3 = (S.flags & kPenaltyR3) != 0;
+        const R gamma = (R)S.gamma;
+        const R xg = (R)(S.xi * S.gamma);
+        const R rho0_i = (R)S.rho0[phi], rho0_o = (R)S.rho0[phi ^ 1];
+        const R phi_i_x = rho0_i / (rho0_i + rho0_o);  // phi_i for a cross pair
+        const R phi_j_x = rho0_o / (rho0_i + rho0_o);
+        const R pen_x = R(-4) * phi_i_x * phi_j_x * xg;
+        Q4<R> ci{0, 0, 0, 0};
+        if (surface) ci = col[i];
+        const R gni = (ci.x * ci.x + ci.y * ci.y + ci.z * ci.z) * ci.w;  // |grad C_i|
+        R sp[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+        const int cnt = A.ncount[i];
+        for (int k = 0; k < cnt; ++k) {
+            const uint32_t j = nbr_at(A, i, k);
+            const Q4<R> gj = geo[j];
+            R r[3];
+            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const R inv_r = rsqrt_r<R>(r2);
+            const R rr = r2 * inv_r;
+            const R dW = wendland_dw<R>(rr * inv_h, coef);
+            const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+            const Q4<R> tj = th[j];
+            const Q4<R> vj = vin[j];
+            const R Vj = tj.y;
+            // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
+            const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
+            const R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
+            const R dU = UL - UR;
+            const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
+            const R Pstar = (ti.x * tj.z + tj.x * ti.z + beta * c0 * ti.x * tj.x * dU) /
+                            (ti.x + tj.x);
+            const R fp = Pstar * dW * Vj;
+            sp[0] += fp * e[0];
+            sp[1] += fp * e[1];
+            if (D == 3) sp[2] += fp * e[2];
+            if (!surface) continue;
+            const bool same = Geo<R>::phase(gj) == phi;
+            const Q4<R> cj = col[j];
+            const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
+            // Pi e = gamma (|g| e - g (g . e) / |g|)
+            const R gie = (ci.x * e[0] + ci.y * e[1] + ci.z * e[2]) * ci.w;
+            const R gje = (cj.x * e[0] + cj.y * e[1] + cj.z * e[2]) * cj.w;
+            const R wi = same ? R(1) : R(2) * phi_j_x;
+            const R wj = same ? R(1) : R(2) * phi_i_x;
+            R se[3];
+            se[0] = gamma * (wi * (gni * e[0] - ci.x * gie) + wj * (gnj * e[0] - cj.x * gje));
+            se[1] = gamma * (wi * (gni * e[1] - ci.y * gie) + wj * (gnj * e[1] - cj.y * gje));
+            se[2] = gamma * (wi * (gni * e[2] - ci.z * gie) + wj * (gnj * e[2] - cj.z * gje));
+            const R fs = dW * Vj;
+            ss[0] += fs * se[0];
+            ss[1] += fs * se[1];
+            if (D == 3) ss[2] += fs * se[2];
+            if (!penalty) continue;
+            // Eq. 27 and Eq. 30 (reading R1): Chat grad W = dW [C e - (gbar.r) gbar/|gbar|]
+            const R sgn = (single && !same) ? R(-1) : R(1);
+            const R gb[3] = {R(0.5) * (ci.x + sgn * cj.x), R(0.5) * (ci.y + sgn * cj.y),
+                             R(0.5) * (ci.z + sgn * cj.z)};
+            const R gb2 = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
+            const R gbr = gb[0] * r[0] + gb[1] * r[1] + gb[2] * r[2];
+            const R inv_gb = gb2 > R(0) ? rsqrt_r<R>(gb2) : R(0);
+            const R C = same ? R(0) : R(1);
+            R q[3];
+            if (r3) {
+                const R sc = dW * (C - gbr * gbr * inv_gb * inv_r);
+                q[0] = sc * e[0];
+                q[1] = sc * e[1];
+                q[2] = sc * e[2];
+            } else {
+                const R t = gbr * inv_gb;
+                q[0] = dW * (C * e[0] - t * gb[0]);
+                q[1] = dW * (C * e[1] - t * gb[1]);
+                q[2] = dW * (C * e[2] - t * gb[2]);
+            }
+            // Nbar q = (n_i (n_i . q) + n_j (n_j . q)) / 2 with n = g / |g|
+            const R niq = (ci.x * q[0] + ci.y * q[1] + ci.z * q[2]) * ci.w * ci.w;
+            const R njq = (cj.x * q[0] + cj.y * q[1] + cj.z * q[2]) * cj.w * cj.w;
+            R Nq[3];
+            Nq[0] = R(0.5) * (ci.x * niq + cj.x * njq);
+            Nq[1] = R(0.5) * (ci.y * niq + cj.y * njq);
+            Nq[2] = R(0.5) * (ci.z * niq + cj.z * njq);
+            const R pc = (same ? xg : pen_x) * inv_r * Vj;
+            if (same) {
+                // Tbar q = q - Nbar q
+                ss[0] += pc * (q[0] - Nq[0]);
+                ss[1] += pc * (q[1] - Nq[1]);
+                if (D == 3) ss[2] += pc * (q[2] - Nq[2]);
+            } else {
+                ss[0] += pc * Nq[0];
+                ss[1] += pc * Nq[1];
+                if (D == 3) ss[2] += pc * Nq[2];
+            }
+        }
+        const R inv_rho = R(1) / ti.x;
+        const Q4<R> av = ((const Q4<R>*)A.av)[i];
+        const R avv[3] = {av.x, av.y, av.z};
+        double acc[3];
+        for (int a = 0; a < 3; ++a)
+            acc[a] = a < D ? (double)(R(-2) * inv_rho * sp[a]) + (double)(inv_rho * ss[a]) +
+                                 (double)avv[a] + S.grav[a]
+                           : 0.0;
+        Q4<R>* vout = (Q4<R>*)A.vbuf[slot ^ 1];
+        if (A.mode == 1) {
+            for (int a = 0; a < 3; ++a) {
+                A.r_acc[3 * i + a] = acc[a];
+                A.r_accp[3 * i + a] = a < D ? (double)(R(-2) * inv_rho * sp[a]) : 0.0;
+                A.r_accs[3 * i + a] = a < D ? (double)(inv_rho * ss[a]) : 0.0;
+            }
+            vout[i] = vi;
+        } else {
+            const double dt = Dy.dt[slot];
+            double v[3] = {0.0, 0.0, 0.0};
+            double v2 = 0.0;
+            bool bad = false;
+            for (int a = 0; a < D; ++a) {
+                v[a] = A.vel[a][i] + dt * acc[a];
+                A.vel[a][i] = v[a];
+                v2 += v[a] * v[a];
+                bad |= !isfinite(v[a]);
+            }
+            if (bad) flag_health(Dy, kHealthNonFinite);
+            vout[i] = Q4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
+            unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
+            if (phi == 0) m0 = bits;
+            else m1 = bits;
+        }
+    }
+    if (A.mode == 1) return;
+    m0 = wave_max_u64(m0);
+    m1 = wave_max_u64(m1);
+    if ((threadIdx.x & 63) == 0) {
+        if (m0) atomicMax(&Dy.vmax_acc[0], m0);
+        if (m1) atomicMax(&Dy.vmax_acc[1], m1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// substep pair pass 3: continuity with the new velocity (Eq. 6 with Eq. 9),
+// second half-step, and the first half-step of the next substep
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int slot)
+{
+    Slot c = slot_of(A);
+    if (c.s < 0) return;
+    SysDyn& Dy = A.sd[c.s];
+    if (A.mode == 0 && !Dy.active[slot]) return;
+    if (!c.lane) return;
+    const SysConst& S = A.sc[c.s];
+    const int64_t i = c.i;
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* th = (const Q4<R>*)A.th[slot];
+    const Q4<R>* vk = (const Q4<R>*)A.vbuf[slot ^ 1];
+    R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
+    const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
+    const R inv_c0 = (R)S.inv_c0;
+    const Q4<R> gi = geo[i];
+    const Q4<R> ti = th[i];
+    const Q4<R> vi = vk[i];
+    R s = 0;
+    const int cnt = A.ncount[i];
+    for (int k = 0; k < cnt; ++k) {
+        const uint32_t j = nbr_at(A, i, k);
+        const Q4<R> gj = geo[j];
+        R r[3];
+        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const R inv_r = rsqrt_r<R>(r2);
+        const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
+        const Q4<R> tj = th[j];
+        const Q4<R> vj = vk[j];
+        const R vie = (vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
+        const R vje = (vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
+        // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e
+        const R Ustar = (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
+        s += (vie + Ustar) * dW * tj.y;
+    }
+    const double drho = 2.0 * (double)ti.x * (double)s;
+    if (A.mode == 1) {
+        A.r_drho[i] = drho;
+        return;
+    }
+    const double dt = Dy.dt[slot];
+    double rho = A.rho[i] + 0.5 * dt * drho;
+    for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt * A.vel[a][i];
+    if (Dy.active[slot ^ 1]) {
+        const double dt2 = Dy.dt[slot ^ 1];
+        rho += 0.5 * dt2 * drho;
+        for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt2 * A.vel[a][i];
+        const int ph = Geo<R>::phase(gi);
+        ((Q4<R>*)A.th[slot ^ 1])[i] =
+            Q4<R>{(R)rho, (R)(A.mass[i] / rho), (R)(S.c0sq * (rho - S.rho0[ph])), (R)0};
+    }
+    A.rho[i] = rho;
+    A.drho[i] = drho;
+    if (!(rho > 0.0)) flag_health(Dy, isfinite(rho) ? kHealthDensity : kHealthNonFinite);
+}
+
+// ---------------------------------------------------------------------------
+// observables: per-wave partial sums in a fixed butterfly order, then one
+// thread per system and field summing its waves in order
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_maxd(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// pass 0: momentum(3) kinetic mass(2) volume(2) vmax(2) m x of fluid k(3)
+// pass 1: moment2 about the centroid (6) p_in n_in p_out n_out
+template <int D>
+__global__ __launch_bounds__(kWave) void k_obs_partial(DevArrays A, int pass)
+{
+    const int64_t w = blockIdx.x;
+    const int64_t i = w * kWave + threadIdx.x;
+    if (i >= A.P) return;
+    int s = A.wave_sys[w];
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s < 0) return;
+    const SysConst& S = A.sc[s];
+    const bool lane = i < S.p_off + S.p_n;
+    double f[16];
+    for (int k = 0; k < 16; ++k) f[k] = 0.0;
+    if (lane) {
+        const double m = A.mass[i];
+        const int ph = A.phase[i];
+        double x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+            x[a] = A.pos[a][i];
+            v[a] = A.vel[a][i];
+        }
+        if (pass == 0) {
+            double v2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                f[a] = m * v[a];
+                v2 += v[a] * v[a];
+            }
+            f[3] = 0.5 * m * v2;
+            f[4 + ph] = m;
+            f[6 + ph] = m / A.rho[i];
+            f[8 + ph] = sqrt(v2);
+            if (ph == 0)
+                for (int a = 0; a < D; ++a) f[10 + a] = m * x[a];
+        } else {
+            const double* o = A.obs_out + (int64_t)s * 32;
+            double dx[3] = {0, 0, 0};
+            double r2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                dx[a] = x[a] - o[10 + a];
+                r2 += dx[a] * dx[a];
+            }
+            if (ph == 0) {
+                f[0] = m * dx[0] * dx[0];
+                f[1] = m * dx[0] * dx[1];
+                f[2] = m * dx[0] * dx[2];
+                f[3] = m * dx[1] * dx[1];
+                f[4] = m * dx[1] * dx[2];
+                f[5] = m * dx[2] * dx[2];
+            }
+            const double r = sqrt(r2);
+            const double p = S.c0sq * (A.rho[i] - S.rho0[ph]);
+            const double req = o[13];
+            if (ph == 0 && r < req - 3.0 * S.h) {
+                f[6] = p;
+                f[7] = 1.0;
+            }
+            if (ph == 1 && r > req + 3.0 * S.h) {
+                f[8] = p;
+                f[9] = 1.0;
+            }
+        }
+    }
+    for (int k = 0; k < 16; ++k) {
+        const bool is_max = pass == 0 && (k == 8 || k == 9);
+        f[k] = is_max ? wave_maxd(f[k]) : wave_sum(f[k]);
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 16; ++k) A.obs_part[w * 16 + k] = f[k];
+}
+
+__global__ void k_obs_final(DevArrays A, int pass)
+{
+    const int s = blockIdx.x;
+    const int k = threadIdx.x & 15;
+    const bool owner = threadIdx.x < 16;
+    const SysConst& S = A.sc[s];
+    const int64_t w0 = S.p_off / kWave, w1 = (S.p_off + S.p_n + kWave - 1) / kWave;
+    const bool is_max = pass == 0 && (k == 8 || k == 9);
+    double acc = 0.0;
+    for (int64_t w = w0; w < w1; ++w) {
+        const double v = A.obs_part[w * 16 + k];
+        acc = is_max ? fmax(acc, v) : acc + v;
+    }
+    double* o = A.obs_out + (int64_t)s * 32;
+    if (pass == 0) {
+        if (owner) o[k] = acc;
+        __syncthreads();
+        if (k == 0) {
+            // centroid of fluid k and equivalent radius of its volume
+            const double mk = o[4];
+            for (int a = 0; a < 3; ++a) o[10 + a] = mk > 0.0 ? o[10 + a] / mk : 0.0;
+            const double vol = o[6];
+            o[13] = S.dim == 2 ? sqrt(vol / M_PI) : cbrt(3.0 * vol / (4.0 * M_PI));
+        }
+    } else if (owner) {
+        o[16 + k] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline dim3 slot_grid(int64_t P)
+{
+    int64_t nb = (P + kBlock - 1) / kBlock;
+    nb = (nb + 7) / 8 * 8;
+    return dim3((unsigned)nb);
+}
+
+static inline dim3 flat_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+void launch_bin(const Launch& L, DevArrays& A, int64_t ncells)
+{
+    hipLaunchKernelGGL(k_fill_i32, flat_grid(ncells), dim3(kBlock), 0, L.stream, A.cell_cnt, ncells, 0);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_key<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    else
+        hipLaunchKernelGGL(k_key<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    const int64_t ntiles = (ncells + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
+                       ncells, A.scan_part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, L.stream, A.scan_part, ntiles);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
+                       ncells, A.scan_part, A.cell_start);
+    hipLaunchKernelGGL(k_scatter, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    hipLaunchKernelGGL(k_cellsort, flat_grid(ncells), dim3(kBlock), 0, L.stream, A, ncells);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_gather<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    else
+        hipLaunchKernelGGL(k_gather<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    // the gathered copy becomes the current state
+    for (int a = 0; a < 3; ++a) {
+        std::swap(A.pos[a], A.pos2[a]);
+        std::swap(A.vel[a], A.vel2[a]);
+    }
+    std::swap(A.rho, A.rho2);
+    std::swap(A.drho, A.drho2);
+    std::swap(A.mass, A.mass2);
+    std::swap(A.id, A.id2);
+    std::swap(A.phase, A.phase2);
+}
+
+#define RSPH_DISPATCH(KERNEL, GRID, ...)                                                        \
+    do {                                                                                        \
+        if (L.fp64) {                                                                           \
+            if (L.dim == 2)                                                                     \
+                hipLaunchKernelGGL((KERNEL<double, 2>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
+            else                                                                                \
+                hipLaunchKernelGGL((KERNEL<double, 3>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
+        } else {                                                                                \
+            if (L.dim == 2)                                                                     \
+                hipLaunchKernelGGL((KERNEL<float, 2>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
+            else                                                                                \
+                hipLaunchKernelGGL((KERNEL<float, 3>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
+        }                                                                                       \
+    } while (0)
+
+void launch_neighbours(const Launch& L, const DevArrays& A)
+{
+    RSPH_DISPATCH(k_neighbours, slot_grid(A.P), A);
+}
+
+void launch_dt_advection(const Launch& L, const DevArrays& A)
+{
+    hipLaunchKernelGGL(k_dt_advection, dim3((A.nsys + 63) / 64), dim3(64), 0, L.stream, A);
+}
+
+void launch_advection(const Launch& L, const DevArrays& A)
+{
+    RSPH_DISPATCH(k_advection, slot_grid(A.P), A);
+}
+
+void launch_shift(const Launch& L, const DevArrays& A) { RSPH_DISPATCH(k_shift, slot_grid(A.P), A); }
+
+void launch_colour(const Launch& L, const DevArrays& A, int slot)
+{
+    RSPH_DISPATCH(k_colour, slot_grid(A.P), A, slot);
+}
+
+void launch_force(const Launch& L, const DevArrays& A, int slot)
+{
+    RSPH_DISPATCH(k_force, slot_grid(A.P), A, slot);
+}
+
+void launch_dt_substep(const Launch& L, const DevArrays& A, int slot)
+{
+    hipLaunchKernelGGL(k_dt_substep, dim3((A.nsys + 63) / 64), dim3(64), 0, L.stream, A, slot);
+}
+
+void launch_continuity(const Launch& L, const DevArrays& A, int slot)
+{
+    RSPH_DISPATCH(k_continuity, slot_grid(A.P), A, slot);
+}
+
+void launch_any_active(const Launch& L, const DevArrays& A, int slot, int32_t* out)
+{
+    hipLaunchKernelGGL(k_any_active, dim3(1), dim3(64), 0, L.stream, A, slot, out);
+}
+
+void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask)
+{
+    hipLaunchKernelGGL(k_set_stepping, dim3((A.nsys + 63) / 64), dim3(64), 0, L.stream, A, mask);
+}
+
+void launch_observables(const Launch& L, const DevArrays& A, int64_t nwaves)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        if (L.dim == 2)
+            hipLaunchKernelGGL(k_obs_partial<2>, dim3((unsigned)nwaves), dim3(kWave), 0, L.stream, A, pass);
+        else
+            hipLaunchKernelGGL(k_obs_partial<3>, dim3((unsigned)nwaves), dim3(kWave), 0, L.stream, A, pass);
+        hipLaunchKernelGGL(k_obs_final, dim3((unsigned)A.nsys), dim3(64), 0, L.stream, A, pass);
+    }
+}
+
+}  // namespace rsph

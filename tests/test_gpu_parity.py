@@ -1,0 +1,291 @@
+"""Parity of the HIP library (through its C-ABI) with the FP64 CPU oracle.
+
+Binning and neighbour sets are compared bit-exactly; floating-point rates are
+compared normwise: e = max_i |x_i - x_i^oracle| / max_i |x_i^oracle|, with
+e <= 1e-12 for the FP64 form (summation order differs) and e <= 1e-5 for the
+mixed form (FP32 pair arithmetic).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2503_16082_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+rsph = pytest.importorskip("paper_2503_16082_amd.rsph")
+
+TOL = {0: 1e-12, 1: 1e-5}
+FIELDS = ["gradC", "acc", "acc_p", "acc_s", "acc_v", "drho", "B", "dr", "sigma"]
+GPU_NAME = {"drho": "rate_drho"}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def normwise(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(len(a), -1)
+    b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a).max())
+
+
+def perturbed_state(w, seed=1, vscale=None, drho=0.01):
+    """Workload state with random velocities and density perturbations so that
+    every term of the method is exercised."""
+    p = dict(w["params"])
+    d = p["dim"]
+    rng = np.random.default_rng(seed)
+    n = w["pos"].shape[0]
+    pos = O.wrap(p, w["pos"])
+    rho0 = np.asarray(p["rho0"])[w["phase"]]
+    if vscale is None:
+        vscale = 0.1 * p["c0"]
+    vel = vscale * rng.normal(size=(n, d))
+    rho = rho0 * (1.0 + drho * rng.normal(size=n))
+    mass = rho0 / O.sigma0(d, p["dp"] * p.get("h_over_dp", 1.3), p["dp"])
+    return p, pos, vel, rho, mass, w["phase"]
+
+
+def gpu_rates(p, pos, vel, rho, mass, phase, precision):
+    s = rsph.System(p, precision=precision)
+    s.set_particles(pos, vel, phase, mass=mass, rho=rho)
+    s.eval_rates()
+    out = {k: s.read(GPU_NAME.get(k, k)) for k in FIELDS}
+    out["nnb"] = s.read("nnb")
+    s.close()
+    return out
+
+
+def compare_rates(g, ref, precision, label, targets=None):
+    tol = TOL[precision]
+    errs = {}
+    for k in FIELDS:
+        a = g[k] if targets is None else g[k][targets]
+        errs[k] = normwise(a, ref[k])
+    say(label, " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+    nn = g["nnb"] if targets is None else g["nnb"][targets]
+    assert np.array_equal(nn.astype(np.int64), ref["nnb"])
+
+
+# ---------------------------------------------------------------------------
+# binning and neighbours: bit-exact
+# ---------------------------------------------------------------------------
+
+def hard_state(dim, seed):
+    p, _, dp = None, None, None
+    n_side = 16
+    dp = 1.0 / n_side
+    p = WL.base_params(dim, (1.0,) * dim, dp, (1.0, 1.0), (0.0, 0.0), 0.0, 1.0)
+    ok, nc = O.grid(p)
+    rng = np.random.default_rng(seed)
+    pts = WL.lattice(dim, (n_side,) * dim, dp)
+    pts = pts + rng.uniform(-0.3 * dp, 0.3 * dp, pts.shape)
+    faces = np.array([[k / nc[0]] + [0.5 + 0.01 * k] * (dim - 1) for k in range(nc[0])])
+    pos = O.wrap(p, np.vstack([pts, faces]))
+    phase = (rng.uniform(size=pos.shape[0]) < 0.3).astype(np.int32)
+    return p, pos, phase
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_binning_bit_exact(dim, precision):
+    p, pos, phase = hard_state(dim, 4)
+    say(f"binning dim={dim} precision={precision} n={len(pos)}")
+    s = rsph.System(p, precision=precision)
+    s.set_particles(pos, np.zeros_like(pos), phase)
+    key, rank = s.binning()
+    kref = O.cell_keys(p, pos)
+    perm, _ = O.bin_particles(p, kref)
+    rref = np.empty_like(perm)
+    rref[perm] = np.arange(len(perm))
+    assert np.array_equal(key, kref)
+    assert np.array_equal(rank, rref)
+    s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neighbour_sets_equal_brute_force(dim):
+    p, pos, phase = hard_state(dim, 5)
+    say(f"neighbours dim={dim} n={len(pos)}")
+    s = rsph.System(p)
+    s.set_particles(pos, np.zeros_like(pos), phase)
+    start, idx = s.neighbours()
+    bs, bi = O.neighbours_brute(p, pos, cap_per=400)
+    assert np.array_equal(start, bs)
+    for i in range(len(pos)):
+        assert np.array_equal(np.sort(idx[start[i]:start[i + 1]]), bi[bs[i]:bs[i + 1]])
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# single evaluations
+# ---------------------------------------------------------------------------
+
+CASES = {
+    "droplet2d_ratio1000": lambda: WL.static_droplet_2d(n_side=50, R=0.2, seed=0),
+    "droplet2d_ratio1": lambda: WL.static_droplet_2d(n_side=40, R=0.2, seed=2,
+                                                      rho=(1.0, 1.0), eta=(0.05, 0.05)),
+    "droplet3d_ratio1000": lambda: WL.static_droplet_3d(n_side=20, R=0.3, seed=0),
+    "ellipse2d_ratio10": lambda: WL.oscillating_ellipse_2d(3000, 1.4, 10.0, 1.5, seed=3),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eval_rates_parity(case, precision):
+    w = CASES[case]()
+    p, pos, vel, rho, mass, phase = perturbed_state(w)
+    say(f"eval {case} precision={precision} n={len(pos)}")
+    g = gpu_rates(p, pos, vel, rho, mass, phase, precision)
+    ref = O.eval_rates(p, pos, vel, rho, mass, phase)
+    compare_rates(g, ref, precision, f"{case}/p{precision}")
+
+
+@pytest.mark.parametrize("flags", [rsph.NO_PENALTY, rsph.GBAR_SINGLE_FIELD, rsph.PENALTY_R3,
+                                   rsph.NO_SURFACE])
+def test_eval_rates_parity_method_switches(flags):
+    w = WL.static_droplet_2d(n_side=40, R=0.2, seed=1)
+    p, pos, vel, rho, mass, phase = perturbed_state(w)
+    p["flags"] = flags
+    p["oracle_flags"] = flags
+    say(f"eval switches flags={flags}")
+    g = gpu_rates(p, pos, vel, rho, mass, phase, 0)
+    ref = O.eval_rates(p, pos, vel, rho, mass, phase)
+    compare_rates(g, ref, 0, f"flags{flags}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_momentum_conservation_on_gpu(precision):
+    w = WL.static_droplet_3d(n_side=20, R=0.3, seed=4)
+    p, pos, vel, rho, mass, phase = perturbed_state(w)
+    s = rsph.System(p, precision=precision)
+    s.set_particles(pos, vel, phase, mass=mass, rho=rho)
+    s.eval_rates()
+    tol = 1e-12 if precision == 0 else 1e-6
+    for k in ["acc_p", "acc_s", "acc_v"]:
+        f = mass[:, None] * s.read(k)
+        tot = np.array([math.fsum(f[:, a]) for a in range(3)])
+        scale = np.abs(f).sum()
+        say(f"momentum p{precision} {k} {np.abs(tot).max() / scale:.2e}")
+        assert np.abs(tot).max() <= tol * scale
+    s.close()
+
+
+def test_single_particle_and_single_phase_edge_cases():
+    # one particle: no neighbours, zero rates except gravity
+    p = WL.base_params(2, (1.0, 1.0), 0.05, (1.0, 1.0), (0.01, 0.01), 1.0, 1.0,
+                       gravity=[0.0, -1.0, 0.0])
+    s = rsph.System(p)
+    s.set_particles(np.array([[0.5, 0.5]]), np.array([[0.1, 0.0]]), np.array([0], np.int32))
+    s.eval_rates()
+    assert np.allclose(s.read("acc"), [[0.0, -1.0]])
+    assert s.read("nnb")[0] == 0
+    s.step(2)
+    o = s.observables()
+    assert o["n_outer"] == 2 and o["n_sub"] >= 2
+    s.close()
+    # a single fluid: the colour gradient and surface terms vanish
+    w = WL.static_droplet_2d(n_side=30, seed=5)
+    p, pos, vel, rho, mass, phase = perturbed_state(w)
+    phase = np.zeros_like(phase)
+    g = gpu_rates(p, pos, vel, rho, mass, phase, 0)
+    assert np.abs(g["gradC"]).max() == 0.0 and np.abs(g["acc_s"]).max() == 0.0
+
+
+# ---------------------------------------------------------------------------
+# trajectories
+# ---------------------------------------------------------------------------
+
+def test_fp64_trajectory_matches_oracle():
+    w = WL.static_droplet_2d(n_side=50, R=0.2, seed=0)
+    p = w["params"]
+    say("trajectory static droplet 2D, 4 advection steps")
+    st = O.State(p, w["pos"], w["vel"], w["phase"])
+    st.step(4)
+    s = rsph.System(p, precision=0)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(4)
+    o = s.observables()
+    ref = st.observables()
+    assert o["n_outer"] == 4 and o["n_sub"] == ref["n_sub"]
+    assert o["t"] == pytest.approx(ref["t"], rel=1e-12)
+    ev = normwise(s.read("vel"), st.vel)
+    er = normwise(s.read("rho") - np.asarray(p["rho0"])[w["phase"]],
+                  st.rho - np.asarray(p["rho0"])[w["phase"]])
+    pos = s.read("pos")
+    dpos = pos - O.wrap(p, st.pos)
+    dpos -= np.round(dpos)
+    say(f"trajectory vel {ev:.2e} rho {er:.2e} pos {np.abs(dpos).max():.2e}")
+    assert ev < 1e-9 and er < 1e-9 and np.abs(dpos).max() < 1e-12
+    assert o["kinetic"] == pytest.approx(ref["kinetic"], rel=1e-9)
+    s.close()
+
+
+def test_bitwise_determinism_and_resume():
+    w = WL.static_droplet_2d(n_side=40, R=0.2, seed=6)
+    p = w["params"]
+    runs = []
+    for _ in range(2):
+        s = rsph.System(p, precision=1)
+        s.set_particles(w["pos"], w["vel"], w["phase"])
+        s.step(3)
+        runs.append((s.read("pos"), s.read("vel"), s.read("rho")))
+        s.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+    # checkpoint after 1 step, resume for 2: bitwise equal to 3 straight steps
+    s = rsph.System(p, precision=1)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(1)
+    ck = {k: s.read(k) for k in ["pos", "vel", "rho", "drho", "mass"]}
+    s.close()
+    s = rsph.System(p, precision=1)
+    s.set_particles(ck["pos"], ck["vel"], w["phase"], mass=ck["mass"], rho=ck["rho"])
+    s.set_drho(ck["drho"])
+    s.step(2)
+    for a, k in zip(runs[0], ["pos", "vel", "rho"]):
+        assert np.array_equal(a, s.read(k)), k
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, sampled outputs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_static_droplet_3d_full_size_subset(precision):
+    """262,144 particles; parity on the 16^3 lattice block straddling the
+    interface (4,096 particles), the oracle evaluating that block only."""
+    w = WL.static_droplet_3d(n_side=64, R=0.25, seed=0)
+    p, pos, vel, rho, mass, phase = perturbed_state(w)
+    say(f"3D full size precision={precision}")
+    g = gpu_rates(p, pos, vel, rho, mass, phase, precision)
+    targets = WL.subset_indices_3d(64, (40, 24, 24), (56, 40, 40))
+    ref = O.eval_rates(p, pos, vel, rho, mass, phase, targets=targets)
+    assert (phase[targets] == 0).sum() > 500
+    compare_rates(g, ref, precision, f"c3subset/p{precision}", targets=targets)
+
+
+@pytest.mark.parametrize("precision", [1])
+def test_droplet_impact_full_size_sampled(precision):
+    """8,388,608 particles; parity on 2,000 sampled particles, half of them
+    within 3h of an interface."""
+    w = WL.droplet_impact_3d()
+    p, pos, vel, rho, mass, phase = perturbed_state(w, vscale=1.0)
+    vel[w["vel"][:, 2] != 0, 2] -= 50.0
+    say(f"impact full size n={len(pos)} precision={precision}")
+    g = gpu_rates(p, pos, vel, rho, mass, phase, precision)
+    rng = np.random.default_rng(9)
+    inter = np.where(np.linalg.norm(g["gradC"], axis=1) > 0)[0]
+    targets = np.concatenate([rng.choice(len(pos), 1000, replace=False),
+                              rng.choice(inter, 1000, replace=False)])
+    ref = O.eval_rates(p, pos, vel, rho, mass, phase, targets=targets)
+    compare_rates(g, ref, precision, f"impact/p{precision}", targets=targets)
