@@ -1,0 +1,219 @@
+"""Benchmark of the Riemann-SPH multiphase surface-tension hot path on one GPU.
+
+A step is one advection step of the dual-criteria scheme: rebinning, neighbour
+lists, density summation, viscous acceleration, correction matrix and position
+shift, then every acoustic substep (colour gradient, Riemann pressure with the
+surface stress and penalty force, kick, continuity) until the advection step is
+covered.  The default workload is the 2D square droplet relaxing to a circle:
+periodic unit square, dp = 1/200 (40,000 particles), a square of side 0.4 of
+fluid k, density ratio 1000 and viscosity ratio 100, gamma = 1, in the mixed
+precision form (FP32 pair loops, FP64 state).  Inputs are synthetic and already
+resident in device memory when the timed region starts.
+
+Prints ONE JSON line.  Everything else goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2503_16082_amd import rsph  # noqa: E402
+from paper_2503_16082_amd import workloads as WL  # noqa: E402
+
+# Published MI355X peaks used for the roofline (dense vector arithmetic).
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic operations per neighbour pair of the force pass (Riemann pressure,
+# Eqs. 7-12) and its surface part (stress divergence and projected penalty,
+# Eqs. 24, 27, 30, 33, near-interface pairs only), counted from the arithmetic
+# of the method with an FMA as two operations and rsqrt / division as one.
+FORCE_OPS = {2: (47, 87), 3: (59, 127)}
+CONT_OPS = {2: 37, 3: 46}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    if name == "square2d":
+        return WL.square_droplet_2d(n_side=200)
+    if name == "droplet2d":
+        return WL.static_droplet_2d(n_side=50)
+    if name == "droplet3d":
+        return WL.static_droplet_3d(n_side=64)
+    if name == "impact3d":
+        return WL.droplet_impact_3d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_gpu(w, precision, steps, warmup, timed_kernels):
+    p = w["params"]
+    s = rsph.System(p, precision=precision)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    if warmup:
+        s.step(warmup)
+    o0 = s.observables()
+    s.set_timing(timed_kernels)
+    t0 = time.perf_counter()
+    s.step(steps)  # returns after the stream is synchronised
+    t1 = time.perf_counter()
+    timing = s.timing()
+    o1 = s.observables()
+    nnb = s.read("nnb")
+    flags = s.read("flags").astype(np.int64)
+    return s, {
+        "seconds": t1 - t0,
+        "substeps": int(o1["n_sub"] - o0["n_sub"]),
+        "timing": timing,
+        "pairs": float(nnb.sum()),
+        "near_pairs": float(nnb[(flags & 2) != 0].sum()),
+        "obs": o1,
+    }
+
+
+def accel_error(w, precision):
+    """Normwise single-evaluation acceleration error of a GPU form against the
+    FP64 oracle at the workload's initial state."""
+    from oracle import oracle as O
+    p = w["params"]
+    s = rsph.System(p, precision=precision)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.eval_rates()
+    acc = s.read("acc")
+    pos, vel, rho, mass = s.read("pos"), s.read("vel"), s.read("rho"), s.read("mass")
+    s.close()
+    ref = O.eval_rates(p, O.wrap(p, pos), vel, rho, mass, w["phase"])["acc"]
+    return float(np.abs(acc - ref).max() / np.abs(ref).max())
+
+
+def cpu_baseline(w, outer_steps):
+    """The FP64 oracle, untuned, on the host cores: a bounded sample of the same
+    workload (its first advection steps)."""
+    from oracle import oracle as O
+    p = w["params"]
+    st = O.State(p, w["pos"], w["vel"], w["phase"])
+    t0 = time.perf_counter()
+    st.step(outer_steps)
+    dt = time.perf_counter() - t0
+    n = w["pos"].shape[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": n * outer_steps / dt,
+        "unit": "particle-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {outer_steps} advection steps ({int(st.clock.n_sub)} substeps) of the "
+                  f"same workload, {n} particles, {dt:.1f} s",
+        "particle_substeps_per_s": n * st.clock.n_sub / dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="square2d",
+                    choices=["square2d", "droplet2d", "droplet3d", "impact3d"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the method's hot path is single-GPU here; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    w = workload(args.workload)
+    n = w["pos"].shape[0]
+    dim = w["params"]["dim"]
+    prec = rsph.MIXED if args.precision == "mixed" else rsph.FP64
+    log(f"workload {w['name']} n={n} precision={args.precision} steps={args.steps} warmup={args.warmup}")
+
+    s, r = run_gpu(w, prec, args.steps, args.warmup, ["force"])
+    s.close()
+    secs = r["seconds"]
+    value = n * args.steps / secs
+    f_launch, f_ms = r["timing"]["force"]
+    f_avg_ms = f_ms / max(f_launch, 1)
+    bulk_ops, surf_ops = FORCE_OPS[dim]
+    ops = r["pairs"] * bulk_ops + r["near_pairs"] * surf_ops
+    achieved = ops / (f_avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS["f32" if prec == rsph.MIXED else "f64"]
+    log(f"gpu {secs:.3f}s substeps={r['substeps']} force launches={f_launch} avg={f_avg_ms * 1e3:.1f}us "
+        f"ops/launch={ops:.3e} -> {achieved:.2f} TFLOP/s")
+
+    extra = {}
+    if prec == rsph.MIXED and not args.no_fp64_compare:
+        s64, r64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, ["force"])
+        s64.close()
+        v64 = n * args.steps / r64["seconds"]
+        l64, m64 = r64["timing"]["force"]
+        extra["fp64_gpu_value"] = v64
+        extra["mixed_over_fp64"] = value / v64
+        extra["fp64_force_avg_us"] = m64 / max(l64, 1) * 1e3
+        log(f"fp64 gpu {r64['seconds']:.3f}s -> {v64:.3e} particle-steps/s, mixed/fp64 = {value / v64:.2f}")
+    try:
+        extra["accel_err_vs_fp64_oracle"] = accel_error(w, prec)
+    except Exception as e:  # the oracle is a checker, not the product
+        log(f"accel error check skipped: {e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_steps)
+        log(f"cpu baseline {cpu}")
+
+    line = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == rsph.MIXED else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w["name"],
+            "particles": n,
+            "dim": dim,
+            "form": args.precision,
+            "step": "one advection step with all its acoustic substeps",
+            "parallelism": "single GPU",
+        },
+        "particle_substeps_per_s": n * r["substeps"] / secs,
+        "substeps_per_step": r["substeps"] / args.steps,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "force pass (k_force)",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "avg_launch_us": f_avg_ms * 1e3,
+            "ops_per_launch": ops,
+        },
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,7 +133,8 @@ enum {
     RSPH_FIELD_DR = 14,    /* dim: position correction (Eq. 14), not applied */
     RSPH_FIELD_SIGMA = 15, /* 1: W(0) + sum_j W_ij */
     RSPH_FIELD_NNB = 16,   /* 1: neighbour count */
-    RSPH_FIELD_COUNT = 17
+    RSPH_FIELD_FLAGS = 17, /* 1: 1 = has a neighbour of the other fluid, +2 = it or a neighbour has */
+    RSPH_FIELD_COUNT = 18
 };
 
 /* Fills *p with the documented defaults (2D, FP64, unit box, dp = 0.02, ...). */
@@ -190,10 +191,11 @@ rsph_status rsph_read_binning(rsph_system* sys, int64_t n, uint32_t* key, int64_
 rsph_status rsph_read_neighbours(rsph_system* sys, int64_t n, int64_t cap, int64_t* start,
                                  int64_t* idx);
 
-/* Kernel timing: when enabled, every launch of the pair kernels is bracketed by
- * HIP events on the system's stream; rsph_read_kernel_timing returns, per kernel
- * (RSPH_KERNEL_*), the number of launches that did work and their summed
- * duration in milliseconds since the last reset. */
+/* Kernel timing: kernel_mask selects kernels by bit (1 << RSPH_KERNEL_*; 0 turns
+ * timing off).  Every launch of a selected kernel is bracketed by HIP events on
+ * the system's stream; rsph_read_kernel_timing returns, per kernel, the number
+ * of launches that did work and their summed duration in milliseconds since the
+ * last call of rsph_set_kernel_timing (which resets the totals). */
 enum {
     RSPH_KERNEL_BIN = 0,
     RSPH_KERNEL_NEIGHBOURS = 1,
@@ -204,7 +206,7 @@ enum {
     RSPH_KERNEL_CONTINUITY = 6,
     RSPH_KERNEL_COUNT = 7
 };
-rsph_status rsph_set_kernel_timing(rsph_system* sys, int32_t enable);
+rsph_status rsph_set_kernel_timing(rsph_system* sys, int32_t kernel_mask);
 rsph_status rsph_read_kernel_timing(rsph_system* sys, int64_t* launches, double* ms);
 
 /* Frees the system and its device memory.  NULL is ignored. */

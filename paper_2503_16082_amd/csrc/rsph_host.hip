@@ -96,6 +96,7 @@ struct rsph_pool {
     std::string err;
     // kernel timing
     bool timing = false;
+    uint32_t timing_mask = 0;
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     int64_t t_launches[RSPH_KERNEL_COUNT] = {};
@@ -454,16 +455,18 @@ struct TimeScope {
     int kind;
     int64_t substep;
     hipEvent_t a = nullptr, b = nullptr;
-    TimeScope(rsph_pool* P_, int kind_, int64_t sub) : P(P_), kind(kind_), substep(sub)
+    bool on;
+    TimeScope(rsph_pool* P_, int kind_, int64_t sub)
+        : P(P_), kind(kind_), substep(sub), on(P_->timing && ((P_->timing_mask >> kind_) & 1u))
     {
-        if (!P->timing) return;
+        if (!on) return;
         a = take_event(P);
         b = take_event(P);
         HIPCHECK(hipEventRecord(a, P->stream));
     }
     ~TimeScope() noexcept(false)
     {
-        if (!P->timing) return;
+        if (!on) return;
         HIPCHECK(hipEventRecord(b, P->stream));
         P->pending.push_back(TimedLaunch{kind, substep, a, b});
     }
@@ -999,7 +1002,7 @@ rsph_status rsph_read_particles(rsph_system* s, int32_t field, int64_t n, double
         if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
         if (n != s->n) fail(RSPH_EINVAL, "n must equal the particle count");
         if (field < 0 || field >= RSPH_FIELD_COUNT) fail(RSPH_EINVAL, "unknown field");
-        if (field >= RSPH_FIELD_ACC && !s->rates_valid)
+        if (field >= RSPH_FIELD_ACC && field <= RSPH_FIELD_SIGMA && !s->rates_valid)
             fail(RSPH_ESTATE, "rates are read after rsph_eval_rates");
         rsph_pool* P = s->pool;
         HIPCHECK(hipStreamSynchronize(P->stream));
@@ -1057,6 +1060,11 @@ rsph_status rsph_read_particles(rsph_system* s, int32_t field, int64_t n, double
         }
         case RSPH_FIELD_NNB: {
             std::vector<int32_t> c = dl(P, A.ncount + o, n);
+            for (int64_t k = 0; k < n; ++k) tmp[k] = (double)c[k];
+            break;
+        }
+        case RSPH_FIELD_FLAGS: {
+            std::vector<uint8_t> c = dl(P, A.flags + o, n);
             for (int64_t k = 0; k < n; ++k) tmp[k] = (double)c[k];
             break;
         }
@@ -1124,6 +1132,7 @@ rsph_status rsph_set_kernel_timing(rsph_system* s, int32_t enable)
         HIPCHECK(hipStreamSynchronize(P->stream));
         collect_timing(P, INT64_MAX);
         P->timing = enable != 0;
+        P->timing_mask = (uint32_t)enable;
         for (int k = 0; k < RSPH_KERNEL_COUNT; ++k) {
             P->t_launches[k] = 0;
             P->t_ms[k] = 0.0;

@@ -29,7 +29,7 @@ KEEP_CLOCK = 1
 FIELDS = {
     "pos": 0, "vel": 1, "rho": 2, "p": 3, "drho": 4, "mass": 5, "phase": 6,
     "acc": 7, "acc_p": 8, "acc_s": 9, "acc_v": 10, "gradC": 11, "rate_drho": 12,
-    "B": 13, "dr": 14, "sigma": 15, "nnb": 16,
+    "B": 13, "dr": 14, "sigma": 15, "nnb": 16, "flags": 17,
 }
 KERNELS = ["bin", "neighbours", "advection", "shift", "colour", "force", "continuity"]
 
@@ -252,8 +252,13 @@ class System:
         _check(lib().rsph_read_neighbours(self.h, self.n, idx.shape[0], _p(start), _p(idx)), self.h)
         return start, idx[: start[-1]].copy()
 
-    def set_timing(self, enable=True):
-        _check(lib().rsph_set_kernel_timing(self.h, 1 if enable else 0), self.h)
+    def set_timing(self, kernels=None):
+        """kernels: iterable of names from KERNELS (None = all, [] = off)."""
+        names = KERNELS if kernels is None else list(kernels)
+        mask = 0
+        for k in names:
+            mask |= 1 << KERNELS.index(k)
+        _check(lib().rsph_set_kernel_timing(self.h, mask), self.h)
 
     def timing(self):
         launches = np.zeros(len(KERNELS), np.int64)
