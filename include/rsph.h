@@ -204,7 +204,9 @@ enum {
     RSPH_KERNEL_COLOUR = 4,
     RSPH_KERNEL_FORCE = 5,
     RSPH_KERNEL_CONTINUITY = 6,
-    RSPH_KERNEL_COUNT = 7
+    RSPH_KERNEL_EVENT_FLOOR = 7, /* an empty one-block kernel bracketed the same way,
+                                    launched 32 times when timing is switched on */
+    RSPH_KERNEL_COUNT = 8
 };
 rsph_status rsph_set_kernel_timing(rsph_system* sys, int32_t kernel_mask);
 rsph_status rsph_read_kernel_timing(rsph_system* sys, int64_t* launches, double* ms);

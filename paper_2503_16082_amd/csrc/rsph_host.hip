@@ -71,7 +71,7 @@ double lattice_sigma0(int dim, double h, double dp)
 
 struct TimedLaunch {
     int kind;
-    int64_t substep;  // -1: not a substep kernel
+    int64_t group;  // launch group: did work if some system was active in it
     hipEvent_t start, stop;
 };
 
@@ -90,13 +90,15 @@ struct rsph_pool {
     int S_cap = 0;
     size_t bytes = 0;
     std::vector<void*> allocs;
-    int32_t* d_flag = nullptr;  // [any active, health]
-    int32_t* h_flag = nullptr;  // pinned
     int32_t* d_mask = nullptr;
+    long long* d_targets = nullptr;
+    int32_t* work_dev = nullptr;
+    int64_t m_pred = 8;  // substeps launched per cycle
     std::string err;
     // kernel timing
     bool timing = false;
     uint32_t timing_mask = 0;
+    int64_t next_group = 0;
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     int64_t t_launches[RSPH_KERNEL_COUNT] = {};
@@ -126,19 +128,6 @@ Launch launch_of(const rsph_pool* P)
 }
 
 int kmax_of(int dim) { return dim == 2 ? kKmax2 : kKmax3; }
-
-size_t slot_bytes(int dim, int precision)
-{
-    const size_t r4 = precision == RSPH_FP64 ? 32 : 16;
-    size_t b = 0;
-    b += 2 * (3 * 8 + 3 * 8 + 8 + 8 + 8 + 4 + 4);  // state, twice
-    b += 4 + 4 + 4;                              // key rank perm
-    b += 9 * r4;                                 // geo vbuf[2] th[2] col av bm[2]
-    b += 1 + 4 + (size_t)kmax_of(dim) * 4;       // flags ncount nbr
-    b += 5 * 24 + 8 + 72 + 24 + 8;               // rates
-    b += 16 * 8 / 64 + 4 / 64 + 1;               // observables partials, wave table
-    return b;
-}
 
 void validate_params(const rsph_params* p)
 {
@@ -214,20 +203,28 @@ SysConst make_const(const rsph_params& p)
     return S;
 }
 
-template <typename T>
-T* dev_alloc(rsph_pool* P, size_t count)
-{
-    void* p = nullptr;
-    size_t b = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(RSPH_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+// Allocation plan of a pool: the same walk either allocates (P given) or only
+// sums the bytes it would allocate, so budget checks are exact.
+struct Alloc {
+    rsph_pool* P;  // nullptr: count only
+    size_t bytes = 0;
+    template <typename T>
+    T* take(size_t count)
+    {
+        const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+        bytes += b;
+        if (!P) return nullptr;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(RSPH_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+        }
+        P->allocs.push_back(p);
+        P->bytes += b;
+        return (T*)p;
     }
-    P->allocs.push_back(p);
-    P->bytes += b;
-    return (T*)p;
-}
+};
 
 void free_arrays(rsph_pool* P)
 {
@@ -239,65 +236,88 @@ void free_arrays(rsph_pool* P)
     P->S_cap = 0;
 }
 
+// Walks every device array of a pool with the capacities given.
+size_t plan_arrays(Alloc& M, int dim, int precision, DevArrays& A, int32_t*& mask, long long*& targets,
+                   int32_t*& work, int64_t Pc, int64_t Cc, int Sc)
+{
+    A = DevArrays{};
+    const size_t r4 = precision == RSPH_FP64 ? 32 : 16;
+    A.P = Pc;
+    A.C = Cc;
+    A.kmax = kmax_of(dim);
+    for (int a = 0; a < 3; ++a) {
+        A.pos[a] = M.take<double>(Pc);
+        A.vel[a] = M.take<double>(Pc);
+        A.pos2[a] = M.take<double>(Pc);
+        A.vel2[a] = M.take<double>(Pc);
+    }
+    A.rho = M.take<double>(Pc);
+    A.drho = M.take<double>(Pc);
+    A.mass = M.take<double>(Pc);
+    A.id = M.take<int32_t>(Pc);
+    A.phase = M.take<int32_t>(Pc);
+    A.rho2 = M.take<double>(Pc);
+    A.drho2 = M.take<double>(Pc);
+    A.mass2 = M.take<double>(Pc);
+    A.id2 = M.take<int32_t>(Pc);
+    A.phase2 = M.take<int32_t>(Pc);
+    A.key = M.take<uint32_t>(Pc);
+    A.rank = M.take<int32_t>(Pc);
+    A.perm = M.take<int32_t>(Pc);
+    A.tmp = M.take<int32_t>(Pc);
+    A.cell_cnt = M.take<int32_t>(Cc);
+    A.cell_start = M.take<int32_t>(Cc + 1);
+    A.cell_sys = M.take<int32_t>(Cc);
+    A.scan_part = M.take<int32_t>(2048);
+    A.wave_sys = M.take<int32_t>(Pc / kWave);
+    A.geo = M.take<char>(Pc * r4);
+    for (int k = 0; k < 2; ++k) {
+        A.vbuf[k] = M.take<char>(Pc * r4);
+        A.th[k] = M.take<char>(Pc * r4);
+        A.bm[k] = M.take<char>(Pc * r4);
+    }
+    A.col = M.take<char>(Pc * r4);
+    A.av = M.take<char>(Pc * r4);
+    A.flags = M.take<uint8_t>(Pc);
+    A.nbr = M.take<uint32_t>(Pc * (size_t)A.kmax);
+    A.ncount = M.take<int32_t>(Pc);
+    A.r_acc = M.take<double>(3 * Pc);
+    A.r_accp = M.take<double>(3 * Pc);
+    A.r_accs = M.take<double>(3 * Pc);
+    A.r_accv = M.take<double>(3 * Pc);
+    A.r_gradc = M.take<double>(3 * Pc);
+    A.r_drho = M.take<double>(Pc);
+    A.r_b = M.take<double>(9 * Pc);
+    A.r_dr = M.take<double>(3 * Pc);
+    A.r_sigma = M.take<double>(Pc);
+    A.obs_part = M.take<double>((Pc / kWave) * kObsPart);
+    A.vpart = M.take<unsigned long long>(2 * (Pc * kMaxLanes / kWave));
+    A.obs_out = M.take<double>((size_t)Sc * kObsOut);
+    A.sc = M.take<SysConst>(Sc);
+    A.sd = M.take<SysDyn>(Sc);
+    mask = M.take<int32_t>(Sc);
+    targets = M.take<long long>(Sc);
+    A.work_cap = 1 << 16;
+    A.work = nullptr;
+    work = M.take<int32_t>(A.work_cap);
+    return M.bytes;
+}
+
+size_t arrays_bytes(const rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
+{
+    Alloc M{nullptr};
+    DevArrays A;
+    int32_t* m;
+    long long* t;
+    int32_t* w;
+    return plan_arrays(M, P->dim, P->precision, A, m, t, w, Pc, Cc, Sc);
+}
+
 // Allocates every device array for the capacities given (contents undefined).
 void alloc_arrays(rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
 {
-    DevArrays& A = P->A;
-    A = DevArrays{};
-    const size_t r4 = P->precision == RSPH_FP64 ? 32 : 16;
-    A.P = Pc;
-    A.C = Cc;
-    A.kmax = kmax_of(P->dim);
-    for (int a = 0; a < 3; ++a) {
-        A.pos[a] = dev_alloc<double>(P, Pc);
-        A.vel[a] = dev_alloc<double>(P, Pc);
-        A.pos2[a] = dev_alloc<double>(P, Pc);
-        A.vel2[a] = dev_alloc<double>(P, Pc);
-    }
-    A.rho = dev_alloc<double>(P, Pc);
-    A.drho = dev_alloc<double>(P, Pc);
-    A.mass = dev_alloc<double>(P, Pc);
-    A.id = dev_alloc<int32_t>(P, Pc);
-    A.phase = dev_alloc<int32_t>(P, Pc);
-    A.rho2 = dev_alloc<double>(P, Pc);
-    A.drho2 = dev_alloc<double>(P, Pc);
-    A.mass2 = dev_alloc<double>(P, Pc);
-    A.id2 = dev_alloc<int32_t>(P, Pc);
-    A.phase2 = dev_alloc<int32_t>(P, Pc);
-    A.key = dev_alloc<uint32_t>(P, Pc);
-    A.rank = dev_alloc<int32_t>(P, Pc);
-    A.perm = dev_alloc<int32_t>(P, Pc);
-    A.cell_cnt = dev_alloc<int32_t>(P, Cc);
-    A.cell_start = dev_alloc<int32_t>(P, Cc + 1);
-    A.cell_sys = dev_alloc<int32_t>(P, Cc);
-    A.scan_part = dev_alloc<int32_t>(P, 2048);
-    A.wave_sys = dev_alloc<int32_t>(P, Pc / kWave);
-    A.geo = dev_alloc<char>(P, Pc * r4);
-    for (int k = 0; k < 2; ++k) {
-        A.vbuf[k] = dev_alloc<char>(P, Pc * r4);
-        A.th[k] = dev_alloc<char>(P, Pc * r4);
-        A.bm[k] = dev_alloc<char>(P, Pc * r4);
-    }
-    A.col = dev_alloc<char>(P, Pc * r4);
-    A.av = dev_alloc<char>(P, Pc * r4);
-    A.flags = dev_alloc<uint8_t>(P, Pc);
-    A.nbr = dev_alloc<uint32_t>(P, Pc * (size_t)A.kmax);
-    A.ncount = dev_alloc<int32_t>(P, Pc);
-    A.r_acc = dev_alloc<double>(P, 3 * Pc);
-    A.r_accp = dev_alloc<double>(P, 3 * Pc);
-    A.r_accs = dev_alloc<double>(P, 3 * Pc);
-    A.r_accv = dev_alloc<double>(P, 3 * Pc);
-    A.r_gradc = dev_alloc<double>(P, 3 * Pc);
-    A.r_drho = dev_alloc<double>(P, Pc);
-    A.r_b = dev_alloc<double>(P, 9 * Pc);
-    A.r_dr = dev_alloc<double>(P, 3 * Pc);
-    A.r_sigma = dev_alloc<double>(P, Pc);
-    A.obs_part = dev_alloc<double>(P, (Pc / kWave) * kObsPart);
-    A.obs_out = dev_alloc<double>(P, (size_t)Sc * kObsOut);
-    A.sc = dev_alloc<SysConst>(P, Sc);
-    A.sd = dev_alloc<SysDyn>(P, Sc);
-    P->d_flag = dev_alloc<int32_t>(P, 2);
-    P->d_mask = dev_alloc<int32_t>(P, Sc);
+    Alloc M{P};
+    plan_arrays(M, P->dim, P->precision, P->A, P->d_mask, P->d_targets, P->work_dev, Pc, Cc, Sc);
     P->P_cap = Pc;
     P->C_cap = Cc;
     P->S_cap = Sc;
@@ -328,12 +348,6 @@ Layout plan(const std::vector<rsph_system*>& sys, const rsph_system* extra)
     return L;
 }
 
-size_t estimate_bytes(const rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
-{
-    return (size_t)Pc * slot_bytes(P->dim, P->precision) + (size_t)Cc * 12 +
-           (size_t)Sc * (sizeof(SysConst) + sizeof(SysDyn) + kObsOut * 8 + 4) + (1 << 16);
-}
-
 // Re-packs the pool's persistent particle state after systems were added or
 // removed: every member keeps its particles, t and counters; slot ranges,
 // cell ranges and the device tables are rebuilt.
@@ -357,13 +371,24 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
         const int64_t Pc = std::max<int64_t>(L.P, P->P_cap + P->P_cap / 2 / kBlock * kBlock);
         const int64_t Cc = std::max<int64_t>(L.C, P->C_cap + P->C_cap / 2);
         const int Sc = std::max(S, P->S_cap + P->S_cap / 2 + 1);
-        const int64_t Pg = P->standalone ? L.P : Pc;
-        const int64_t Cg = P->standalone ? L.C : Cc;
-        const int Sg = P->standalone ? S : Sc;
-        if (P->budget && estimate_bytes(P, Pg, Cg, Sg) > P->budget)
+        int64_t Pg = P->standalone ? L.P : Pc;
+        int64_t Cg = P->standalone ? L.C : Cc;
+        int Sg = P->standalone ? S : Sc;
+        if (P->budget && arrays_bytes(P, Pg, Cg, Sg) > P->budget) {
+            // no head room for growth: exactly what the members need
+            Pg = L.P;
+            Cg = L.C;
+            Sg = S;
+        }
+        if (P->budget && arrays_bytes(P, Pg, Cg, Sg) > P->budget)
             fail(RSPH_EBUSY, "pool HBM budget exhausted");
         old_allocs.swap(P->allocs);
         P->bytes = 0;
+        int32_t* old_mask = P->d_mask;
+        long long* old_targets = P->d_targets;
+        int32_t* old_work = P->work_dev;
+        const int64_t oP = P->P_cap, oC = P->C_cap;
+        const int oS = P->S_cap;
         try {
             alloc_arrays(P, Pg, Cg, Sg);
         } catch (...) {
@@ -371,6 +396,12 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
             P->allocs.swap(old_allocs);
             P->bytes = old_bytes;
             P->A = old;
+            P->d_mask = old_mask;
+            P->d_targets = old_targets;
+            P->work_dev = old_work;
+            P->P_cap = oP;
+            P->C_cap = oC;
+            P->S_cap = oS;
             throw;
         }
     }
@@ -446,38 +477,50 @@ hipEvent_t take_event(rsph_pool* P)
         return e;
     }
     hipEvent_t e;
-    HIPCHECK(hipEventCreate(&e));
+    // timing-only events: no system-scope fence around the timed kernel
+    HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
 }
 
 struct TimeScope {
     rsph_pool* P;
     int kind;
-    int64_t substep;
-    hipEvent_t a = nullptr, b = nullptr;
+    int64_t group;
     bool on;
-    TimeScope(rsph_pool* P_, int kind_, int64_t sub)
-        : P(P_), kind(kind_), substep(sub), on(P_->timing && ((P_->timing_mask >> kind_) & 1u))
+    Ev ev;
+    TimeScope(rsph_pool* P_, int kind_, int64_t group_)
+        : P(P_), kind(kind_), group(group_), on(P_->timing && ((P_->timing_mask >> kind_) & 1u))
     {
         if (!on) return;
-        a = take_event(P);
-        b = take_event(P);
-        HIPCHECK(hipEventRecord(a, P->stream));
+        ev.start = take_event(P);
+        ev.stop = take_event(P);
     }
-    ~TimeScope() noexcept(false)
+    // events recorded around several launches (the binning sequence)
+    void begin_range()
     {
-        if (!on) return;
-        HIPCHECK(hipEventRecord(b, P->stream));
-        P->pending.push_back(TimedLaunch{kind, substep, a, b});
+        if (on) HIPCHECK(hipEventRecord(ev.start, P->stream));
+    }
+    void end_range()
+    {
+        if (on) HIPCHECK(hipEventRecord(ev.stop, P->stream));
+    }
+    ~TimeScope()
+    {
+        if (on) P->pending.push_back(TimedLaunch{kind, group, ev.start, ev.stop});
     }
 };
 
-// Folds recorded launches into the totals; substep launches at or beyond
-// `substeps_done` found every system idle and are dropped.
-void collect_timing(rsph_pool* P, int64_t substeps_done)
+// Folds recorded launches into the totals; launches of groups in which no
+// system had work are dropped.
+void collect_timing(rsph_pool* P)
 {
+    if (P->pending.empty() && P->next_group == 0) return;
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    std::vector<int32_t> work(std::max<int64_t>(P->next_group, 1), 0);
+    if (P->next_group > 0)
+        HIPCHECK(hipMemcpy(work.data(), P->work_dev, sizeof(int32_t) * P->next_group, hipMemcpyDeviceToHost));
     for (auto& t : P->pending) {
-        if (t.substep < 0 || t.substep < substeps_done) {
+        if (t.group < 0 || (t.group < P->next_group && work[t.group])) {
             float ms = 0.f;
             HIPCHECK(hipEventElapsedTime(&ms, t.start, t.stop));
             P->t_ms[t.kind] += ms;
@@ -487,48 +530,48 @@ void collect_timing(rsph_pool* P, int64_t substeps_done)
         P->event_pool.push_back(t.stop);
     }
     P->pending.clear();
+    if (P->next_group > 0) launch_fill_i32(launch_of(P), P->work_dev, P->next_group, 0);
+    P->next_group = 0;
 }
 
 // ---- driver ----------------------------------------------------------------
 
 void set_mask(rsph_pool* P, const std::vector<int32_t>& mask)
 {
-    HIPCHECK(hipMemcpyAsync(P->d_mask, mask.data(), sizeof(int32_t) * mask.size(),
-                            hipMemcpyHostToDevice, P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    HIPCHECK(hipMemcpy(P->d_mask, mask.data(), sizeof(int32_t) * mask.size(), hipMemcpyHostToDevice));
     launch_set_stepping(launch_of(P), P->A, P->d_mask);
 }
 
-void rebuild(rsph_pool* P, int mode)
+DevArrays kernel_view(rsph_pool* P)
 {
-    const Launch L = launch_of(P);
-    DevArrays& A = P->A;
-    A.mode = mode;
-    {
-        TimeScope t(P, RSPH_KERNEL_BIN, -1);
-        launch_bin(L, A, A.C);
-    }
-    {
-        TimeScope t(P, RSPH_KERNEL_NEIGHBOURS, -1);
-        launch_neighbours(L, A);
-    }
+    DevArrays A = P->A;
+    A.work = P->timing ? P->work_dev : nullptr;
+    return A;
 }
 
-void read_flags(rsph_pool* P, int slot, int32_t* any, uint32_t* health)
+// binning and neighbour lists for the systems whose stepping flag is set
+void rebuild(rsph_pool* P, int mode, int64_t group)
 {
-    launch_any_active(launch_of(P), P->A, slot, P->d_flag);
-    HIPCHECK(hipMemcpyAsync(P->h_flag, P->d_flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
-    HIPCHECK(hipStreamSynchronize(P->stream));
-    *any = P->h_flag[0];
-    *health = (uint32_t)P->h_flag[1];
+    const Launch L = launch_of(P);
+    DevArrays A = kernel_view(P);
+    A.mode = mode;
+    {
+        TimeScope t(P, RSPH_KERNEL_BIN, group);
+        t.begin_range();
+        launch_bin(L, A);
+        t.end_range();
+    }
+    TimeScope t(P, RSPH_KERNEL_NEIGHBOURS, group);
+    launch_neighbours(L, A, t.ev);
 }
 
 std::vector<SysDyn> read_dyn(rsph_pool* P)
 {
     std::vector<SysDyn> d(P->systems.size());
-    if (!d.empty()) {
-        HIPCHECK(hipMemcpyAsync(d.data(), P->A.sd, sizeof(SysDyn) * d.size(), hipMemcpyDeviceToHost, P->stream));
-        HIPCHECK(hipStreamSynchronize(P->stream));
-    }
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    if (!d.empty())
+        HIPCHECK(hipMemcpy(d.data(), P->A.sd, sizeof(SysDyn) * d.size(), hipMemcpyDeviceToHost));
     return d;
 }
 
@@ -536,66 +579,83 @@ constexpr uint32_t kFaultBits =
     kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident | kHealthDtCollapse;
 constexpr int64_t kMaxSubsteps = 1000000;  // per advection step
 
-// One advection step for the systems whose mask entry is 1. Returns the OR of
-// the health bits of all systems afterwards.
-uint32_t outer_step(rsph_pool* P, const std::vector<int32_t>& mask)
+// One launch cycle: the advection-step prologue for systems at a boundary,
+// then m acoustic substeps for systems inside an advection step.  Every kernel
+// checks its system's state on the device, so no host synchronisation is
+// needed between cycles.
+void launch_cycle(rsph_pool* P, int64_t m)
 {
     const Launch L = launch_of(P);
-    DevArrays& A = P->A;
-    set_mask(P, mask);
-    rebuild(P, 0);
+    if (P->timing && P->next_group + m + 1 > P->A.work_cap) collect_timing(P);
+    DevArrays A = kernel_view(P);
+    A.mode = 0;
+    const int64_t g0 = P->next_group++;
+    launch_cycle_begin(L, A, g0);
+    rebuild(P, 0, g0);
     launch_dt_advection(L, A);
     {
-        TimeScope t(P, RSPH_KERNEL_ADVECTION, -1);
-        launch_advection(L, A);
+        TimeScope t(P, RSPH_KERNEL_ADVECTION, g0);
+        launch_advection(L, A, t.ev);
     }
     {
-        TimeScope t(P, RSPH_KERNEL_SHIFT, -1);
-        launch_shift(L, A);
+        TimeScope t(P, RSPH_KERNEL_SHIFT, g0);
+        launch_shift(L, A, t.ev);
     }
-    // substep count predicted from the first acoustic step of each system
-    std::vector<SysDyn> d0 = read_dyn(P);
-    int64_t predicted = 1;
-    std::vector<long long> nsub0(d0.size());
-    for (size_t s = 0; s < d0.size(); ++s) {
-        nsub0[s] = d0[s].n_sub;
-        if (!mask[s] || !d0[s].active[0]) continue;
-        const double r = d0[s].dt_ad / d0[s].dt[0];
-        predicted = std::max<int64_t>(predicted, (int64_t)std::ceil(r * (1.0 + 1e-9)));
-    }
-    int64_t k = 0;
-    int64_t chunk = std::min<int64_t>(predicted, 4096);
-    uint32_t health = 0;
-    for (;;) {
-        for (int64_t q = 0; q < chunk; ++q, ++k) {
-            const int slot = (int)(k & 1);
-            {
-                TimeScope t(P, RSPH_KERNEL_COLOUR, k);
-                launch_colour(L, A, slot);
-            }
-            {
-                TimeScope t(P, RSPH_KERNEL_FORCE, k);
-                launch_force(L, A, slot);
-            }
-            launch_dt_substep(L, A, slot);
-            {
-                TimeScope t(P, RSPH_KERNEL_CONTINUITY, k);
-                launch_continuity(L, A, slot);
-            }
+    for (int64_t q = 0; q < m; ++q) {
+        const int64_t g = P->next_group++;
+        {
+            TimeScope t(P, RSPH_KERNEL_COLOUR, g);
+            launch_colour(L, A, t.ev);
         }
-        int32_t any = 0;
-        read_flags(P, (int)(k & 1), &any, &health);
-        if (!any || (health & kFaultBits)) break;
-        if (k >= kMaxSubsteps) fail(RSPH_ENUMERIC, "more than 1e6 acoustic substeps in one advection step");
-        chunk = std::min<int64_t>(4096, std::max<int64_t>(1, (chunk + 7) / 8));
+        {
+            TimeScope t(P, RSPH_KERNEL_FORCE, g);
+            launch_force(L, A, t.ev);
+        }
+        launch_dt_substep(L, A, g);
+        {
+            TimeScope t(P, RSPH_KERNEL_CONTINUITY, g);
+            launch_continuity(L, A, t.ev);
+        }
     }
-    if (P->timing) {
-        std::vector<SysDyn> d1 = read_dyn(P);
-        int64_t done = 0;
-        for (size_t s = 0; s < d1.size(); ++s) done = std::max<int64_t>(done, d1[s].n_sub - nsub0[s]);
-        collect_timing(P, done);
+}
+
+// Advances every system of the pool to its device-side target.  Returns the
+// OR of the health bits.
+uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
+{
+    std::vector<SysDyn> d0 = read_dyn(P);
+    int64_t cycles = std::max<int64_t>(outer_hint, 1);
+    for (;;) {
+        for (int64_t c = 0; c < cycles; ++c) launch_cycle(P, P->m_pred);
+        std::vector<SysDyn> d = read_dyn(P);
+        uint32_t health = 0;
+        int64_t remaining = 0;
+        bool pending = false;
+        double sub_per_outer = 0.0;
+        for (size_t s = 0; s < d.size(); ++s) {
+            health |= d[s].health;
+            const long long left = d[s].target - d[s].n_outer;
+            const bool inside = d[s].state == kSubstepping;
+            if (d[s].health & kFaultBits) continue;
+            if (left > 0 || inside) pending = true;
+            remaining = std::max<int64_t>(remaining, left);
+            const long long dn = d[s].n_outer - d0[s].n_outer;
+            if (dn > 0) sub_per_outer = std::max(sub_per_outer, (double)(d[s].n_sub - d0[s].n_sub) / dn);
+            if (d[s].ksub > kMaxSubsteps) fail(RSPH_ENUMERIC, "more than 1e6 acoustic substeps in one advection step");
+        }
+        if (sub_per_outer > 0) P->m_pred = std::min<int64_t>(4096, (int64_t)std::ceil(sub_per_outer));
+        // faulted systems stay idle on the device; the others run to their targets
+        if (!pending) return health;
+        cycles = std::max<int64_t>(remaining, 1);
+        d0 = d;
     }
-    return health;
+}
+
+void set_targets(rsph_pool* P, const std::vector<long long>& targets)
+{
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    HIPCHECK(hipMemcpy(P->d_targets, targets.data(), sizeof(long long) * targets.size(), hipMemcpyHostToDevice));
+    launch_set_targets(launch_of(P), P->A, P->d_targets);
 }
 
 template <typename F>
@@ -648,6 +708,7 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
                       const double* mass, const double* rho)
 {
     rsph_pool* P = s->pool;
+    HIPCHECK(hipStreamSynchronize(P->stream));
     const int64_t n = s->n;
     const int d = s->prm.dim;
     std::vector<double> buf(n);
@@ -683,20 +744,32 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
 void reset_dyn(rsph_system* s, bool keep_clock)
 {
     rsph_pool* P = s->pool;
+    HIPCHECK(hipStreamSynchronize(P->stream));
     SysDyn d{};
-    if (keep_clock) {
-        HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
-    }
+    if (keep_clock) HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
     d.health = 0;
-    d.vmax_acc[0] = d.vmax_acc[1] = 0;
-    d.active[0] = d.active[1] = 0;
     d.stepping = 0;
+    d.state = kBoundary;
+    d.ksub = 0;
     if (!keep_clock) {
         d.t = d.tau = d.dt_ad = d.dt_last = 0.0;
         d.n_sub = d.n_outer = 0;
         d.dt[0] = d.dt[1] = 0.0;
         d.vmax[0] = d.vmax[1] = 0.0;
     }
+    d.target = d.n_outer;
+    HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
+}
+
+// clears the evaluation's traces: stepping flags and the |v| accumulator
+void clear_after_rebuild(rsph_system* s)
+{
+    rsph_pool* P = s->pool;
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    SysDyn d;
+    HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
+    d.stepping = 0;
+    d.health &= ~kHealthClose;
     HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
 }
 
@@ -708,13 +781,12 @@ void check_spacing(rsph_system* s)
     std::vector<int32_t> mask(P->systems.size(), 0);
     mask[s->row] = 1;
     set_mask(P, mask);
-    rebuild(P, 1);
+    rebuild(P, 1, -1);
     HIPCHECK(hipStreamSynchronize(P->stream));
     SysDyn d;
     HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
     const uint32_t bad = d.health;
     d.health = 0;
-    d.vmax_acc[0] = d.vmax_acc[1] = 0;
     d.stepping = 0;
     HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
     if (bad & (kHealthClose | kHealthCoincident))
@@ -734,7 +806,6 @@ void make_pool(rsph_pool* P, int dim, int precision, size_t budget, void* stream
         HIPCHECK(hipStreamCreate(&P->stream));
         P->own_stream = true;
     }
-    HIPCHECK(hipHostMalloc((void**)&P->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
 }
 
 void destroy_pool(rsph_pool* P)
@@ -747,7 +818,6 @@ void destroy_pool(rsph_pool* P)
     }
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     free_arrays(P);
-    if (P->h_flag) (void)hipHostFree(P->h_flag);
     if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
 }
@@ -770,6 +840,7 @@ template <typename T>
 std::vector<T> dl(rsph_pool* P, const T* src, int64_t count)
 {
     std::vector<T> v(count);
+    HIPCHECK(hipStreamSynchronize(P->stream));
     if (count) HIPCHECK(hipMemcpy(v.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
     return v;
 }
@@ -906,20 +977,20 @@ rsph_status rsph_step(rsph_system* s, int64_t n_outer)
         if (n_outer < 0) fail(RSPH_EINVAL, "n_outer must be >= 0");
         if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
         if (s->faulted) fail(RSPH_ESTATE, "system is faulted; reset it with rsph_set_particles");
+        if (n_outer == 0) return;
         rsph_pool* P = s->pool;
-        std::vector<int32_t> mask(P->systems.size(), 0);
-        mask[s->row] = 1;
         s->rates_valid = false;
-        for (int64_t k = 0; k < n_outer; ++k) {
-            uint32_t h = outer_step(P, mask);
-            if (h & kFaultBits) {
-                s->faulted = true;
-                char buf[128];
-                std::snprintf(buf, sizeof buf, "health check tripped (bits 0x%x) in advection step", h);
-                fail(RSPH_ENUMERIC, buf);
-            }
+        std::vector<SysDyn> d = read_dyn(P);
+        std::vector<long long> targets(P->systems.size(), -1);
+        targets[s->row] = d[s->row].n_outer + n_outer;
+        set_targets(P, targets);
+        const uint32_t h = run_to_targets(P, n_outer);
+        if (h & kFaultBits) {
+            s->faulted = true;
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "health check tripped (bits 0x%x)", h);
+            fail(RSPH_ENUMERIC, buf);
         }
-        HIPCHECK(hipStreamSynchronize(P->stream));
     });
 }
 
@@ -933,22 +1004,16 @@ rsph_status rsph_eval_rates(rsph_system* s)
         std::vector<int32_t> mask(P->systems.size(), 0);
         mask[s->row] = 1;
         set_mask(P, mask);
-        rebuild(P, 1);
-        DevArrays& A = P->A;
+        rebuild(P, 1, -1);
+        DevArrays A = kernel_view(P);
+        A.work = nullptr;
         A.mode = 1;
-        launch_advection(L, A);
-        launch_shift(L, A);
-        launch_colour(L, A, 0);
-        launch_force(L, A, 0);
-        launch_continuity(L, A, 0);
-        A.mode = 0;
-        // the evaluation's |v| max is not an advection-step input
-        SysDyn d;
-        HIPCHECK(hipMemcpyAsync(&d, A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost, P->stream));
-        HIPCHECK(hipStreamSynchronize(P->stream));
-        d.vmax_acc[0] = d.vmax_acc[1] = 0;
-        d.stepping = 0;
-        HIPCHECK(hipMemcpy(A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
+        launch_advection(L, A, Ev{});
+        launch_shift(L, A, Ev{});
+        launch_colour(L, A, Ev{});
+        launch_force(L, A, Ev{});
+        launch_continuity(L, A, Ev{});
+        clear_after_rebuild(s);
         s->rates_valid = true;
     });
 }
@@ -961,12 +1026,12 @@ rsph_status rsph_read_observables(rsph_system* s, rsph_observables* out)
         if (!s->has_particles) fail(RSPH_ESTATE, "no particles");
         rsph_pool* P = s->pool;
         const Launch L = launch_of(P);
-        launch_observables(L, P->A, P->A.P / kWave);
+        launch_observables(L, P->A);
         double o[kObsOut];
         SysDyn d;
-        HIPCHECK(hipMemcpyAsync(o, P->A.obs_out + (int64_t)s->row * kObsOut, sizeof o, hipMemcpyDeviceToHost, P->stream));
-        HIPCHECK(hipMemcpyAsync(&d, P->A.sd + s->row, sizeof d, hipMemcpyDeviceToHost, P->stream));
         HIPCHECK(hipStreamSynchronize(P->stream));
+        HIPCHECK(hipMemcpy(o, P->A.obs_out + (int64_t)s->row * kObsOut, sizeof o, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof d, hipMemcpyDeviceToHost));
         std::memset(out, 0, sizeof(*out));
         out->t = d.t;
         out->n_outer = d.n_outer;
@@ -1129,13 +1194,20 @@ rsph_status rsph_set_kernel_timing(rsph_system* s, int32_t enable)
     if (!s) return RSPH_EINVAL;
     return guarded(&s->err, [&] {
         rsph_pool* P = s->pool;
-        HIPCHECK(hipStreamSynchronize(P->stream));
-        collect_timing(P, INT64_MAX);
+        collect_timing(P);
         P->timing = enable != 0;
-        P->timing_mask = (uint32_t)enable;
+        P->timing_mask = (uint32_t)enable | (1u << RSPH_KERNEL_EVENT_FLOOR);
         for (int k = 0; k < RSPH_KERNEL_COUNT; ++k) {
             P->t_launches[k] = 0;
             P->t_ms[k] = 0.0;
+        }
+        if (P->timing) {
+            // the fixed cost of a dispatch bracketed by timing events
+            for (int q = 0; q < 32; ++q) {
+                TimeScope t(P, RSPH_KERNEL_EVENT_FLOOR, -1);
+                launch_empty(launch_of(P), t.ev);
+            }
+            collect_timing(P);
         }
     });
 }
@@ -1146,7 +1218,7 @@ rsph_status rsph_read_kernel_timing(rsph_system* s, int64_t* launches, double* m
     return guarded(&s->err, [&] {
         if (!launches || !ms) fail(RSPH_EINVAL, "NULL output");
         rsph_pool* P = s->pool;
-        HIPCHECK(hipStreamSynchronize(P->stream));
+        collect_timing(P);
         for (int k = 0; k < RSPH_KERNEL_COUNT; ++k) {
             launches[k] = P->t_launches[k];
             ms[k] = P->t_ms[k];
@@ -1233,43 +1305,34 @@ rsph_status rsph_pool_step(rsph_pool* P, rsph_system* const* systems, const int6
     if (!P) return RSPH_EINVAL;
     return guarded(&P->err, [&] {
         if (count < 0 || (count > 0 && (!systems || !n_outer))) fail(RSPH_EINVAL, "bad arguments");
-        std::vector<int64_t> left(P->systems.size(), 0);
+        std::vector<SysDyn> d = read_dyn(P);
+        std::vector<long long> targets(P->systems.size(), -1);
+        int64_t most = 0;
         for (int k = 0; k < count; ++k) {
             rsph_system* s = systems[k];
             if (!s || s->pool != P || s->row < 0) fail(RSPH_EINVAL, "system is not in this pool");
             if (s->faulted) fail(RSPH_ESTATE, "a system of the batch is faulted");
             if (n_outer[k] < 0) fail(RSPH_EINVAL, "n_outer must be >= 0");
-            left[s->row] += n_outer[k];
+            const long long base = targets[s->row] >= 0 ? targets[s->row] : d[s->row].n_outer;
+            targets[s->row] = base + n_outer[k];
+            most = std::max<int64_t>(most, targets[s->row] - d[s->row].n_outer);
             s->rates_valid = false;
         }
-        for (;;) {
-            std::vector<int32_t> mask(P->systems.size(), 0);
-            bool any = false;
-            for (size_t r = 0; r < left.size(); ++r)
-                if (left[r] > 0) {
-                    mask[r] = 1;
-                    any = true;
+        if (most == 0) return;
+        set_targets(P, targets);
+        const uint32_t h = run_to_targets(P, most);
+        if (h & kFaultBits) {
+            std::vector<SysDyn> dd = read_dyn(P);
+            std::string names;
+            for (size_t r = 0; r < dd.size(); ++r)
+                if (dd[r].health & kFaultBits) {
+                    P->systems[r]->faulted = true;
+                    names += " " + std::to_string(r);
                 }
-            if (!any) break;
-            uint32_t h = outer_step(P, mask);
-            for (size_t r = 0; r < left.size(); ++r)
-                if (left[r] > 0) --left[r];
-            if (h & kFaultBits) {
-                // mark the systems whose own health tripped
-                std::vector<SysDyn> d = read_dyn(P);
-                std::string names;
-                for (size_t r = 0; r < d.size(); ++r)
-                    if (d[r].health & kFaultBits) {
-                        P->systems[r]->faulted = true;
-                        left[r] = 0;
-                        names += " " + std::to_string(r);
-                    }
-                P->err = "health check tripped in pool rows" + names;
-            }
+            P->err = "health check tripped in pool rows" + names;
+            for (int k = 0; k < count; ++k)
+                if (systems[k]->faulted) fail(RSPH_ENUMERIC, P->err);
         }
-        HIPCHECK(hipStreamSynchronize(P->stream));
-        for (int k = 0; k < count; ++k)
-            if (systems[k]->faulted) fail(RSPH_ENUMERIC, P->err);
     });
 }
 

@@ -25,6 +25,7 @@ constexpr int kBlock = 256;
 constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lattice)
 constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
 constexpr int kMaxCellsPerAxis = 1024;
+constexpr int kMaxLanes = 8;  // lanes per particle slot in the pair passes (at most)
 
 // method switches (mirror of the public RSPH_* flags)
 constexpr uint32_t kNoPenalty = 1u;
@@ -85,19 +86,32 @@ struct SysConst {
     double close2;        // (1e-3 dp)^2
 };
 
+// Advection-step state of a system (device resident, changed only by the
+// one-thread-per-system kernels):
+//   idle -> boundary (outer-step target not reached) -> substepping (after the
+//   advection-step prologue) -> ending (the substep that completes the
+//   advection step, its continuity pass still to run) -> ended -> boundary/idle.
+constexpr int32_t kIdle = 0;
+constexpr int32_t kBoundary = 1;
+constexpr int32_t kSubstepping = 2;
+constexpr int32_t kEnding = 3;
+constexpr int32_t kEnded = 4;
+
 // Per-system dynamic scalars, device resident.
 struct SysDyn {
     double dt_ad;
     double tau;
     double t;
-    double dt[2];                    // substep parity slots
+    double dt[2];                    // acoustic step of substep k at [k & 1]
     double vmax[2];                  // per fluid, of the last velocity update
-    unsigned long long vmax_acc[2];  // atomic max of |v| bit patterns (non-negative doubles)
-    int32_t active[2];               // substep parity slots
-    int32_t stepping;                // 1 while the system takes part in the current advection step
+    int32_t state;                   // kIdle ... kEnded
+    int32_t stepping;                // 1 while the advection-step prologue runs for this system
     uint32_t health;
+    int32_t pad;
+    long long ksub;                  // substeps started in the current advection step
     long long n_sub;
     long long n_outer;
+    long long target;                // advection steps to reach
     double dt_last;
 };
 
@@ -105,7 +119,7 @@ struct DevArrays {
     int64_t P;       // slot capacity (multiple of 256)
     int64_t C;       // global cell capacity
     int32_t kmax;
-    int32_t mode;    // 0 = step, 1 = evaluate rates only
+    int32_t mode;    // 0 = step, 1 = evaluate rates only (no state update)
     // FP64 state, structure of arrays
     double* pos[3];
     double* vel[3];
@@ -126,6 +140,7 @@ struct DevArrays {
     uint32_t* key;
     int32_t* rank;
     int32_t* perm;
+    int32_t* tmp;   // slots in arrival order within each cell
     int32_t* cell_cnt;
     int32_t* cell_start;  // C + 1
     int32_t* cell_sys;
@@ -154,6 +169,11 @@ struct DevArrays {
     // observables partials
     double* obs_part;
     double* obs_out;
+    // per-wave partial maxima of |v| (bit patterns), [2 w] fluid k, [2 w + 1] fluid l
+    unsigned long long* vpart;
+    // per launch group: 1 if some system did work (kernel timing)
+    int32_t* work;
+    int64_t work_cap;
     // system tables
     const SysConst* sc;
     SysDyn* sd;
@@ -167,18 +187,28 @@ struct Launch {
     int fp64;  // 1: FP64 pair loops, 0: mixed
 };
 
-void launch_bin(const Launch& L, DevArrays& A, int64_t ncells_total);
-void launch_neighbours(const Launch& L, const DevArrays& A);
-void launch_dt_advection(const Launch& L, const DevArrays& A);
-void launch_advection(const Launch& L, const DevArrays& A);
-void launch_shift(const Launch& L, const DevArrays& A);
-void launch_colour(const Launch& L, const DevArrays& A, int slot);
-void launch_force(const Launch& L, const DevArrays& A, int slot);
-void launch_dt_substep(const Launch& L, const DevArrays& A, int slot);
-void launch_continuity(const Launch& L, const DevArrays& A, int slot);
-void launch_observables(const Launch& L, const DevArrays& A, int64_t nwaves_used);
-void launch_any_active(const Launch& L, const DevArrays& A, int slot, int32_t* out);
+// optional events recorded by the dispatch itself around one kernel
+struct Ev {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
+void launch_fill_i32(const Launch& L, int32_t* p, int64_t n, int32_t v);
+void launch_empty(const Launch& L, Ev ev);
+void launch_cycle_begin(const Launch& L, const DevArrays& A, int64_t group);
 void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask);
+void launch_set_targets(const Launch& L, const DevArrays& A, const long long* targets);
+void launch_bin(const Launch& L, const DevArrays& A);
+void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev);
+void launch_dt_advection(const Launch& L, const DevArrays& A);
+int lanes_per_particle(int dim);
+void launch_advection(const Launch& L, const DevArrays& A, Ev ev);
+void launch_shift(const Launch& L, const DevArrays& A, Ev ev);
+void launch_colour(const Launch& L, const DevArrays& A, Ev ev);
+void launch_force(const Launch& L, const DevArrays& A, Ev ev);
+void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group);
+void launch_continuity(const Launch& L, const DevArrays& A, Ev ev);
+void launch_observables(const Launch& L, const DevArrays& A);
 
 constexpr int kObsPart = 16;  // partial sums per wave and pass
 constexpr int kObsOut = 32;   // reduced values per system

@@ -1,7 +1,8 @@
 // rsph_kernels.hip -- HIP kernels for gfx950 (CDNA4) of the Riemann-SPH
 // multiphase surface-tension method (arXiv 2503.16082).
 //
-// One thread per particle slot, wave64, 256-thread blocks.  Blocks are remapped
+// Pair passes use G lanes per particle slot (4 in 2D, 8 in 3D), wave64,
+// 256-thread blocks.  Blocks are remapped
 // so that each of the 8 XCDs works on one contiguous eighth of the slot range:
 // particles are cell-sorted, so neighbour gathers of a block mostly hit the L2
 // of its own XCD.  Pair loops gather-only: every particle sums its own
@@ -12,6 +13,8 @@
 // Precision forms: R = double (FP64 form) or R = float (mixed form: FP32 pair
 // arithmetic on split positions, FP64 state updates).  D = 2 or 3.
 #include <math.h>
+
+#include <hip/hip_ext.h>
 
 #include <utility>
 
@@ -196,6 +199,52 @@ __device__ __forceinline__ void flag_health(SysDyn& D, uint32_t bits)
     atomicOr(&D.health, bits);
 }
 
+// lanes per particle in the pair passes: a particle's neighbour list is split
+// over G consecutive lanes, whose partial sums are combined by a butterfly of
+// xor-shuffles (fixed order, identical in every lane of the group)
+template <int D>
+struct Lanes;
+template <>
+struct Lanes<2> {
+    static constexpr int G = 4;
+};
+template <>
+struct Lanes<3> {
+    static constexpr int G = 8;
+};
+
+template <int G>
+__device__ __forceinline__ Slot slot_of_group(const DevArrays& A, int& g)
+{
+    const int64_t t = logical_block() * kBlock + threadIdx.x;
+    g = (int)(t & (G - 1));
+    Slot c;
+    c.i = t / G;
+    c.s = -1;
+    c.lane = false;
+    if (c.i >= A.P) return c;
+    // the 64 / G slots of a wave lie in one 64-slot block, hence one system
+    int s = A.wave_sys[c.i >> 6];
+    s = __builtin_amdgcn_readfirstlane(s);
+    c.s = s;
+    if (s < 0) return c;
+    const SysConst& S = A.sc[s];
+    c.lane = c.i < S.p_off + S.p_n;
+    return c;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool substep_on(const SysDyn& D, int mode)
+{
+    return mode ? D.stepping != 0 : D.state == kSubstepping;
+}
+
 // ---------------------------------------------------------------------------
 // binning: cell key, counting sort (histogram, scan, scatter), ordering of
 // each cell by the caller's particle index, gather of the state
@@ -233,7 +282,6 @@ constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total)
 {
-    // wave inclusive scan by shuffles, then across the 4 waves
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int x = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -305,62 +353,34 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t* in, int64_
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = ex;
 }
 
+// scatter in arrival order (the cell-relative rank of the histogram atomics)
 __global__ __launch_bounds__(kBlock) void k_scatter(DevArrays A)
 {
     Slot c = slot_of(A);
     if (!c.lane) return;
+    if (!A.sd[c.s].stepping) return;
     const SysConst& S = A.sc[c.s];
-    if (!A.sd[c.s].stepping) {
-        A.perm[c.i] = (int32_t)c.i;  // frozen system: identity
-        return;
-    }
     const uint32_t key = A.key[c.i];
     const int64_t dest = S.p_off + (A.cell_start[S.c_off + key] - A.cell_start[S.c_off]) + A.rank[c.i];
-    A.perm[dest] = (int32_t)c.i;
+    A.tmp[dest] = (int32_t)c.i;
 }
 
-// Orders each cell's slots by the caller's particle index (insertion sort; cells
-// hold ~7 particles in 2D and ~18 in 3D).  One thread per global cell.
-__global__ __launch_bounds__(kBlock) void k_cellsort(DevArrays A, int64_t ncells)
+// Final, canonical order: within its cell a particle's rank is the number of
+// cell members with a smaller caller index (ids are unique), so the sorted
+// order is (cell, id) whatever order the atomics produced.
+__global__ __launch_bounds__(kBlock) void k_rank(DevArrays A)
 {
-    int64_t gc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gc >= ncells) return;
-    int s = A.cell_sys[gc];
-    if (s < 0) return;
-    if (!A.sd[s].stepping) return;
-    const SysConst& S = A.sc[s];
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    if (!A.sd[c.s].stepping) return;
+    const SysConst& S = A.sc[c.s];
+    const uint32_t key = A.key[c.i];
     const int64_t base = S.p_off - A.cell_start[S.c_off];
-    const int64_t b = base + A.cell_start[gc], e = base + A.cell_start[gc + 1];
-    constexpr int kLocal = 48;
-    if (e - b <= kLocal) {
-        int32_t sl[kLocal];
-        int32_t id[kLocal];
-        int m = (int)(e - b);
-        for (int k = 0; k < m; ++k) {
-            int32_t v = A.perm[b + k];
-            int32_t key = A.id[v];
-            int q = k;
-            while (q > 0 && id[q - 1] > key) {
-                id[q] = id[q - 1];
-                sl[q] = sl[q - 1];
-                --q;
-            }
-            id[q] = key;
-            sl[q] = v;
-        }
-        for (int k = 0; k < m; ++k) A.perm[b + k] = sl[k];
-    } else {
-        for (int64_t k = b + 1; k < e; ++k) {
-            int32_t v = A.perm[k];
-            int32_t key = A.id[v];
-            int64_t q = k;
-            while (q > b && A.id[A.perm[q - 1]] > key) {
-                A.perm[q] = A.perm[q - 1];
-                --q;
-            }
-            A.perm[q] = v;
-        }
-    }
+    const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
+    const int32_t me = A.id[c.i];
+    int r = 0;
+    for (int64_t k = b; k < e; ++k) r += A.id[A.tmp[k]] < me;
+    A.perm[b + r] = (int32_t)c.i;
 }
 
 // state gather into the second buffer, plus the per-fluid |v| max for the
@@ -370,8 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
 {
     Slot c = slot_of(A);
     if (c.s < 0) return;
+    if (!A.sd[c.s].stepping) return;  // wave-uniform
     unsigned long long m0 = 0, m1 = 0;
-    const bool stepping = A.sd[c.s].stepping;
     if (c.lane) {
         const int64_t src = A.perm[c.i];
         double v2 = 0.0;
@@ -391,13 +411,33 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
         if (ph == 0) m0 = bits;
         else m1 = bits;
     }
-    if (!stepping) return;  // wave-uniform
     m0 = wave_max_u64(m0);
     m1 = wave_max_u64(m1);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&A.sd[c.s].vmax_acc[0], m0);
-        atomicMax(&A.sd[c.s].vmax_acc[1], m1);
+        const int64_t w = c.i >> 6;
+        A.vpart[2 * w] = m0;
+        A.vpart[2 * w + 1] = m1;
     }
+}
+
+// the sorted copy back into the primary arrays (systems outside the prologue
+// are not touched)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_copyback(DevArrays A)
+{
+    Slot c = slot_of(A);
+    if (!c.lane) return;
+    if (!A.sd[c.s].stepping) return;
+    const int64_t i = c.i;
+    for (int a = 0; a < D; ++a) {
+        A.pos[a][i] = A.pos2[a][i];
+        A.vel[a][i] = A.vel2[a][i];
+    }
+    A.rho[i] = A.rho2[i];
+    A.drho[i] = A.drho2[i];
+    A.mass[i] = A.mass2[i];
+    A.id[i] = A.id2[i];
+    A.phase[i] = A.phase2[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -408,22 +448,33 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
 {
-    Slot c = slot_of(A);
-    if (!c.lane) return;
+    // the candidates of a stencil cell are tested G at a time by the lanes of
+    // the particle's group; an ordered ballot keeps the list in candidate
+    // order (stencil cells in a fixed order, slots ascending within a cell)
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
+    if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
-    if (!Dy.stepping) return;
+    if (!Dy.stepping) return;  // wave-uniform
     const SysConst& S = A.sc[c.s];
     const int64_t i = c.i;
+    const bool live = c.lane;
+    const int gshift = (threadIdx.x & 63) & ~(G - 1);
+    const uint32_t below = (1u << g) - 1u;
     const int64_t base = S.p_off - A.cell_start[S.c_off];
     double xi[3] = {0.0, 0.0, 0.0};
     int ci[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) {
-        xi[a] = A.pos[a][i];
-        ci[a] = cell_of(xi[a], S, a);
+    int ph = 0;
+    if (live) {
+        for (int a = 0; a < D; ++a) {
+            xi[a] = A.pos[a][i];
+            ci[a] = cell_of(xi[a], S, a);
+        }
+        ph = A.phase[i];
     }
-    const int ph = A.phase[i];
     int cnt = 0;
-    bool cross = false, coincident = false, close = false;
+    int cross = 0, coincident = 0, close = 0;
     double wsum = 0.0;
     uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
     const int zr = D == 3 ? 1 : 0;
@@ -444,37 +495,55 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                 double kx = 0.0;
                 if (cx < 0) { cx += S.ncell[0]; kx = -S.box[0]; }
                 else if (cx >= S.ncell[0]) { cx -= S.ncell[0]; kx = S.box[0]; }
-                const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
-                const int64_t jb = base + A.cell_start[gc], je = base + A.cell_start[gc + 1];
-                for (int64_t j = jb; j < je; ++j) {
-                    if (j == i) continue;
-                    // the neighbour predicate, one rounding per operation: the
-                    // image shift is the periodic wrap of the stencil cell
-                    // (the minimum image for every pair closer than 2h)
-                    // x_i - x_j, then minus the image shift, squares summed in axis order
-                    double d = __dsub_rn(xi[0], A.pos[0][j]);
-                    if (kx != 0.0) d = __dsub_rn(d, kx);
-                    double r2 = __dmul_rn(d, d);
-                    d = __dsub_rn(xi[1], A.pos[1][j]);
-                    if (ky != 0.0) d = __dsub_rn(d, ky);
-                    r2 = __dadd_rn(r2, __dmul_rn(d, d));
-                    if (D == 3) {
-                        d = __dsub_rn(xi[2], A.pos[2][j]);
-                        if (kz != 0.0) d = __dsub_rn(d, kz);
+                int64_t jb = 0, je = 0;
+                if (live) {
+                    const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
+                    jb = base + A.cell_start[gc];
+                    je = base + A.cell_start[gc + 1];
+                }
+                for (int64_t j0 = jb; j0 < je; j0 += G) {
+                    const int64_t j = j0 + g;
+                    bool hit = false;
+                    double r2 = 0.0;
+                    if (j < je && j != i) {
+                        // the neighbour predicate, one rounding per operation:
+                        // x_i - x_j, minus the periodic image offset of the stencil
+                        // cell (the minimum image for every pair closer than 2h),
+                        // squares summed in axis order
+                        double d = __dsub_rn(xi[0], A.pos[0][j]);
+                        if (kx != 0.0) d = __dsub_rn(d, kx);
+                        r2 = __dmul_rn(d, d);
+                        d = __dsub_rn(xi[1], A.pos[1][j]);
+                        if (ky != 0.0) d = __dsub_rn(d, ky);
                         r2 = __dadd_rn(r2, __dmul_rn(d, d));
+                        if (D == 3) {
+                            d = __dsub_rn(xi[2], A.pos[2][j]);
+                            if (kz != 0.0) d = __dsub_rn(d, kz);
+                            r2 = __dadd_rn(r2, __dmul_rn(d, d));
+                        }
+                        hit = r2 < S.cut2;
                     }
-                    if (r2 < S.cut2) {
-                        if (cnt < A.kmax) out[(int64_t)cnt * kWave] = (uint32_t)j;
-                        ++cnt;
+                    const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
+                    if (hit) {
+                        const int at = cnt + __popc(gm & below);
+                        if (at < A.kmax) out[(int64_t)at * kWave] = (uint32_t)j;
                         wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
                         cross |= A.phase[j] != ph;
                         coincident |= r2 < S.coincident2;
                         close |= r2 < S.close2;
                     }
+                    cnt += __popc(gm);
                 }
             }
         }
     }
+    wsum = group_sum<G>(wsum);
+    for (int o = 1; o < G; o <<= 1) {
+        cross |= __shfl_xor(cross, o, 64);
+        coincident |= __shfl_xor(coincident, o, 64);
+        close |= __shfl_xor(close, o, 64);
+    }
+    if (!live || g != 0) return;
     if (cnt > A.kmax) {
         flag_health(Dy, kHealthNeighbours);
         cnt = A.kmax;
@@ -511,9 +580,11 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
 {
-    Slot c = slot_of(A);
-    if (!c.lane) return;
-    if (!A.sd[c.s].stepping) return;
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
+    if (c.s < 0) return;
+    if (!A.sd[c.s].stepping) return;  // wave-uniform
     const SysConst& S = A.sc[c.s];
     const int64_t i = c.i;
     const Q4<R>* geo = (const Q4<R>*)A.geo;
@@ -521,16 +592,20 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     const Q4<R>* vb = (const Q4<R>*)A.vbuf[0];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    const Q4<R> gi = geo[i];
-    const Q4<R> vi = vb[i];
-    const int phi = Geo<R>::phase(gi);
-    const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
-    const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
     R av[3] = {0, 0, 0};
     R M[6] = {0, 0, 0, 0, 0, 0};  // 00 01 02 11 12 22
-    uint8_t near = A.flags[i] & kFlagInterface;
-    const int cnt = A.ncount[i];
-    for (int k = 0; k < cnt; ++k) {
+    int near = 0;
+    Q4<R> gi{0, 0, 0, 0}, vi{0, 0, 0, 0};
+    int cnt = 0, phi = 0;
+    if (c.lane) {
+        gi = geo[i];
+        vi = vb[i];
+        phi = Geo<R>::phase(gi);
+        cnt = A.ncount[i];
+    }
+    const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
+    const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
+    for (int k = g; k < cnt; k += G) {
         const uint32_t j = nbr_at(A, i, k);
         const Q4<R> gj = geo[j];
         R r[3];
@@ -547,17 +622,28 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
         av[0] += f * (vi.x - vj.x);
         av[1] += f * (vi.y - vj.y);
         if (D == 3) av[2] += f * (vi.z - vj.z);
-        const R g = dW * Vj * inv_r;
-        M[0] += g * r[0] * r[0];
-        M[1] += g * r[0] * r[1];
-        M[3] += g * r[1] * r[1];
+        const R gg = dW * Vj * inv_r;
+        M[0] += gg * r[0] * r[0];
+        M[1] += gg * r[0] * r[1];
+        M[3] += gg * r[1] * r[1];
         if (D == 3) {
-            M[2] += g * r[0] * r[2];
-            M[4] += g * r[1] * r[2];
-            M[5] += g * r[2] * r[2];
+            M[2] += gg * r[0] * r[2];
+            M[4] += gg * r[1] * r[2];
+            M[5] += gg * r[2] * r[2];
         }
         near |= A.flags[j] & kFlagInterface;
     }
+    for (int a = 0; a < D; ++a) av[a] = group_sum<G>(av[a]);
+    M[0] = group_sum<G>(M[0]);
+    M[1] = group_sum<G>(M[1]);
+    M[3] = group_sum<G>(M[3]);
+    if (D == 3) {
+        M[2] = group_sum<G>(M[2]);
+        M[4] = group_sum<G>(M[4]);
+        M[5] = group_sum<G>(M[5]);
+    }
+    for (int o = 1; o < G; o <<= 1) near |= __shfl_xor(near, o, 64);
+    if (!c.lane || g != 0) return;
     const R two_over_rho = R(2) / th[i].x;
     Q4<R> a4{two_over_rho * av[0], two_over_rho * av[1], two_over_rho * av[2], (R)0};
     ((Q4<R>*)A.av)[i] = a4;
@@ -585,13 +671,13 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
         const R c22 = M[0] * M[3] - M[1] * M[1];
         const R det = M[0] * c00 + M[1] * c01 + M[2] * c02;
         if (det != R(0) && isfinite((double)det)) {
-            const R s = R(-1) / det;
-            B[0] = s * c00;
-            B[1] = s * c01;
-            B[2] = s * c02;
-            B[3] = s * c11;
-            B[4] = s * c12;
-            B[5] = s * c22;
+            const R sc = R(-1) / det;
+            B[0] = sc * c00;
+            B[1] = sc * c01;
+            B[2] = sc * c02;
+            B[3] = sc * c11;
+            B[4] = sc * c12;
+            B[5] = sc * c22;
         } else {
             B[0] = B[3] = B[5] = R(1);
             B[1] = B[2] = B[4] = R(0);
@@ -617,8 +703,10 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
 {
-    Slot c = slot_of(A);
-    if (!c.lane) return;
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
+    if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
     if (!Dy.stepping) return;
     const SysConst& S = A.sc[c.s];
@@ -629,11 +717,16 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
     const Q4<R>* b1 = (const Q4<R>*)A.bm[1];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    const Q4<R> gi = geo[i];
-    const Q4<R> Bi0 = b0[i], Bi1 = b1[i];
+    Q4<R> gi{0, 0, 0, 0}, Bi0{0, 0, 0, 0}, Bi1{0, 0, 0, 0};
+    int cnt = 0;
+    if (c.lane) {
+        gi = geo[i];
+        Bi0 = b0[i];
+        Bi1 = b1[i];
+        cnt = A.ncount[i];
+    }
     R s[3] = {0, 0, 0};
-    const int cnt = A.ncount[i];
-    for (int k = 0; k < cnt; ++k) {
+    for (int k = g; k < cnt; k += G) {
         const uint32_t j = nbr_at(A, i, k);
         const Q4<R> gj = geo[j];
         R r[3];
@@ -654,6 +747,8 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
             s[2] += f * (m02 * r[0] + m12 * r[1] + m22 * r[2]);
         }
     }
+    for (int a = 0; a < D; ++a) s[a] = group_sum<G>(s[a]);
+    if (!c.lane || g != 0) return;
     double dr[3];
     for (int a = 0; a < 3; ++a) dr[a] = a < D ? -S.alpha_h2 * (double)s[a] : 0.0;
     Q4<R>* th0 = (Q4<R>*)A.th[0];
@@ -674,7 +769,8 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
 }
 
 // ---------------------------------------------------------------------------
-// time steps (Eqs. 16-18), one thread per system
+// advection-step state machine and time steps (Eqs. 16-18): one thread per
+// system
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double dt_acoustic(const SysConst& S, const double* vmax)
@@ -685,22 +781,84 @@ __device__ __forceinline__ double dt_acoustic(const SysConst& S, const double* v
     return dt;
 }
 
-__global__ void k_dt_advection(DevArrays A)
+__device__ __forceinline__ bool dt_collapsed(const SysConst& S, double dt_ac)
+{
+    return !(dt_ac > 1e-12 * S.cfl_ac * S.h * S.inv_c0);
+}
+
+// start of a launch cycle: systems that finished an advection step go back to
+// the boundary (or to idle once their target is reached); systems at the
+// boundary with steps left run the prologue of this cycle
+__global__ void k_cycle_begin(DevArrays A, int64_t group)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.nsys) return;
     SysDyn& D = A.sd[s];
+    int st = D.state;
+    if (st == kEnding || st == kEnded) st = kBoundary;
+    if (st == kBoundary && D.n_outer >= D.target) st = kIdle;
+    if (st == kIdle && D.n_outer < D.target) st = kBoundary;
+    if (st == kBoundary && (D.health & ~kHealthClose)) st = kIdle;  // faulted: stop
+    D.state = st;
+    D.stepping = st == kBoundary;
+    if (D.stepping && A.work) atomicOr(A.work + group, 1);
+}
+
+__global__ void k_set_stepping(DevArrays A, const int32_t* mask)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < A.nsys) A.sd[s].stepping = mask[s];
+}
+
+__global__ void k_set_targets(DevArrays A, const long long* targets)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < A.nsys && targets[s] >= 0) A.sd[s].target = targets[s];
+}
+
+// per-fluid max |v| of one system from its partials: one entry per
+// `slots_per_entry` slots (64 for the per-wave partials of the gather, 256 / G
+// for the per-block partials of the force pass); one 256-thread block per
+// system, result in every thread
+__device__ __forceinline__ void reduce_vmax(const DevArrays& A, const SysConst& S, int slots_per_entry,
+                                            double* vmax)
+{
+    __shared__ unsigned long long red[2 * (kBlock / kWave)];
+    const int64_t e0 = S.p_off / slots_per_entry;
+    const int64_t e1 = (S.p_off + ((S.p_n + kWave - 1) / kWave) * kWave) / slots_per_entry;
+    unsigned long long m0 = 0, m1 = 0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+        const unsigned long long a = A.vpart[2 * e], b = A.vpart[2 * e + 1];
+        m0 = a > m0 ? a : m0;
+        m1 = b > m1 ? b : m1;
+    }
+    m0 = wave_max_u64(m0);
+    m1 = wave_max_u64(m1);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * wv] = m0;
+        red[2 * wv + 1] = m1;
+    }
+    __syncthreads();
+    for (int k = 0; k < kBlock / kWave; ++k) {
+        m0 = red[2 * k] > m0 ? red[2 * k] : m0;
+        m1 = red[2 * k + 1] > m1 ? red[2 * k + 1] : m1;
+    }
+    vmax[0] = __longlong_as_double((long long)m0);
+    vmax[1] = __longlong_as_double((long long)m1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dt_advection(DevArrays A)
+{
+    const int s = blockIdx.x;
+    SysDyn& D = A.sd[s];
     const SysConst& S = A.sc[s];
-    if (!D.stepping) {
-        D.active[0] = D.active[1] = 0;
-        return;
-    }
+    if (!D.stepping) return;  // block-uniform
     double vmax[2];
-    for (int f = 0; f < 2; ++f) {
-        vmax[f] = __longlong_as_double((long long)D.vmax_acc[f]);
-        D.vmax[f] = vmax[f];
-        D.vmax_acc[f] = 0ull;
-    }
+    reduce_vmax(A, S, kWave, vmax);
+    if (threadIdx.x != 0) return;
+    D.vmax[0] = vmax[0];
+    D.vmax[1] = vmax[1];
     double dt_ad = INFINITY;
     for (int f = 0; f < 2; ++f) {
         double a = vmax[f] > 0.0 ? S.h / vmax[f] : INFINITY;
@@ -711,67 +869,52 @@ __global__ void k_dt_advection(DevArrays A)
     if (!isfinite(dt_ad)) dt_ad = dt_ac;
     D.dt_ad = dt_ad;
     D.tau = 0.0;
+    D.ksub = 0;
     D.dt[0] = fmin(dt_ac, dt_ad);
-    D.active[0] = 1;
-    D.active[1] = 0;
-    if (!(dt_ac > 1e-12 * S.cfl_ac * S.h * S.inv_c0) || !(dt_ad > 0.0)) {
+    D.state = kSubstepping;
+    if (dt_collapsed(S, dt_ac) || !(dt_ad > 0.0)) {
         atomicOr(&D.health, kHealthDtCollapse);
-        D.active[0] = 0;
+        D.state = kIdle;
     }
 }
 
-__global__ void k_dt_substep(DevArrays A, int slot)
+// after the force pass of substep k: advance the clock, choose the step of
+// substep k + 1 or end the advection step
+__global__ __launch_bounds__(kBlock) void k_dt_substep(DevArrays A, int64_t group, int G)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= A.nsys) return;
+    const int s = blockIdx.x;
     SysDyn& D = A.sd[s];
     const SysConst& S = A.sc[s];
-    if (!D.active[slot]) {
-        D.active[slot ^ 1] = 0;
+    const int st = D.state;
+    if (st == kEnding) {
+        if (threadIdx.x == 0) D.state = kEnded;
         return;
     }
-    const double dt = D.dt[slot];
+    if (st != kSubstepping) return;  // block-uniform
+    double vmax[2];
+    reduce_vmax(A, S, kBlock / G, vmax);
+    if (threadIdx.x != 0) return;
+    if (A.work) atomicOr(A.work + group, 1);
+    const long long k = D.ksub;
+    const double dt = D.dt[k & 1];
     D.tau += dt;
     D.t += dt;
     D.n_sub += 1;
+    D.ksub = k + 1;
     D.dt_last = dt;
-    double vmax[2];
-    for (int f = 0; f < 2; ++f) {
-        vmax[f] = __longlong_as_double((long long)D.vmax_acc[f]);
-        D.vmax[f] = vmax[f];
-        D.vmax_acc[f] = 0ull;
-    }
+    D.vmax[0] = vmax[0];
+    D.vmax[1] = vmax[1];
     const double dt_ac = dt_acoustic(S, vmax);
-    if (!(dt_ac > 1e-12 * S.cfl_ac * S.h * S.inv_c0)) {
-        // time-step collapse (or NaN): stop this system, the host reports a fault
+    if (dt_collapsed(S, dt_ac) || (D.health & kHealthNonFinite)) {
         atomicOr(&D.health, kHealthDtCollapse);
-        D.active[slot ^ 1] = 0;
+        D.state = kEnding;
+        D.n_outer += 1;
     } else if (D.tau < D.dt_ad * (1.0 - 1e-12)) {
-        D.dt[slot ^ 1] = fmin(dt_ac, D.dt_ad - D.tau);
-        D.active[slot ^ 1] = 1;
+        D.dt[(k + 1) & 1] = fmin(dt_ac, D.dt_ad - D.tau);
     } else {
-        D.active[slot ^ 1] = 0;
+        D.state = kEnding;
         D.n_outer += 1;
     }
-}
-
-__global__ void k_set_stepping(DevArrays A, const int32_t* mask)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < A.nsys) A.sd[s].stepping = mask[s];
-}
-
-__global__ void k_any_active(DevArrays A, int slot, int32_t* out)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t any = 0;
-    uint32_t health = 0;
-    for (int s = 0; s < A.nsys; ++s) {
-        any |= A.sd[s].active[slot];
-        health |= A.sd[s].health;
-    }
-    out[0] = any;
-    out[1] = (int32_t)health;
 }
 
 // ---------------------------------------------------------------------------
@@ -779,26 +922,32 @@ __global__ void k_any_active(DevArrays A, int slot, int32_t* out)
 // ---------------------------------------------------------------------------
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_colour(DevArrays A, int slot)
+__global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 {
-    Slot c = slot_of(A);
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
     if (c.s < 0) return;
-    if (!A.sd[c.s].active[slot] && A.mode == 0) return;
-    if (!c.lane) return;
+    const SysDyn& Dy = A.sd[c.s];
+    if (!substep_on(Dy, A.mode)) return;
     const int64_t i = c.i;
-    if (!(A.flags[i] & kFlagInterface)) return;
+    const bool on = c.lane && (A.flags[i] & kFlagInterface);
+    if (!__any(on)) return;  // wave without interface particles
     const SysConst& S = A.sc[c.s];
+    const int slot = A.mode ? 0 : (int)(Dy.ksub & 1);
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    const Q4<R> gi = geo[i];
-    const int phi = Geo<R>::phase(gi);
-    // 2 phi_i = 2 rho0_i / (rho0_i + rho0_j) for a neighbour of the other fluid
-    const R two_phi = (R)(2.0 * S.rho0[phi] / (S.rho0[0] + S.rho0[1]));
-    R g[3] = {0, 0, 0};
-    const int cnt = A.ncount[i];
-    for (int k = 0; k < cnt; ++k) {
+    Q4<R> gi{0, 0, 0, 0};
+    int cnt = 0, phi = 0;
+    if (on) {
+        gi = geo[i];
+        phi = Geo<R>::phase(gi);
+        cnt = A.ncount[i];
+    }
+    R gsum[3] = {0, 0, 0};
+    for (int k = g; k < cnt; k += G) {
         const uint32_t j = nbr_at(A, i, k);
         const Q4<R> gj = geo[j];
         if (Geo<R>::phase(gj) == phi) continue;
@@ -807,16 +956,20 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A, int slot)
         const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         const R inv_r = rsqrt_r<R>(r2);
         const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * th[j].y * inv_r;
-        g[0] += f * r[0];
-        g[1] += f * r[1];
-        if (D == 3) g[2] += f * r[2];
+        gsum[0] += f * r[0];
+        gsum[1] += f * r[1];
+        if (D == 3) gsum[2] += f * r[2];
     }
-    for (int a = 0; a < D; ++a) g[a] *= two_phi;
-    const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    for (int a = 0; a < D; ++a) gsum[a] = group_sum<G>(gsum[a]);
+    if (!on || g != 0) return;
+    // 2 phi_i = 2 rho0_i / (rho0_i + rho0_j) for a neighbour of the other fluid
+    const R two_phi = (R)(2.0 * S.rho0[phi] / (S.rho0[0] + S.rho0[1]));
+    for (int a = 0; a < D; ++a) gsum[a] *= two_phi;
+    const R gg = gsum[0] * gsum[0] + gsum[1] * gsum[1] + gsum[2] * gsum[2];
     const R invg = gg > R(0) ? rsqrt_r<R>(gg) : R(0);
-    ((Q4<R>*)A.col)[i] = Q4<R>{g[0], g[1], g[2], invg};
+    ((Q4<R>*)A.col)[i] = Q4<R>{gsum[0], gsum[1], gsum[2], invg};
     if (A.mode == 1)
-        for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = a < D ? (double)g[a] : 0.0;
+        for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = a < D ? (double)gsum[a] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -825,123 +978,134 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A, int slot)
 // ---------------------------------------------------------------------------
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_force(DevArrays A, int slot)
+__global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 {
-    Slot c = slot_of(A);
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
-    if (A.mode == 0 && !Dy.active[slot]) return;  // wave-uniform
+    if (!substep_on(Dy, A.mode)) return;  // wave-uniform
     const SysConst& S = A.sc[c.s];
     const int64_t i = c.i;
-    unsigned long long m0 = 0, m1 = 0;
+    const int64_t kk = A.mode ? 0 : Dy.ksub;
+    const int slot = (int)(kk & 1);
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* th = (const Q4<R>*)A.th[slot];
+    const Q4<R>* vin = (const Q4<R>*)A.vbuf[slot];
+    const Q4<R>* col = (const Q4<R>*)A.col;
+    R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
+    const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
+    const R c0 = (R)S.c0, inv_c0 = (R)S.inv_c0;
+    Q4<R> gi{0, 0, 0, 0}, ti{1, 0, 0, 0}, vi{0, 0, 0, 0}, ci{0, 0, 0, 0};
+    int cnt = 0, phi = 0;
+    bool surface = false;
     if (c.lane) {
-        const Q4<R>* geo = (const Q4<R>*)A.geo;
-        const Q4<R>* th = (const Q4<R>*)A.th[slot];
-        const Q4<R>* vin = (const Q4<R>*)A.vbuf[slot];
-        const Q4<R>* col = (const Q4<R>*)A.col;
-        R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
-        const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-        const R c0 = (R)S.c0, inv_c0 = (R)S.inv_c0;
-        const Q4<R> gi = geo[i];
-        const Q4<R> ti = th[i];
-        const Q4<R> vi = vin[i];
-        const int phi = Geo<R>::phase(gi);
-        const bool surface = (A.flags[i] & kFlagNearInterface) && !(S.flags & kNoSurface);
-        const bool penalty = !(S.flags & kNoPenalty);
-        const bool single = (S.flags & kGbarSingleField) != 0;
-        const bool r3 = (S.flags & kPenaltyR3) != 0;
-        const R gamma = (R)S.gamma;
-        const R xg = (R)(S.xi * S.gamma);
-        const R rho0_i = (R)S.rho0[phi], rho0_o = (R)S.rho0[phi ^ 1];
-        const R phi_i_x = rho0_i / (rho0_i + rho0_o);  // phi_i for a cross pair
-        const R phi_j_x = rho0_o / (rho0_i + rho0_o);
-        const R pen_x = R(-4) * phi_i_x * phi_j_x * xg;
-        Q4<R> ci{0, 0, 0, 0};
+        gi = geo[i];
+        ti = th[i];
+        vi = vin[i];
+        phi = Geo<R>::phase(gi);
+        cnt = A.ncount[i];
+        surface = (A.flags[i] & kFlagNearInterface) && !(S.flags & kNoSurface);
         if (surface) ci = col[i];
-        const R gni = (ci.x * ci.x + ci.y * ci.y + ci.z * ci.z) * ci.w;  // |grad C_i|
-        R sp[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
-        const int cnt = A.ncount[i];
-        for (int k = 0; k < cnt; ++k) {
-            const uint32_t j = nbr_at(A, i, k);
-            const Q4<R> gj = geo[j];
-            R r[3];
-            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
-            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const R inv_r = rsqrt_r<R>(r2);
-            const R rr = r2 * inv_r;
-            const R dW = wendland_dw<R>(rr * inv_h, coef);
-            const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
-            const Q4<R> tj = th[j];
-            const Q4<R> vj = vin[j];
-            const R Vj = tj.y;
-            // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
-            const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
-            const R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
-            const R dU = UL - UR;
-            const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
-            const R Pstar = (ti.x * tj.z + tj.x * ti.z + beta * c0 * ti.x * tj.x * dU) /
-                            (ti.x + tj.x);
-            const R fp = Pstar * dW * Vj;
-            sp[0] += fp * e[0];
-            sp[1] += fp * e[1];
-            if (D == 3) sp[2] += fp * e[2];
-            if (!surface) continue;
-            const bool same = Geo<R>::phase(gj) == phi;
-            const Q4<R> cj = col[j];
-            const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
-            // Pi e = gamma (|g| e - g (g . e) / |g|)
-            const R gie = (ci.x * e[0] + ci.y * e[1] + ci.z * e[2]) * ci.w;
-            const R gje = (cj.x * e[0] + cj.y * e[1] + cj.z * e[2]) * cj.w;
-            const R wi = same ? R(1) : R(2) * phi_j_x;
-            const R wj = same ? R(1) : R(2) * phi_i_x;
-            R se[3];
-            se[0] = gamma * (wi * (gni * e[0] - ci.x * gie) + wj * (gnj * e[0] - cj.x * gje));
-            se[1] = gamma * (wi * (gni * e[1] - ci.y * gie) + wj * (gnj * e[1] - cj.y * gje));
-            se[2] = gamma * (wi * (gni * e[2] - ci.z * gie) + wj * (gnj * e[2] - cj.z * gje));
-            const R fs = dW * Vj;
-            ss[0] += fs * se[0];
-            ss[1] += fs * se[1];
-            if (D == 3) ss[2] += fs * se[2];
-            if (!penalty) continue;
-            // Eq. 27 and Eq. 30 (reading R1): Chat grad W = dW [C e - (gbar.r) gbar/|gbar|]
-            const R sgn = (single && !same) ? R(-1) : R(1);
-            const R gb[3] = {R(0.5) * (ci.x + sgn * cj.x), R(0.5) * (ci.y + sgn * cj.y),
-                             R(0.5) * (ci.z + sgn * cj.z)};
-            const R gb2 = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
-            const R gbr = gb[0] * r[0] + gb[1] * r[1] + gb[2] * r[2];
-            const R inv_gb = gb2 > R(0) ? rsqrt_r<R>(gb2) : R(0);
-            const R C = same ? R(0) : R(1);
-            R q[3];
-            if (r3) {
-                const R sc = dW * (C - gbr * gbr * inv_gb * inv_r);
-                q[0] = sc * e[0];
-                q[1] = sc * e[1];
-                q[2] = sc * e[2];
-            } else {
-                const R t = gbr * inv_gb;
-                q[0] = dW * (C * e[0] - t * gb[0]);
-                q[1] = dW * (C * e[1] - t * gb[1]);
-                q[2] = dW * (C * e[2] - t * gb[2]);
-            }
-            // Nbar q = (n_i (n_i . q) + n_j (n_j . q)) / 2 with n = g / |g|
-            const R niq = (ci.x * q[0] + ci.y * q[1] + ci.z * q[2]) * ci.w * ci.w;
-            const R njq = (cj.x * q[0] + cj.y * q[1] + cj.z * q[2]) * cj.w * cj.w;
-            R Nq[3];
-            Nq[0] = R(0.5) * (ci.x * niq + cj.x * njq);
-            Nq[1] = R(0.5) * (ci.y * niq + cj.y * njq);
-            Nq[2] = R(0.5) * (ci.z * niq + cj.z * njq);
-            const R pc = (same ? xg : pen_x) * inv_r * Vj;
-            if (same) {
-                // Tbar q = q - Nbar q
-                ss[0] += pc * (q[0] - Nq[0]);
-                ss[1] += pc * (q[1] - Nq[1]);
-                if (D == 3) ss[2] += pc * (q[2] - Nq[2]);
-            } else {
-                ss[0] += pc * Nq[0];
-                ss[1] += pc * Nq[1];
-                if (D == 3) ss[2] += pc * Nq[2];
-            }
+    }
+    const bool penalty = !(S.flags & kNoPenalty);
+    const bool single = (S.flags & kGbarSingleField) != 0;
+    const bool r3 = (S.flags & kPenaltyR3) != 0;
+    const R gamma = (R)S.gamma;
+    const R xg = (R)(S.xi * S.gamma);
+    const R rho0_i = (R)S.rho0[phi], rho0_o = (R)S.rho0[phi ^ 1];
+    const R phi_i_x = rho0_i / (rho0_i + rho0_o);  // phi_i for a cross pair
+    const R phi_j_x = rho0_o / (rho0_i + rho0_o);
+    const R pen_x = R(-4) * phi_i_x * phi_j_x * xg;
+    const R gni = (ci.x * ci.x + ci.y * ci.y + ci.z * ci.z) * ci.w;  // |grad C_i|
+    R sp[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+    for (int k = g; k < cnt; k += G) {
+        const uint32_t j = nbr_at(A, i, k);
+        const Q4<R> gj = geo[j];
+        R r[3];
+        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const R inv_r = rsqrt_r<R>(r2);
+        const R rr = r2 * inv_r;
+        const R dW = wendland_dw<R>(rr * inv_h, coef);
+        const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+        const Q4<R> tj = th[j];
+        const Q4<R> vj = vin[j];
+        const R Vj = tj.y;
+        // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
+        const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
+        const R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
+        const R dU = UL - UR;
+        const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
+        const R Pstar = (ti.x * tj.z + tj.x * ti.z + beta * c0 * ti.x * tj.x * dU) / (ti.x + tj.x);
+        const R fp = Pstar * dW * Vj;
+        sp[0] += fp * e[0];
+        sp[1] += fp * e[1];
+        if (D == 3) sp[2] += fp * e[2];
+        if (!surface) continue;
+        const bool same = Geo<R>::phase(gj) == phi;
+        const Q4<R> cj = col[j];
+        const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
+        // Pi e = gamma (|g| e - g (g . e) / |g|)
+        const R gie = (ci.x * e[0] + ci.y * e[1] + ci.z * e[2]) * ci.w;
+        const R gje = (cj.x * e[0] + cj.y * e[1] + cj.z * e[2]) * cj.w;
+        const R wi = same ? R(1) : R(2) * phi_j_x;
+        const R wj = same ? R(1) : R(2) * phi_i_x;
+        R se[3];
+        se[0] = gamma * (wi * (gni * e[0] - ci.x * gie) + wj * (gnj * e[0] - cj.x * gje));
+        se[1] = gamma * (wi * (gni * e[1] - ci.y * gie) + wj * (gnj * e[1] - cj.y * gje));
+        se[2] = gamma * (wi * (gni * e[2] - ci.z * gie) + wj * (gnj * e[2] - cj.z * gje));
+        const R fs = dW * Vj;
+        ss[0] += fs * se[0];
+        ss[1] += fs * se[1];
+        if (D == 3) ss[2] += fs * se[2];
+        if (!penalty) continue;
+        // Eq. 27 and Eq. 30 (reading R1): Chat grad W = dW [C e - (gbar.r) gbar/|gbar|]
+        const R sgn = (single && !same) ? R(-1) : R(1);
+        const R gb[3] = {R(0.5) * (ci.x + sgn * cj.x), R(0.5) * (ci.y + sgn * cj.y),
+                         R(0.5) * (ci.z + sgn * cj.z)};
+        const R gb2 = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
+        const R gbr = gb[0] * r[0] + gb[1] * r[1] + gb[2] * r[2];
+        const R inv_gb = gb2 > R(0) ? rsqrt_r<R>(gb2) : R(0);
+        const R C = same ? R(0) : R(1);
+        R q[3];
+        if (r3) {
+            const R sc = dW * (C - gbr * gbr * inv_gb * inv_r);
+            q[0] = sc * e[0];
+            q[1] = sc * e[1];
+            q[2] = sc * e[2];
+        } else {
+            const R t = gbr * inv_gb;
+            q[0] = dW * (C * e[0] - t * gb[0]);
+            q[1] = dW * (C * e[1] - t * gb[1]);
+            q[2] = dW * (C * e[2] - t * gb[2]);
         }
+        // Nbar q = (n_i (n_i . q) + n_j (n_j . q)) / 2 with n = g / |g|
+        const R niq = (ci.x * q[0] + ci.y * q[1] + ci.z * q[2]) * ci.w * ci.w;
+        const R njq = (cj.x * q[0] + cj.y * q[1] + cj.z * q[2]) * cj.w * cj.w;
+        R Nq[3];
+        Nq[0] = R(0.5) * (ci.x * niq + cj.x * njq);
+        Nq[1] = R(0.5) * (ci.y * niq + cj.y * njq);
+        Nq[2] = R(0.5) * (ci.z * niq + cj.z * njq);
+        const R pc = (same ? xg : pen_x) * inv_r * Vj;
+        if (same) {
+            // Tbar q = q - Nbar q
+            ss[0] += pc * (q[0] - Nq[0]);
+            ss[1] += pc * (q[1] - Nq[1]);
+            if (D == 3) ss[2] += pc * (q[2] - Nq[2]);
+        } else {
+            ss[0] += pc * Nq[0];
+            ss[1] += pc * Nq[1];
+            if (D == 3) ss[2] += pc * Nq[2];
+        }
+    }
+    for (int a = 0; a < D; ++a) {
+        sp[a] = group_sum<G>(sp[a]);
+        ss[a] = group_sum<G>(ss[a]);
+    }
+    unsigned long long m0 = 0, m1 = 0;
+    if (c.lane && g == 0) {
         const R inv_rho = R(1) / ti.x;
         const Q4<R> av = ((const Q4<R>*)A.av)[i];
         const R avv[3] = {av.x, av.y, av.z};
@@ -959,7 +1123,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A, int slot)
             }
             vout[i] = vi;
         } else {
-            const double dt = Dy.dt[slot];
+            const double dt = Dy.dt[kk & 1];
             double v[3] = {0.0, 0.0, 0.0};
             double v2 = 0.0;
             bool bad = false;
@@ -976,12 +1140,25 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A, int slot)
             else m1 = bits;
         }
     }
-    if (A.mode == 1) return;
+    if (A.mode == 1) return;  // block-uniform
+    // block maximum: one partial per block (a block lies in one system)
+    __shared__ unsigned long long red[2 * (kBlock / kWave)];
     m0 = wave_max_u64(m0);
     m1 = wave_max_u64(m1);
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (m0) atomicMax(&Dy.vmax_acc[0], m0);
-        if (m1) atomicMax(&Dy.vmax_acc[1], m1);
+        red[2 * wv] = m0;
+        red[2 * wv + 1] = m1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / kWave; ++k) {
+            m0 = red[2 * k] > m0 ? red[2 * k] : m0;
+            m1 = red[2 * k + 1] > m1 ? red[2 * k + 1] : m1;
+        }
+        const int64_t lb = logical_block();
+        A.vpart[2 * lb] = m0;
+        A.vpart[2 * lb + 1] = m1;
     }
 }
 
@@ -991,27 +1168,37 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A, int slot)
 // ---------------------------------------------------------------------------
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int slot)
+__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A)
 {
-    Slot c = slot_of(A);
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
-    if (A.mode == 0 && !Dy.active[slot]) return;
-    if (!c.lane) return;
+    const int st = Dy.state;
+    if (A.mode == 0 && st != kSubstepping && st != kEnding) return;
+    if (A.mode == 1 && !Dy.stepping) return;
     const SysConst& S = A.sc[c.s];
     const int64_t i = c.i;
+    // the substep this pass completes (its force pass already advanced ksub)
+    const int64_t kk = A.mode ? 0 : Dy.ksub - 1;
+    const int slot = (int)(kk & 1);
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
     const Q4<R>* vk = (const Q4<R>*)A.vbuf[slot ^ 1];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const R inv_c0 = (R)S.inv_c0;
-    const Q4<R> gi = geo[i];
-    const Q4<R> ti = th[i];
-    const Q4<R> vi = vk[i];
+    Q4<R> gi{0, 0, 0, 0}, ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
+    int cnt = 0;
+    if (c.lane) {
+        gi = geo[i];
+        ti = th[i];
+        vi = vk[i];
+        cnt = A.ncount[i];
+    }
     R s = 0;
-    const int cnt = A.ncount[i];
-    for (int k = 0; k < cnt; ++k) {
+    for (int k = g; k < cnt; k += G) {
         const uint32_t j = nbr_at(A, i, k);
         const Q4<R> gj = geo[j];
         R r[3];
@@ -1027,16 +1214,18 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int slot)
         const R Ustar = (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
         s += (vie + Ustar) * dW * tj.y;
     }
+    s = group_sum<G>(s);
+    if (!c.lane || g != 0) return;
     const double drho = 2.0 * (double)ti.x * (double)s;
     if (A.mode == 1) {
         A.r_drho[i] = drho;
         return;
     }
-    const double dt = Dy.dt[slot];
+    const double dt = Dy.dt[kk & 1];
     double rho = A.rho[i] + 0.5 * dt * drho;
     for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt * A.vel[a][i];
-    if (Dy.active[slot ^ 1]) {
-        const double dt2 = Dy.dt[slot ^ 1];
+    if (st == kSubstepping) {
+        const double dt2 = Dy.dt[(kk + 1) & 1];
         rho += 0.5 * dt2 * drho;
         for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt2 * A.vel[a][i];
         const int ph = Geo<R>::phase(gi);
@@ -1050,7 +1239,7 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int slot)
 
 // ---------------------------------------------------------------------------
 // observables: per-wave partial sums in a fixed butterfly order, then one
-// thread per system and field summing its waves in order
+// block per system summing its waves in a fixed strided order and a fixed tree
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -1078,8 +1267,8 @@ __global__ __launch_bounds__(kWave) void k_obs_partial(DevArrays A, int pass)
     if (s < 0) return;
     const SysConst& S = A.sc[s];
     const bool lane = i < S.p_off + S.p_n;
-    double f[16];
-    for (int k = 0; k < 16; ++k) f[k] = 0.0;
+    double f[kObsPart];
+    for (int k = 0; k < kObsPart; ++k) f[k] = 0.0;
     if (lane) {
         const double m = A.mass[i];
         const int ph = A.phase[i];
@@ -1101,7 +1290,7 @@ __global__ __launch_bounds__(kWave) void k_obs_partial(DevArrays A, int pass)
             if (ph == 0)
                 for (int a = 0; a < D; ++a) f[10 + a] = m * x[a];
         } else {
-            const double* o = A.obs_out + (int64_t)s * 32;
+            const double* o = A.obs_out + (int64_t)s * kObsOut;
             double dx[3] = {0, 0, 0};
             double r2 = 0.0;
             for (int a = 0; a < D; ++a) {
@@ -1129,40 +1318,45 @@ __global__ __launch_bounds__(kWave) void k_obs_partial(DevArrays A, int pass)
             }
         }
     }
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < kObsPart; ++k) {
         const bool is_max = pass == 0 && (k == 8 || k == 9);
         f[k] = is_max ? wave_maxd(f[k]) : wave_sum(f[k]);
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 16; ++k) A.obs_part[w * 16 + k] = f[k];
+        for (int k = 0; k < kObsPart; ++k) A.obs_part[w * kObsPart + k] = f[k];
 }
 
-__global__ void k_obs_final(DevArrays A, int pass)
+__global__ __launch_bounds__(kBlock) void k_obs_final(DevArrays A, int pass)
 {
+    __shared__ double lds[kBlock];
     const int s = blockIdx.x;
-    const int k = threadIdx.x & 15;
-    const bool owner = threadIdx.x < 16;
     const SysConst& S = A.sc[s];
     const int64_t w0 = S.p_off / kWave, w1 = (S.p_off + S.p_n + kWave - 1) / kWave;
-    const bool is_max = pass == 0 && (k == 8 || k == 9);
-    double acc = 0.0;
-    for (int64_t w = w0; w < w1; ++w) {
-        const double v = A.obs_part[w * 16 + k];
-        acc = is_max ? fmax(acc, v) : acc + v;
-    }
-    double* o = A.obs_out + (int64_t)s * 32;
-    if (pass == 0) {
-        if (owner) o[k] = acc;
-        __syncthreads();
-        if (k == 0) {
-            // centroid of fluid k and equivalent radius of its volume
-            const double mk = o[4];
-            for (int a = 0; a < 3; ++a) o[10 + a] = mk > 0.0 ? o[10 + a] / mk : 0.0;
-            const double vol = o[6];
-            o[13] = S.dim == 2 ? sqrt(vol / M_PI) : cbrt(3.0 * vol / (4.0 * M_PI));
+    double* o = A.obs_out + (int64_t)s * kObsOut;
+    for (int k = 0; k < kObsPart; ++k) {
+        const bool is_max = pass == 0 && (k == 8 || k == 9);
+        double acc = 0.0;
+        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) {
+            const double v = A.obs_part[w * kObsPart + k];
+            acc = is_max ? fmax(acc, v) : acc + v;
         }
-    } else if (owner) {
-        o[16 + k] = acc;
+        lds[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h)
+                lds[threadIdx.x] = is_max ? fmax(lds[threadIdx.x], lds[threadIdx.x + h])
+                                          : lds[threadIdx.x] + lds[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) o[(pass == 0 ? 0 : 16) + k] = lds[0];
+        __syncthreads();
+    }
+    if (pass == 0 && threadIdx.x == 0) {
+        // centroid of fluid k and equivalent radius of its volume
+        const double mk = o[4];
+        for (int a = 0; a < 3; ++a) o[10 + a] = mk > 0.0 ? o[10 + a] / mk : 0.0;
+        const double vol = o[6];
+        o[13] = S.dim == 2 ? sqrt(vol / M_PI) : cbrt(3.0 * vol / (4.0 * M_PI));
     }
 }
 
@@ -1170,18 +1364,53 @@ __global__ void k_obs_final(DevArrays A, int pass)
 // launchers
 // ---------------------------------------------------------------------------
 
-static inline dim3 slot_grid(int64_t P)
+static inline dim3 slot_grid(int64_t P, int lanes = 1)
 {
-    int64_t nb = (P + kBlock - 1) / kBlock;
+    int64_t nb = (P * lanes + kBlock - 1) / kBlock;
     nb = (nb + 7) / 8 * 8;
     return dim3((unsigned)nb);
 }
 
 static inline dim3 flat_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+static inline dim3 sys_grid(int n) { return dim3((unsigned)((n + 63) / 64)); }
 
-void launch_bin(const Launch& L, DevArrays& A, int64_t ncells)
+template <typename K, typename... Args>
+static void go(K kernel, dim3 grid, dim3 block, hipStream_t st, Ev ev, Args... args)
 {
-    hipLaunchKernelGGL(k_fill_i32, flat_grid(ncells), dim3(kBlock), 0, L.stream, A.cell_cnt, ncells, 0);
+    if (ev.start || ev.stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev.start, ev.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
+__global__ void k_empty() {}
+
+void launch_empty(const Launch& L, Ev ev) { go(k_empty, dim3(1), dim3(kWave), L.stream, ev); }
+
+void launch_fill_i32(const Launch& L, int32_t* p, int64_t n, int32_t v)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, flat_grid(n), dim3(kBlock), 0, L.stream, p, n, v);
+}
+
+void launch_cycle_begin(const Launch& L, const DevArrays& A, int64_t group)
+{
+    hipLaunchKernelGGL(k_cycle_begin, sys_grid(A.nsys), dim3(64), 0, L.stream, A, group);
+}
+
+void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask)
+{
+    hipLaunchKernelGGL(k_set_stepping, sys_grid(A.nsys), dim3(64), 0, L.stream, A, mask);
+}
+
+void launch_set_targets(const Launch& L, const DevArrays& A, const long long* targets)
+{
+    hipLaunchKernelGGL(k_set_targets, sys_grid(A.nsys), dim3(64), 0, L.stream, A, targets);
+}
+
+void launch_bin(const Launch& L, const DevArrays& A)
+{
+    const int64_t ncells = A.C;
+    launch_fill_i32(L, A.cell_cnt, ncells, 0);
     if (L.dim == 2)
         hipLaunchKernelGGL(k_key<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     else
@@ -1193,93 +1422,77 @@ void launch_bin(const Launch& L, DevArrays& A, int64_t ncells)
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
                        ncells, A.scan_part, A.cell_start);
     hipLaunchKernelGGL(k_scatter, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    hipLaunchKernelGGL(k_cellsort, flat_grid(ncells), dim3(kBlock), 0, L.stream, A, ncells);
-    if (L.dim == 2)
+    hipLaunchKernelGGL(k_rank, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    if (L.dim == 2) {
         hipLaunchKernelGGL(k_gather<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    else
+        hipLaunchKernelGGL(k_copyback<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    } else {
         hipLaunchKernelGGL(k_gather<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    // the gathered copy becomes the current state
-    for (int a = 0; a < 3; ++a) {
-        std::swap(A.pos[a], A.pos2[a]);
-        std::swap(A.vel[a], A.vel2[a]);
+        hipLaunchKernelGGL(k_copyback<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     }
-    std::swap(A.rho, A.rho2);
-    std::swap(A.drho, A.drho2);
-    std::swap(A.mass, A.mass2);
-    std::swap(A.id, A.id2);
-    std::swap(A.phase, A.phase2);
 }
 
-#define RSPH_DISPATCH(KERNEL, GRID, ...)                                                        \
-    do {                                                                                        \
-        if (L.fp64) {                                                                           \
-            if (L.dim == 2)                                                                     \
-                hipLaunchKernelGGL((KERNEL<double, 2>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
-            else                                                                                \
-                hipLaunchKernelGGL((KERNEL<double, 3>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
-        } else {                                                                                \
-            if (L.dim == 2)                                                                     \
-                hipLaunchKernelGGL((KERNEL<float, 2>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
-            else                                                                                \
-                hipLaunchKernelGGL((KERNEL<float, 3>), GRID, dim3(kBlock), 0, L.stream, __VA_ARGS__); \
-        }                                                                                       \
+#define RSPH_DISPATCH(KERNEL, LANES2, LANES3, EV, ...)                                                 \
+    do {                                                                                           \
+        if (L.fp64) {                                                                              \
+            if (L.dim == 2)                                                                        \
+                go(KERNEL<double, 2>, slot_grid(A.P, LANES2), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+            else                                                                                   \
+                go(KERNEL<double, 3>, slot_grid(A.P, LANES3), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+        } else {                                                                                   \
+            if (L.dim == 2)                                                                        \
+                go(KERNEL<float, 2>, slot_grid(A.P, LANES2), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+            else                                                                                   \
+                go(KERNEL<float, 3>, slot_grid(A.P, LANES3), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+        }                                                                                          \
     } while (0)
 
-void launch_neighbours(const Launch& L, const DevArrays& A)
+constexpr int G2 = Lanes<2>::G;
+constexpr int G3 = Lanes<3>::G;
+
+void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev)
 {
-    RSPH_DISPATCH(k_neighbours, slot_grid(A.P), A);
+    RSPH_DISPATCH(k_neighbours, G2, G3, ev, A);
 }
+
+int lanes_per_particle(int dim) { return dim == 2 ? G2 : G3; }
 
 void launch_dt_advection(const Launch& L, const DevArrays& A)
 {
-    hipLaunchKernelGGL(k_dt_advection, dim3((A.nsys + 63) / 64), dim3(64), 0, L.stream, A);
+    hipLaunchKernelGGL(k_dt_advection, dim3((unsigned)A.nsys), dim3(kBlock), 0, L.stream, A);
 }
 
-void launch_advection(const Launch& L, const DevArrays& A)
+void launch_advection(const Launch& L, const DevArrays& A, Ev ev)
 {
-    RSPH_DISPATCH(k_advection, slot_grid(A.P), A);
+    RSPH_DISPATCH(k_advection, G2, G3, ev, A);
 }
 
-void launch_shift(const Launch& L, const DevArrays& A) { RSPH_DISPATCH(k_shift, slot_grid(A.P), A); }
+void launch_shift(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_shift, G2, G3, ev, A); }
 
-void launch_colour(const Launch& L, const DevArrays& A, int slot)
+void launch_colour(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_colour, G2, G3, ev, A); }
+
+void launch_force(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_force, G2, G3, ev, A); }
+
+void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group)
 {
-    RSPH_DISPATCH(k_colour, slot_grid(A.P), A, slot);
+    hipLaunchKernelGGL(k_dt_substep, dim3((unsigned)A.nsys), dim3(kBlock), 0, L.stream, A, group,
+                       lanes_per_particle(L.dim));
 }
 
-void launch_force(const Launch& L, const DevArrays& A, int slot)
+void launch_continuity(const Launch& L, const DevArrays& A, Ev ev)
 {
-    RSPH_DISPATCH(k_force, slot_grid(A.P), A, slot);
+    RSPH_DISPATCH(k_continuity, G2, G3, ev, A);
 }
 
-void launch_dt_substep(const Launch& L, const DevArrays& A, int slot)
+void launch_observables(const Launch& L, const DevArrays& A)
 {
-    hipLaunchKernelGGL(k_dt_substep, dim3((A.nsys + 63) / 64), dim3(64), 0, L.stream, A, slot);
-}
-
-void launch_continuity(const Launch& L, const DevArrays& A, int slot)
-{
-    RSPH_DISPATCH(k_continuity, slot_grid(A.P), A, slot);
-}
-
-void launch_any_active(const Launch& L, const DevArrays& A, int slot, int32_t* out)
-{
-    hipLaunchKernelGGL(k_any_active, dim3(1), dim3(64), 0, L.stream, A, slot, out);
-}
-
-void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask)
-{
-    hipLaunchKernelGGL(k_set_stepping, dim3((A.nsys + 63) / 64), dim3(64), 0, L.stream, A, mask);
-}
-
-void launch_observables(const Launch& L, const DevArrays& A, int64_t nwaves)
-{
+    const int64_t nwaves = A.P / kWave;
     for (int pass = 0; pass < 2; ++pass) {
         if (L.dim == 2)
             hipLaunchKernelGGL(k_obs_partial<2>, dim3((unsigned)nwaves), dim3(kWave), 0, L.stream, A, pass);
         else
             hipLaunchKernelGGL(k_obs_partial<3>, dim3((unsigned)nwaves), dim3(kWave), 0, L.stream, A, pass);
-        hipLaunchKernelGGL(k_obs_final, dim3((unsigned)A.nsys), dim3(64), 0, L.stream, A, pass);
+        hipLaunchKernelGGL(k_obs_final, dim3((unsigned)A.nsys), dim3(kBlock), 0, L.stream, A, pass);
     }
 }
 

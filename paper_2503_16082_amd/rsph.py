@@ -31,7 +31,8 @@ FIELDS = {
     "acc": 7, "acc_p": 8, "acc_s": 9, "acc_v": 10, "gradC": 11, "rate_drho": 12,
     "B": 13, "dr": 14, "sigma": 15, "nnb": 16, "flags": 17,
 }
-KERNELS = ["bin", "neighbours", "advection", "shift", "colour", "force", "continuity"]
+KERNELS = ["bin", "neighbours", "advection", "shift", "colour", "force", "continuity",
+           "event_floor"]
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENUMERIC",
           -6: "EBUSY"}
