@@ -25,7 +25,7 @@ constexpr int kBlock = 256;
 constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lattice)
 constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
 constexpr int kMaxCellsPerAxis = 1024;
-constexpr int kMaxLanes = 8;  // lanes per particle slot in the pair passes (at most)
+constexpr int kMaxLanes = 16;  // lanes per particle slot in the pair passes (at most)
 
 // method switches (mirror of the public RSPH_* flags)
 constexpr uint32_t kNoPenalty = 1u;

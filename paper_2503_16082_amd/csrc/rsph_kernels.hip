@@ -1,7 +1,7 @@
 // rsph_kernels.hip -- HIP kernels for gfx950 (CDNA4) of the Riemann-SPH
 // multiphase surface-tension method (arXiv 2503.16082).
 //
-// Pair passes use G lanes per particle slot (4 in 2D, 8 in 3D), wave64,
+// Pair passes use G = 4 lanes per particle slot, wave64,
 // 256-thread blocks.  Blocks are remapped
 // so that each of the 8 XCDs works on one contiguous eighth of the slot range:
 // particles are cell-sorted, so neighbour gathers of a block mostly hit the L2
@@ -202,16 +202,26 @@ __device__ __forceinline__ void flag_health(SysDyn& D, uint32_t bits)
 // lanes per particle in the pair passes: a particle's neighbour list is split
 // over G consecutive lanes, whose partial sums are combined by a butterfly of
 // xor-shuffles (fixed order, identical in every lane of the group)
+#ifndef RSPH_LANES_2D
+#define RSPH_LANES_2D 4
+#endif
+#ifndef RSPH_LANES_3D
+#define RSPH_LANES_3D 4
+#endif
 template <int D>
 struct Lanes;
 template <>
 struct Lanes<2> {
-    static constexpr int G = 4;
+    static constexpr int G = RSPH_LANES_2D;
 };
 template <>
 struct Lanes<3> {
-    static constexpr int G = 8;
+    static constexpr int G = RSPH_LANES_3D;
 };
+// at least 4 lanes: a 256-thread block then covers at most 64 slots, i.e. lies
+// inside one system, which the per-block partial maxima rely on
+static_assert(RSPH_LANES_2D >= 4 && RSPH_LANES_3D >= 4, "lanes per slot");
+static_assert(RSPH_LANES_2D <= kMaxLanes && RSPH_LANES_3D <= kMaxLanes, "lanes per slot");
 
 template <int G>
 __device__ __forceinline__ Slot slot_of_group(const DevArrays& A, int& g)
@@ -445,6 +455,102 @@ __global__ __launch_bounds__(kBlock) void k_copyback(DevArrays A)
 // per-particle inputs of the pair loops
 // ---------------------------------------------------------------------------
 
+// Candidates of one block's particles are staged in LDS: the block's 64 slots
+// lie in a few consecutive cells, so the union of their 3^d stencils is a small
+// box of cells.  Its particles (FP64 positions and phase) are copied once per
+// block; every candidate test then reads LDS instead of L2.  Blocks whose union
+// does not fit fall back to reading candidates from global memory; both paths
+// produce the same list in the same order.
+constexpr int kStageCells = 128;
+constexpr int kStageCap = 1792;
+
+struct Stage {
+    double x[kStageCap];
+    double y[kStageCap];
+    double z[kStageCap];
+    int8_t ph[kStageCap];
+    int32_t off[kStageCells + 1];  // LDS offset of each union cell
+    int32_t gs[kStageCells];       // first global slot of each union cell
+    int32_t lo[3], hi[3];          // cell-coordinate bounds of the block's particles
+    int32_t dims[3];               // union box extent (cells)
+    int32_t ok;
+};
+
+template <int D>
+__device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& S, Stage& L,
+                                            int64_t base, bool live, const int* ci, int g)
+{
+    const int t = threadIdx.x;
+    if (t < 3) {
+        L.lo[t] = 0x7fffffff;
+        L.hi[t] = -0x7fffffff;
+    }
+    __syncthreads();
+    if (live && g == 0)
+        for (int a = 0; a < D; ++a) {
+            atomicMin(&L.lo[a], ci[a]);
+            atomicMax(&L.hi[a], ci[a]);
+        }
+    __syncthreads();
+    int ux = L.hi[0] - L.lo[0] + 3, uy = L.hi[1] - L.lo[1] + 3, uz = D == 3 ? L.hi[2] - L.lo[2] + 3 : 1;
+    const int ncu = ux * uy * uz;
+    const bool fits_cells = L.hi[0] >= L.lo[0] && ncu <= kStageCells;
+    // per union cell: count and first slot (one thread per cell), then offsets
+    int cnt = 0, gs = 0;
+    if (fits_cells && t < ncu) {
+        const int lx = t % ux, ly = (t / ux) % uy, lz = t / (ux * uy);
+        int cx = L.lo[0] - 1 + lx, cy = L.lo[1] - 1 + ly, cz = D == 3 ? L.lo[2] - 1 + lz : 0;
+        cx = cx < 0 ? cx + S.ncell[0] : (cx >= S.ncell[0] ? cx - S.ncell[0] : cx);
+        cy = cy < 0 ? cy + S.ncell[1] : (cy >= S.ncell[1] ? cy - S.ncell[1] : cy);
+        if (D == 3) cz = cz < 0 ? cz + S.ncell[2] : (cz >= S.ncell[2] ? cz - S.ncell[2] : cz);
+        const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
+        const int a0 = A.cell_start[gc];
+        cnt = A.cell_start[gc + 1] - a0;
+        gs = (int)(base + a0);
+    }
+    // exclusive scan of the counts over the first 128 threads (two waves)
+    const int lane = t & 63, wv = t >> 6;
+    int x = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __shared__ int wsum[kBlock / kWave];
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    const int before = wv == 0 ? 0 : wsum[0];
+    if (fits_cells && t < ncu) {
+        L.off[t] = before + x - cnt;
+        L.gs[t] = gs;
+    }
+    if (t == 0) {
+        const int total = wsum[0] + wsum[1];
+        L.ok = fits_cells && total <= kStageCap;
+        L.dims[0] = ux;
+        L.dims[1] = uy;
+        L.dims[2] = uz;
+        if (fits_cells) L.off[ncu] = total;
+    }
+    __syncthreads();
+    if (!L.ok) return;  // block-uniform
+    const int total = L.off[ncu];
+    for (int k = t; k < total; k += kBlock) {
+        // union cell holding entry k: binary search over the offsets
+        int lo = 0, hi = ncu;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (L.off[mid] <= k) lo = mid;
+            else hi = mid;
+        }
+        const int64_t j = L.gs[lo] + (k - L.off[lo]);
+        L.x[k] = A.pos[0][j];
+        L.y[k] = A.pos[1][j];
+        if (D == 3) L.z[k] = A.pos[2][j];
+        L.ph[k] = (int8_t)A.phase[j];
+    }
+    __syncthreads();
+}
+
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
 {
@@ -452,11 +558,12 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     // the particle's group; an ordered ballot keeps the list in candidate
     // order (stencil cells in a fixed order, slots ascending within a cell)
     constexpr int G = Lanes<D>::G;
+    __shared__ Stage L;
     int g;
     Slot c = slot_of_group<G>(A, g);
-    if (c.s < 0) return;
+    if (c.s < 0) return;  // block-uniform: a block lies in one 64-slot range
     SysDyn& Dy = A.sd[c.s];
-    if (!Dy.stepping) return;  // wave-uniform
+    if (!Dy.stepping) return;
     const SysConst& S = A.sc[c.s];
     const int64_t i = c.i;
     const bool live = c.lane;
@@ -473,6 +580,8 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
         }
         ph = A.phase[i];
     }
+    stage_union<D>(A, S, L, base, live, ci, g);
+    const bool lds = L.ok;
     int cnt = 0;
     int cross = 0, coincident = 0, close = 0;
     double wsum = 0.0;
@@ -495,29 +604,54 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                 double kx = 0.0;
                 if (cx < 0) { cx += S.ncell[0]; kx = -S.box[0]; }
                 else if (cx >= S.ncell[0]) { cx -= S.ncell[0]; kx = S.box[0]; }
-                int64_t jb = 0, je = 0;
+                // candidate range: LDS entries [lb, le) mapping to slots gs + (k - lb),
+                // or global slots [jb, je)
+                int64_t jb = 0, je = 0, gs0 = 0;
                 if (live) {
-                    const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
-                    jb = base + A.cell_start[gc];
-                    je = base + A.cell_start[gc + 1];
+                    if (lds) {
+                        const int lx = ci[0] + dx - (L.lo[0] - 1), ly = ci[1] + dy - (L.lo[1] - 1);
+                        const int lz = D == 3 ? ci[2] + dz - (L.lo[2] - 1) : 0;
+                        const int u = lx + L.dims[0] * (ly + L.dims[1] * lz);
+                        jb = L.off[u];
+                        je = L.off[u + 1];
+                        gs0 = L.gs[u] - jb;
+                    } else {
+                        const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
+                        jb = base + A.cell_start[gc];
+                        je = base + A.cell_start[gc + 1];
+                    }
                 }
                 for (int64_t j0 = jb; j0 < je; j0 += G) {
-                    const int64_t j = j0 + g;
+                    const int64_t k = j0 + g;
+                    const int64_t j = lds ? gs0 + k : k;
                     bool hit = false;
                     double r2 = 0.0;
-                    if (j < je && j != i) {
+                    int phj = 0;
+                    if (k < je && j != i) {
+                        double xj, yj, zj = 0.0;
+                        if (lds) {
+                            xj = L.x[k];
+                            yj = L.y[k];
+                            if (D == 3) zj = L.z[k];
+                            phj = L.ph[k];
+                        } else {
+                            xj = A.pos[0][j];
+                            yj = A.pos[1][j];
+                            if (D == 3) zj = A.pos[2][j];
+                            phj = A.phase[j];
+                        }
                         // the neighbour predicate, one rounding per operation:
                         // x_i - x_j, minus the periodic image offset of the stencil
                         // cell (the minimum image for every pair closer than 2h),
                         // squares summed in axis order
-                        double d = __dsub_rn(xi[0], A.pos[0][j]);
+                        double d = __dsub_rn(xi[0], xj);
                         if (kx != 0.0) d = __dsub_rn(d, kx);
                         r2 = __dmul_rn(d, d);
-                        d = __dsub_rn(xi[1], A.pos[1][j]);
+                        d = __dsub_rn(xi[1], yj);
                         if (ky != 0.0) d = __dsub_rn(d, ky);
                         r2 = __dadd_rn(r2, __dmul_rn(d, d));
                         if (D == 3) {
-                            d = __dsub_rn(xi[2], A.pos[2][j]);
+                            d = __dsub_rn(xi[2], zj);
                             if (kz != 0.0) d = __dsub_rn(d, kz);
                             r2 = __dadd_rn(r2, __dmul_rn(d, d));
                         }
@@ -528,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                         const int at = cnt + __popc(gm & below);
                         if (at < A.kmax) out[(int64_t)at * kWave] = (uint32_t)j;
                         wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
-                        cross |= A.phase[j] != ph;
+                        cross |= phj != ph;
                         coincident |= r2 < S.coincident2;
                         close |= r2 < S.close2;
                     }
