@@ -455,26 +455,32 @@ __global__ __launch_bounds__(kBlock) void k_copyback(DevArrays A)
 // per-particle inputs of the pair loops
 // ---------------------------------------------------------------------------
 
-// Candidates of one block's particles are staged in LDS: the block's 64 slots
-// lie in a few consecutive cells, so the union of their 3^d stencils is a small
-// box of cells.  Its particles (FP64 positions and phase) are copied once per
-// block; every candidate test then reads LDS instead of L2.  Blocks whose union
-// does not fit fall back to reading candidates from global memory; both paths
-// produce the same list in the same order.
+// Neighbour lists.  The candidates of one block's particles are staged in LDS:
+// the block's 64 slots lie in a few consecutive cells, so the union of their
+// 3^d stencils is a small box of cells whose particles are copied once per
+// block as FP32 offsets from their own cell corner.  A candidate is tested in
+// FP32 on these split positions; only candidates within a relative 1e-5 of the
+// cut-off (2h)^2 are decided by the exact FP64 predicate on the stored
+// positions, so the neighbour set is exactly the one of the FP64 predicate.
+// Blocks whose union does not fit fall back to testing every candidate in FP64
+// from global memory; both paths produce the same list in the same order.
 constexpr int kStageCells = 128;
-constexpr int kStageCap = 1792;
+constexpr int kStageCap = 2560;
 
 struct Stage {
-    double x[kStageCap];
-    double y[kStageCap];
-    double z[kStageCap];
+    float x[kStageCap];
+    float y[kStageCap];
+    float z[kStageCap];
     int8_t ph[kStageCap];
     int32_t off[kStageCells + 1];  // LDS offset of each union cell
     int32_t gs[kStageCells];       // first global slot of each union cell
     int32_t lo[3], hi[3];          // cell-coordinate bounds of the block's particles
     int32_t dims[3];               // union box extent (cells)
     int32_t ok;
+    int32_t wsum[kBlock / kWave];
 };
+
+__device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 template <int D>
 __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& S, Stage& L,
@@ -492,17 +498,17 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
             atomicMax(&L.hi[a], ci[a]);
         }
     __syncthreads();
-    int ux = L.hi[0] - L.lo[0] + 3, uy = L.hi[1] - L.lo[1] + 3, uz = D == 3 ? L.hi[2] - L.lo[2] + 3 : 1;
+    const int ux = L.hi[0] - L.lo[0] + 3, uy = L.hi[1] - L.lo[1] + 3;
+    const int uz = D == 3 ? L.hi[2] - L.lo[2] + 3 : 1;
     const int ncu = ux * uy * uz;
     const bool fits_cells = L.hi[0] >= L.lo[0] && ncu <= kStageCells;
     // per union cell: count and first slot (one thread per cell), then offsets
     int cnt = 0, gs = 0;
     if (fits_cells && t < ncu) {
         const int lx = t % ux, ly = (t / ux) % uy, lz = t / (ux * uy);
-        int cx = L.lo[0] - 1 + lx, cy = L.lo[1] - 1 + ly, cz = D == 3 ? L.lo[2] - 1 + lz : 0;
-        cx = cx < 0 ? cx + S.ncell[0] : (cx >= S.ncell[0] ? cx - S.ncell[0] : cx);
-        cy = cy < 0 ? cy + S.ncell[1] : (cy >= S.ncell[1] ? cy - S.ncell[1] : cy);
-        if (D == 3) cz = cz < 0 ? cz + S.ncell[2] : (cz >= S.ncell[2] ? cz - S.ncell[2] : cz);
+        const int cx = wrap_cell(L.lo[0] - 1 + lx, S.ncell[0]);
+        const int cy = wrap_cell(L.lo[1] - 1 + ly, S.ncell[1]);
+        const int cz = D == 3 ? wrap_cell(L.lo[2] - 1 + lz, S.ncell[2]) : 0;
         const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
         const int a0 = A.cell_start[gc];
         cnt = A.cell_start[gc + 1] - a0;
@@ -515,16 +521,15 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
         int y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    __shared__ int wsum[kBlock / kWave];
-    if (lane == 63) wsum[wv] = x;
+    if (lane == 63) L.wsum[wv] = x;
     __syncthreads();
-    const int before = wv == 0 ? 0 : wsum[0];
+    const int before = wv == 0 ? 0 : L.wsum[0];
     if (fits_cells && t < ncu) {
         L.off[t] = before + x - cnt;
         L.gs[t] = gs;
     }
     if (t == 0) {
-        const int total = wsum[0] + wsum[1];
+        const int total = L.wsum[0] + L.wsum[1];
         L.ok = fits_cells && total <= kStageCap;
         L.dims[0] = ux;
         L.dims[1] = uy;
@@ -542,13 +547,40 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
             if (L.off[mid] <= k) lo = mid;
             else hi = mid;
         }
+        const int lx = lo % ux, ly = (lo / ux) % uy, lz = lo / (ux * uy);
+        const int cx = wrap_cell(L.lo[0] - 1 + lx, S.ncell[0]);
+        const int cy = wrap_cell(L.lo[1] - 1 + ly, S.ncell[1]);
         const int64_t j = L.gs[lo] + (k - L.off[lo]);
-        L.x[k] = A.pos[0][j];
-        L.y[k] = A.pos[1][j];
-        if (D == 3) L.z[k] = A.pos[2][j];
+        L.x[k] = (float)(A.pos[0][j] - (double)cx * S.cell[0]);
+        L.y[k] = (float)(A.pos[1][j] - (double)cy * S.cell[1]);
+        if (D == 3) {
+            const int cz = wrap_cell(L.lo[2] - 1 + lz, S.ncell[2]);
+            L.z[k] = (float)(A.pos[2][j] - (double)cz * S.cell[2]);
+        }
         L.ph[k] = (int8_t)A.phase[j];
     }
     __syncthreads();
+}
+
+// exact neighbour predicate: x_i - x_j, minus the periodic image offset of the
+// stencil cell (the minimum image for every pair closer than 2h), squares
+// summed in axis order, one rounding per operation
+template <int D>
+__device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi, int64_t j, double kx,
+                                           double ky, double kz)
+{
+    double d = __dsub_rn(xi[0], A.pos[0][j]);
+    if (kx != 0.0) d = __dsub_rn(d, kx);
+    double r2 = __dmul_rn(d, d);
+    d = __dsub_rn(xi[1], A.pos[1][j]);
+    if (ky != 0.0) d = __dsub_rn(d, ky);
+    r2 = __dadd_rn(r2, __dmul_rn(d, d));
+    if (D == 3) {
+        d = __dsub_rn(xi[2], A.pos[2][j]);
+        if (kz != 0.0) d = __dsub_rn(d, kz);
+        r2 = __dadd_rn(r2, __dmul_rn(d, d));
+    }
+    return r2;
 }
 
 template <typename R, int D>
@@ -582,9 +614,14 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     }
     stage_union<D>(A, S, L, base, live, ci, g);
     const bool lds = L.ok;
+    float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
+    for (int a = 0; a < 3; ++a) {
+        cellf[a] = (float)S.cell[a];
+        if (a < D) oi[a] = (float)(xi[a] - (double)ci[a] * S.cell[a]);
+    }
+    const float cut_hi = (float)(S.cut2 * (1.0 + 1e-5)), cut_lo = (float)(S.cut2 * (1.0 - 1e-5));
     int cnt = 0;
-    int cross = 0, coincident = 0, close = 0;
-    double wsum = 0.0;
+    int cross = 0;
     uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
     const int zr = D == 3 ? 1 : 0;
     for (int dz = -zr; dz <= zr; ++dz) {
@@ -594,18 +631,19 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
             if (cz < 0) { cz += S.ncell[2]; kz = -S.box[2]; }
             else if (cz >= S.ncell[2]) { cz -= S.ncell[2]; kz = S.box[2]; }
         }
+        const float rz0 = oi[2] - (float)dz * cellf[2];
         for (int dy = -1; dy <= 1; ++dy) {
             int cy = ci[1] + dy;
             double ky = 0.0;
             if (cy < 0) { cy += S.ncell[1]; ky = -S.box[1]; }
             else if (cy >= S.ncell[1]) { cy -= S.ncell[1]; ky = S.box[1]; }
+            const float ry0 = oi[1] - (float)dy * cellf[1];
             for (int dx = -1; dx <= 1; ++dx) {
                 int cx = ci[0] + dx;
                 double kx = 0.0;
                 if (cx < 0) { cx += S.ncell[0]; kx = -S.box[0]; }
                 else if (cx >= S.ncell[0]) { cx -= S.ncell[0]; kx = S.box[0]; }
-                // candidate range: LDS entries [lb, le) mapping to slots gs + (k - lb),
-                // or global slots [jb, je)
+                const float rx0 = oi[0] - (float)dx * cellf[0];
                 int64_t jb = 0, je = 0, gs0 = 0;
                 if (live) {
                     if (lds) {
@@ -625,85 +663,103 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                     const int64_t k = j0 + g;
                     const int64_t j = lds ? gs0 + k : k;
                     bool hit = false;
-                    double r2 = 0.0;
                     int phj = 0;
                     if (k < je && j != i) {
-                        double xj, yj, zj = 0.0;
                         if (lds) {
-                            xj = L.x[k];
-                            yj = L.y[k];
-                            if (D == 3) zj = L.z[k];
+                            const float ax = rx0 - L.x[k], ay = ry0 - L.y[k];
+                            const float az = D == 3 ? rz0 - L.z[k] : 0.f;
+                            const float r2f = ax * ax + ay * ay + az * az;
                             phj = L.ph[k];
+                            if (r2f < cut_lo) hit = true;
+                            else if (r2f < cut_hi) hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
                         } else {
-                            xj = A.pos[0][j];
-                            yj = A.pos[1][j];
-                            if (D == 3) zj = A.pos[2][j];
                             phj = A.phase[j];
+                            hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
                         }
-                        // the neighbour predicate, one rounding per operation:
-                        // x_i - x_j, minus the periodic image offset of the stencil
-                        // cell (the minimum image for every pair closer than 2h),
-                        // squares summed in axis order
-                        double d = __dsub_rn(xi[0], xj);
-                        if (kx != 0.0) d = __dsub_rn(d, kx);
-                        r2 = __dmul_rn(d, d);
-                        d = __dsub_rn(xi[1], yj);
-                        if (ky != 0.0) d = __dsub_rn(d, ky);
-                        r2 = __dadd_rn(r2, __dmul_rn(d, d));
-                        if (D == 3) {
-                            d = __dsub_rn(xi[2], zj);
-                            if (kz != 0.0) d = __dsub_rn(d, kz);
-                            r2 = __dadd_rn(r2, __dmul_rn(d, d));
-                        }
-                        hit = r2 < S.cut2;
                     }
                     const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
                     if (hit) {
                         const int at = cnt + __popc(gm & below);
                         if (at < A.kmax) out[(int64_t)at * kWave] = (uint32_t)j;
-                        wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
                         cross |= phj != ph;
-                        coincident |= r2 < S.coincident2;
-                        close |= r2 < S.close2;
                     }
                     cnt += __popc(gm);
                 }
             }
         }
     }
-    wsum = group_sum<G>(wsum);
-    for (int o = 1; o < G; o <<= 1) {
-        cross |= __shfl_xor(cross, o, 64);
-        coincident |= __shfl_xor(coincident, o, 64);
-        close |= __shfl_xor(close, o, 64);
-    }
+    for (int o = 1; o < G; o <<= 1) cross |= __shfl_xor(cross, o, 64);
     if (!live || g != 0) return;
     if (cnt > A.kmax) {
         flag_health(Dy, kHealthNeighbours);
         cnt = A.kmax;
     }
-    if (coincident) flag_health(Dy, kHealthCoincident);
-    if (close) flag_health(Dy, kHealthClose);
     A.ncount[i] = cnt;
     A.flags[i] = cross ? kFlagInterface : 0;
+    Q4<R>* vb = (Q4<R>*)A.vbuf[0];
+    vb[i] = Q4<R>{(R)A.vel[0][i], (R)A.vel[1][i], D == 3 ? (R)A.vel[2][i] : (R)0, (R)0};
+    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, S, ci);
+    ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
+    if (A.mode == 1)
+        for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
+}
+
+// Kernel sum sigma_i = W(0) + sum_j W_ij over the frozen list, the normalised
+// density summation rho_i = rho0_i sigma_i / sigma0, and the {rho, V, p}
+// records of the advection-step passes; flags pairs closer than 1e-9 h.  FP64
+// in both forms: the density decides the pressure c0^2 (rho - rho0), which
+// amplifies a density error by rho / (rho - rho0).
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
+{
+    constexpr int G = Lanes<D>::G;
+    int g;
+    Slot c = slot_of_group<G>(A, g);
+    if (c.s < 0) return;
+    SysDyn& Dy = A.sd[c.s];
+    if (!Dy.stepping) return;
+    const SysConst& S = A.sc[c.s];
+    const int64_t i = c.i;
+    double xi[3] = {0.0, 0.0, 0.0};
+    int cnt = 0;
+    if (c.lane) {
+        for (int a = 0; a < D; ++a) xi[a] = A.pos[a][i];
+        cnt = A.ncount[i];
+    }
+    double wsum = 0.0;
+    int coincident = 0, close = 0;
+    for (int k = g; k < cnt; k += G) {
+        const uint32_t j = nbr_at(A, i, k);
+        double r2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double d = xi[a] - A.pos[a][j];
+            if (d > S.half_box[a]) d -= S.box[a];
+            else if (d < -S.half_box[a]) d += S.box[a];
+            r2 += d * d;
+        }
+        wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
+        coincident |= r2 < S.coincident2;
+        close |= r2 < S.close2;
+    }
+    wsum = group_sum<G>(wsum);
+    for (int o = 1; o < G; o <<= 1) {
+        coincident |= __shfl_xor(coincident, o, 64);
+        close |= __shfl_xor(close, o, 64);
+    }
+    if (!c.lane || g != 0) return;
+    if (coincident) flag_health(Dy, kHealthCoincident);
+    if (close) flag_health(Dy, kHealthClose);
     const double sigma = S.w0 + wsum;
+    const int ph = A.phase[i];
     double rho = A.rho[i];
     if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
         rho = S.rho0[ph] * sigma / S.sigma0;
         A.rho[i] = rho;
     }
-    if (A.mode == 1) {
-        A.r_sigma[i] = sigma;
-        for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
-    }
+    if (A.mode == 1) A.r_sigma[i] = sigma;
     const double V = A.mass[i] / rho;
     const double p = S.c0sq * (rho - S.rho0[ph]);
-    Q4<R>* th = (Q4<R>*)A.th[1];
-    th[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
-    Q4<R>* vb = (Q4<R>*)A.vbuf[0];
-    vb[i] = Q4<R>{(R)A.vel[0][i], (R)A.vel[1][i], D == 3 ? (R)A.vel[2][i] : (R)0, (R)0};
-    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, S, ci);
-    ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
+    ((Q4<R>*)A.th[1])[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
 }
 
 // ---------------------------------------------------------------------------
@@ -1587,6 +1643,7 @@ constexpr int G3 = Lanes<3>::G;
 void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev)
 {
     RSPH_DISPATCH(k_neighbours, G2, G3, ev, A);
+    RSPH_DISPATCH(k_density, G2, G3, Ev{}, A);
 }
 
 int lanes_per_particle(int dim) { return dim == 2 ? G2 : G3; }
