@@ -68,6 +68,42 @@ __device__ __forceinline__ uint32_t nbr_at(const DevArrays& A, int64_t i, int k)
     return A.nbr[(w * A.kmax + k) * kWave + (i & 63)];
 }
 
+// Iterates lane g of particle i's group over list entries g, g + G, ... in
+// order.  Entries are taken CH at a time: the CH indices are loaded together,
+// then the neighbour records of all CH (load(j)), then body(j, record) runs
+// for each valid entry in list order.  The gathers of CH iterations are thus
+// in flight at once, while every sum accumulates in the order of the list.
+// Entries past the count reuse the group's first entry (a valid slot), so every
+// load stays inside the arrays.
+template <int G, int CH, typename Load, typename Body>
+__device__ __forceinline__ void for_neighbours(const DevArrays& A, int64_t i, int g, int cnt,
+                                               Load&& load, Body&& body)
+{
+    const uint32_t* list = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
+    for (int k0 = g; k0 < cnt; k0 += G * CH) {
+        uint32_t jb[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int k = k0 + u * G;
+            jb[u] = list[(int64_t)(k < cnt ? k : k0) * kWave];
+        }
+        decltype(load(0u)) rec[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) rec[u] = load(jb[u]);
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (k0 + u * G < cnt) body(jb[u], rec[u]);
+    }
+}
+
+template <typename R, int N>
+struct Recs {
+    Q4<R> q[N];
+};
+struct Pos3 {
+    double x[3];
+};
+
 // ---------------------------------------------------------------------------
 // kernel function (Wendland C2): W = alpha (1 - q/2)^4 (1 + 2q), q = r/h < 2
 // ---------------------------------------------------------------------------
@@ -218,30 +254,97 @@ template <>
 struct Lanes<3> {
     static constexpr int G = RSPH_LANES_3D;
 };
+// list entries per lane whose gathers are issued together in the pair passes
+// (measured: 1 in 2D, where the lists are short; in 3D 4 with FP32 records
+// and 2 with FP64 records, whose registers would otherwise cut occupancy)
+#ifndef RSPH_CHUNK_2D
+#define RSPH_CHUNK_2D 1
+#endif
+#ifndef RSPH_CHUNK_3D
+#define RSPH_CHUNK_3D 4
+#endif
+template <typename R, int D>
+struct Chunk {
+    static constexpr int N = D == 2 ? RSPH_CHUNK_2D : (sizeof(R) == 4 ? RSPH_CHUNK_3D : 2);
+};
 // at least 4 lanes: a 256-thread block then covers at most 64 slots, i.e. lies
 // inside one system, which the per-block partial maxima rely on
 static_assert(RSPH_LANES_2D >= 4 && RSPH_LANES_3D >= 4, "lanes per slot");
 static_assert(RSPH_LANES_2D <= kMaxLanes && RSPH_LANES_3D <= kMaxLanes, "lanes per slot");
 
+// slot of this thread's group and its lane g in the group (no memory access)
 template <int G>
-__device__ __forceinline__ Slot slot_of_group(const DevArrays& A, int& g)
+__device__ __forceinline__ int64_t group_slot(int& g)
 {
     const int64_t t = logical_block() * kBlock + threadIdx.x;
     g = (int)(t & (G - 1));
+    return t / G;
+}
+
+// system of slot i < A.P; the 64 / G slots of a wave lie in one 64-slot block,
+// hence one system
+__device__ __forceinline__ Slot lookup_slot(const DevArrays& A, int64_t i)
+{
     Slot c;
-    c.i = t / G;
-    c.s = -1;
+    c.i = i;
     c.lane = false;
-    if (c.i >= A.P) return c;
-    // the 64 / G slots of a wave lie in one 64-slot block, hence one system
-    int s = A.wave_sys[c.i >> 6];
-    s = __builtin_amdgcn_readfirstlane(s);
+    const int s = A.wave_sys[__builtin_amdgcn_readfirstlane((int)(i >> 6))];
     c.s = s;
     if (s < 0) return c;
     const SysConst& S = A.sc[s];
-    c.lane = c.i < S.p_off + S.p_n;
+    c.lane = i < S.p_off + S.p_n;
     return c;
 }
+
+template <int G>
+__device__ __forceinline__ Slot slot_of_group(const DevArrays& A, int& g)
+{
+    const int64_t i = group_slot<G>(g);
+    if (i >= A.P) return Slot{i, -1, false};
+    return lookup_slot(A, i);
+}
+
+// Neighbour-list walk of the substep passes, lane g of particle i's group
+// taking entries g, g + G, ... in order, CH at a time: the records of a chunk
+// are gathered together and the indices of the next chunk are loaded while
+// the current one is evaluated.  The first chunk's indices are requested by
+// start(), which needs only the slot, so that their latency overlaps the
+// system lookup; entries past the count hold stale values and are never used
+// as addresses (a lane past the count reuses its group's first entry).
+template <int G, int CH>
+struct NbrList {
+    static_assert(G * CH <= kKmax2, "first chunk inside every list");
+    const uint32_t* list;
+    uint32_t jn[CH];
+
+    __device__ __forceinline__ void start(const DevArrays& A, int64_t i, int g)
+    {
+        list = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) jn[u] = list[(int64_t)(g + u * G) * kWave];
+    }
+
+    template <typename Load, typename Body>
+    __device__ __forceinline__ void run(int g, int cnt, Load&& load, Body&& body)
+    {
+        for (int k0 = g; k0 < cnt; k0 += G * CH) {
+            uint32_t jb[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) jb[u] = k0 + u * G < cnt ? jn[u] : jn[0];
+            decltype(load(0u)) rec[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) rec[u] = load(jb[u]);
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int k = k0 + (CH + u) * G;
+                if (k < cnt) jn[u] = list[(int64_t)k * kWave];
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (k0 + u * G < cnt) body(jb[u], rec[u]);
+        }
+    }
+};
 
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v)
@@ -728,19 +831,20 @@ __global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
     }
     double wsum = 0.0;
     int coincident = 0, close = 0;
-    for (int k = g; k < cnt; k += G) {
-        const uint32_t j = nbr_at(A, i, k);
-        double r2 = 0.0;
-        for (int a = 0; a < D; ++a) {
-            double d = xi[a] - A.pos[a][j];
-            if (d > S.half_box[a]) d -= S.box[a];
-            else if (d < -S.half_box[a]) d += S.box[a];
-            r2 += d * d;
-        }
-        wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
-        coincident |= r2 < S.coincident2;
-        close |= r2 < S.close2;
-    }
+    for_neighbours<G, Chunk<R, D>::N>(
+        A, i, g, cnt, [&](uint32_t j) { return Pos3{{A.pos[0][j], A.pos[1][j], D == 3 ? A.pos[2][j] : 0.0}}; },
+        [&](uint32_t j, const Pos3& rj) {
+            double r2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                double d = xi[a] - rj.x[a];
+                if (d > S.half_box[a]) d -= S.box[a];
+                else if (d < -S.half_box[a]) d += S.box[a];
+                r2 += d * d;
+            }
+            wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
+            coincident |= r2 < S.coincident2;
+            close |= r2 < S.close2;
+        });
     wsum = group_sum<G>(wsum);
     for (int o = 1; o < G; o <<= 1) {
         coincident |= __shfl_xor(coincident, o, 64);
@@ -795,34 +899,35 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     }
     const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
-    for (int k = g; k < cnt; k += G) {
-        const uint32_t j = nbr_at(A, i, k);
-        const Q4<R> gj = geo[j];
-        R r[3];
-        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
-        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const R inv_r = rsqrt_r<R>(r2);
-        const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
-        const R Vj = th[j].y;
-        const Q4<R> vj = vb[j];
-        const R eta_j = Geo<R>::phase(gj) == phi ? eta_i : eta_o;
-        const R es = eta_i + eta_j;
-        const R eta_bar = es > R(0) ? R(2) * eta_i * eta_j / es : R(0);
-        const R f = eta_bar * dW * inv_r * Vj;
-        av[0] += f * (vi.x - vj.x);
-        av[1] += f * (vi.y - vj.y);
-        if (D == 3) av[2] += f * (vi.z - vj.z);
-        const R gg = dW * Vj * inv_r;
-        M[0] += gg * r[0] * r[0];
-        M[1] += gg * r[0] * r[1];
-        M[3] += gg * r[1] * r[1];
-        if (D == 3) {
-            M[2] += gg * r[0] * r[2];
-            M[4] += gg * r[1] * r[2];
-            M[5] += gg * r[2] * r[2];
-        }
-        near |= A.flags[j] & kFlagInterface;
-    }
+    for_neighbours<G, 2>(
+        A, i, g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vb[j]}}; },
+        [&](uint32_t j, const Recs<R, 3>& rj) {
+            const Q4<R> gj = rj.q[0];
+            R r[3];
+            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const R inv_r = rsqrt_r<R>(r2);
+            const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
+            const R Vj = rj.q[1].y;
+            const Q4<R> vj = rj.q[2];
+            const R eta_j = Geo<R>::phase(gj) == phi ? eta_i : eta_o;
+            const R es = eta_i + eta_j;
+            const R eta_bar = es > R(0) ? R(2) * eta_i * eta_j / es : R(0);
+            const R f = eta_bar * dW * inv_r * Vj;
+            av[0] += f * (vi.x - vj.x);
+            av[1] += f * (vi.y - vj.y);
+            if (D == 3) av[2] += f * (vi.z - vj.z);
+            const R gg = dW * Vj * inv_r;
+            M[0] += gg * r[0] * r[0];
+            M[1] += gg * r[0] * r[1];
+            M[3] += gg * r[1] * r[1];
+            if (D == 3) {
+                M[2] += gg * r[0] * r[2];
+                M[4] += gg * r[1] * r[2];
+                M[5] += gg * r[2] * r[2];
+            }
+            near |= A.flags[j] & kFlagInterface;
+        });
     for (int a = 0; a < D; ++a) av[a] = group_sum<G>(av[a]);
     M[0] = group_sum<G>(M[0]);
     M[1] = group_sum<G>(M[1]);
@@ -916,27 +1021,28 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
         cnt = A.ncount[i];
     }
     R s[3] = {0, 0, 0};
-    for (int k = g; k < cnt; k += G) {
-        const uint32_t j = nbr_at(A, i, k);
-        const Q4<R> gj = geo[j];
-        R r[3];
-        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
-        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const R inv_r = rsqrt_r<R>(r2);
-        const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * th[j].y * inv_r;  // dW V_j / r
-        const Q4<R> Bj0 = b0[j], Bj1 = b1[j];
-        // (B_i + B_j) r_ij, symmetric storage 00 01 02 11 12 22
-        const R m00 = Bi0.x + Bj0.x, m01 = Bi0.y + Bj0.y, m11 = Bi0.w + Bj0.w;
-        if (D == 2) {
-            s[0] += f * (m00 * r[0] + m01 * r[1]);
-            s[1] += f * (m01 * r[0] + m11 * r[1]);
-        } else {
-            const R m02 = Bi0.z + Bj0.z, m12 = Bi1.x + Bj1.x, m22 = Bi1.y + Bj1.y;
-            s[0] += f * (m00 * r[0] + m01 * r[1] + m02 * r[2]);
-            s[1] += f * (m01 * r[0] + m11 * r[1] + m12 * r[2]);
-            s[2] += f * (m02 * r[0] + m12 * r[1] + m22 * r[2]);
-        }
-    }
+    for_neighbours<G, Chunk<R, D>::N>(
+        A, i, g, cnt, [&](uint32_t j) { return Recs<R, 4>{{geo[j], th[j], b0[j], b1[j]}}; },
+        [&](uint32_t j, const Recs<R, 4>& rj) {
+            const Q4<R> gj = rj.q[0];
+            R r[3];
+            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const R inv_r = rsqrt_r<R>(r2);
+            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * rj.q[1].y * inv_r;  // dW V_j / r
+            const Q4<R> Bj0 = rj.q[2], Bj1 = rj.q[3];
+            // (B_i + B_j) r_ij, symmetric storage 00 01 02 11 12 22
+            const R m00 = Bi0.x + Bj0.x, m01 = Bi0.y + Bj0.y, m11 = Bi0.w + Bj0.w;
+            if (D == 2) {
+                s[0] += f * (m00 * r[0] + m01 * r[1]);
+                s[1] += f * (m01 * r[0] + m11 * r[1]);
+            } else {
+                const R m02 = Bi0.z + Bj0.z, m12 = Bi1.x + Bj1.x, m22 = Bi1.y + Bj1.y;
+                s[0] += f * (m00 * r[0] + m01 * r[1] + m02 * r[2]);
+                s[1] += f * (m01 * r[0] + m11 * r[1] + m12 * r[2]);
+                s[2] += f * (m02 * r[0] + m12 * r[1] + m22 * r[2]);
+            }
+        });
     for (int a = 0; a < D; ++a) s[a] = group_sum<G>(s[a]);
     if (!c.lane || g != 0) return;
     double dr[3];
@@ -1116,40 +1222,44 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
-    Slot c = slot_of_group<G>(A, g);
+    const int64_t i = group_slot<G>(g);
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    NbrList<G, Chunk<R, D>::N> nl;
+    nl.start(A, i, g);
+    const int fl = A.flags[i];
+    const int cnt_i = A.ncount[i];
+    const Q4<R> gi_i = geo[i];
+    const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     const SysDyn& Dy = A.sd[c.s];
     if (!substep_on(Dy, A.mode)) return;
-    const int64_t i = c.i;
-    const bool on = c.lane && (A.flags[i] & kFlagInterface);
+    const bool on = c.lane && (fl & kFlagInterface);
     if (!__any(on)) return;  // wave without interface particles
     const SysConst& S = A.sc[c.s];
     const int slot = A.mode ? 0 : (int)(Dy.ksub & 1);
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    Q4<R> gi{0, 0, 0, 0};
-    int cnt = 0, phi = 0;
-    if (on) {
-        gi = geo[i];
-        phi = Geo<R>::phase(gi);
-        cnt = A.ncount[i];
-    }
+    const Q4<R> gi = on ? gi_i : Q4<R>{0, 0, 0, 0};
+    const int cnt = on ? cnt_i : 0;
+    const int phi = Geo<R>::phase(gi);
     R gsum[3] = {0, 0, 0};
-    for (int k = g; k < cnt; k += G) {
-        const uint32_t j = nbr_at(A, i, k);
-        const Q4<R> gj = geo[j];
-        if (Geo<R>::phase(gj) == phi) continue;
-        R r[3];
-        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
-        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const R inv_r = rsqrt_r<R>(r2);
-        const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * th[j].y * inv_r;
-        gsum[0] += f * r[0];
-        gsum[1] += f * r[1];
-        if (D == 3) gsum[2] += f * r[2];
-    }
+    nl.run(
+        g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], th[j]}}; },
+        [&](uint32_t j, const Recs<R, 2>& rj) {
+            const Q4<R> gj = rj.q[0];
+            if (Geo<R>::phase(gj) == phi) return;
+            R r[3];
+            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const R inv_r = rsqrt_r<R>(r2);
+            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * rj.q[1].y * inv_r;
+            gsum[0] += f * r[0];
+            gsum[1] += f * r[1];
+            if (D == 3) gsum[2] += f * r[2];
+        });
     for (int a = 0; a < D; ++a) gsum[a] = group_sum<G>(gsum[a]);
     if (!on || g != 0) return;
     // 2 phi_i = 2 rho0_i / (rho0_i + rho0_j) for a neighbour of the other fluid
@@ -1172,33 +1282,43 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
-    Slot c = slot_of_group<G>(A, g);
+    const int64_t i = group_slot<G>(g);
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* col = (const Q4<R>*)A.col;
+    NbrList<G, Chunk<R, D>::N> nl;
+    nl.start(A, i, g);
+    const int fl = A.flags[i];
+    const int cnt_i = A.ncount[i];
+    const Q4<R> gi_i = geo[i];
+    // particles away from the interface all read entry 0 (one cache line)
+    const Q4<R> ci_i = col[(fl & kFlagNearInterface) ? i : 0];
+    const Q4<R> av_i = ((const Q4<R>*)A.av)[i];
+    double vel_i[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) vel_i[a] = A.vel[a][i];
+    const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
     if (!substep_on(Dy, A.mode)) return;  // wave-uniform
     const SysConst& S = A.sc[c.s];
-    const int64_t i = c.i;
     const int64_t kk = A.mode ? 0 : Dy.ksub;
     const int slot = (int)(kk & 1);
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
     const Q4<R>* vin = (const Q4<R>*)A.vbuf[slot];
-    const Q4<R>* col = (const Q4<R>*)A.col;
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const R c0 = (R)S.c0, inv_c0 = (R)S.inv_c0;
-    Q4<R> gi{0, 0, 0, 0}, ti{1, 0, 0, 0}, vi{0, 0, 0, 0}, ci{0, 0, 0, 0};
-    int cnt = 0, phi = 0;
-    bool surface = false;
+    Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
     if (c.lane) {
-        gi = geo[i];
         ti = th[i];
         vi = vin[i];
-        phi = Geo<R>::phase(gi);
-        cnt = A.ncount[i];
-        surface = (A.flags[i] & kFlagNearInterface) && !(S.flags & kNoSurface);
-        if (surface) ci = col[i];
     }
+    const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
+    const int cnt = c.lane ? cnt_i : 0;
+    const int phi = Geo<R>::phase(gi);
+    const bool surface = c.lane && (fl & kFlagNearInterface) && !(S.flags & kNoSurface);
+    const Q4<R> ci = surface ? ci_i : Q4<R>{0, 0, 0, 0};
     const bool penalty = !(S.flags & kNoPenalty);
     const bool single = (S.flags & kGbarSingleField) != 0;
     const bool r3 = (S.flags & kPenaltyR3) != 0;
@@ -1210,86 +1330,87 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     const R pen_x = R(-4) * phi_i_x * phi_j_x * xg;
     const R gni = (ci.x * ci.x + ci.y * ci.y + ci.z * ci.z) * ci.w;  // |grad C_i|
     R sp[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
-    for (int k = g; k < cnt; k += G) {
-        const uint32_t j = nbr_at(A, i, k);
-        const Q4<R> gj = geo[j];
-        R r[3];
-        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
-        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const R inv_r = rsqrt_r<R>(r2);
-        const R rr = r2 * inv_r;
-        const R dW = wendland_dw<R>(rr * inv_h, coef);
-        const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
-        const Q4<R> tj = th[j];
-        const Q4<R> vj = vin[j];
-        const R Vj = tj.y;
-        // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
-        const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
-        const R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
-        const R dU = UL - UR;
-        const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
-        const R Pstar = (ti.x * tj.z + tj.x * ti.z + beta * c0 * ti.x * tj.x * dU) / (ti.x + tj.x);
-        const R fp = Pstar * dW * Vj;
-        sp[0] += fp * e[0];
-        sp[1] += fp * e[1];
-        if (D == 3) sp[2] += fp * e[2];
-        if (!surface) continue;
-        const bool same = Geo<R>::phase(gj) == phi;
-        const Q4<R> cj = col[j];
-        const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
-        // Pi e = gamma (|g| e - g (g . e) / |g|)
-        const R gie = (ci.x * e[0] + ci.y * e[1] + ci.z * e[2]) * ci.w;
-        const R gje = (cj.x * e[0] + cj.y * e[1] + cj.z * e[2]) * cj.w;
-        const R wi = same ? R(1) : R(2) * phi_j_x;
-        const R wj = same ? R(1) : R(2) * phi_i_x;
-        R se[3];
-        se[0] = gamma * (wi * (gni * e[0] - ci.x * gie) + wj * (gnj * e[0] - cj.x * gje));
-        se[1] = gamma * (wi * (gni * e[1] - ci.y * gie) + wj * (gnj * e[1] - cj.y * gje));
-        se[2] = gamma * (wi * (gni * e[2] - ci.z * gie) + wj * (gnj * e[2] - cj.z * gje));
-        const R fs = dW * Vj;
-        ss[0] += fs * se[0];
-        ss[1] += fs * se[1];
-        if (D == 3) ss[2] += fs * se[2];
-        if (!penalty) continue;
-        // Eq. 27 and Eq. 30 (reading R1): Chat grad W = dW [C e - (gbar.r) gbar/|gbar|]
-        const R sgn = (single && !same) ? R(-1) : R(1);
-        const R gb[3] = {R(0.5) * (ci.x + sgn * cj.x), R(0.5) * (ci.y + sgn * cj.y),
-                         R(0.5) * (ci.z + sgn * cj.z)};
-        const R gb2 = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
-        const R gbr = gb[0] * r[0] + gb[1] * r[1] + gb[2] * r[2];
-        const R inv_gb = gb2 > R(0) ? rsqrt_r<R>(gb2) : R(0);
-        const R C = same ? R(0) : R(1);
-        R q[3];
-        if (r3) {
-            const R sc = dW * (C - gbr * gbr * inv_gb * inv_r);
-            q[0] = sc * e[0];
-            q[1] = sc * e[1];
-            q[2] = sc * e[2];
-        } else {
-            const R t = gbr * inv_gb;
-            q[0] = dW * (C * e[0] - t * gb[0]);
-            q[1] = dW * (C * e[1] - t * gb[1]);
-            q[2] = dW * (C * e[2] - t * gb[2]);
-        }
-        // Nbar q = (n_i (n_i . q) + n_j (n_j . q)) / 2 with n = g / |g|
-        const R niq = (ci.x * q[0] + ci.y * q[1] + ci.z * q[2]) * ci.w * ci.w;
-        const R njq = (cj.x * q[0] + cj.y * q[1] + cj.z * q[2]) * cj.w * cj.w;
-        R Nq[3];
-        Nq[0] = R(0.5) * (ci.x * niq + cj.x * njq);
-        Nq[1] = R(0.5) * (ci.y * niq + cj.y * njq);
-        Nq[2] = R(0.5) * (ci.z * niq + cj.z * njq);
-        const R pc = (same ? xg : pen_x) * inv_r * Vj;
-        if (same) {
-            // Tbar q = q - Nbar q
-            ss[0] += pc * (q[0] - Nq[0]);
-            ss[1] += pc * (q[1] - Nq[1]);
-            if (D == 3) ss[2] += pc * (q[2] - Nq[2]);
-        } else {
-            ss[0] += pc * Nq[0];
-            ss[1] += pc * Nq[1];
-            if (D == 3) ss[2] += pc * Nq[2];
-        }
-    }
+    nl.run(
+        g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vin[j]}}; },
+        [&](uint32_t j, const Recs<R, 3>& rj) {
+            const Q4<R> gj = rj.q[0];
+            R r[3];
+            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const R inv_r = rsqrt_r<R>(r2);
+            const R rr = r2 * inv_r;
+            const R dW = wendland_dw<R>(rr * inv_h, coef);
+            const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+            const Q4<R> tj = rj.q[1];
+            const Q4<R> vj = rj.q[2];
+            const R Vj = tj.y;
+            // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
+            const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
+            const R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
+            const R dU = UL - UR;
+            const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
+            const R Pstar = (ti.x * tj.z + tj.x * ti.z + beta * c0 * ti.x * tj.x * dU) / (ti.x + tj.x);
+            const R fp = Pstar * dW * Vj;
+            sp[0] += fp * e[0];
+            sp[1] += fp * e[1];
+            if (D == 3) sp[2] += fp * e[2];
+            if (!surface) return;
+            const bool same = Geo<R>::phase(gj) == phi;
+            const Q4<R> cj = col[j];
+            const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
+            // Pi e = gamma (|g| e - g (g . e) / |g|)
+            const R gie = (ci.x * e[0] + ci.y * e[1] + ci.z * e[2]) * ci.w;
+            const R gje = (cj.x * e[0] + cj.y * e[1] + cj.z * e[2]) * cj.w;
+            const R wi = same ? R(1) : R(2) * phi_j_x;
+            const R wj = same ? R(1) : R(2) * phi_i_x;
+            R se[3];
+            se[0] = gamma * (wi * (gni * e[0] - ci.x * gie) + wj * (gnj * e[0] - cj.x * gje));
+            se[1] = gamma * (wi * (gni * e[1] - ci.y * gie) + wj * (gnj * e[1] - cj.y * gje));
+            se[2] = gamma * (wi * (gni * e[2] - ci.z * gie) + wj * (gnj * e[2] - cj.z * gje));
+            const R fs = dW * Vj;
+            ss[0] += fs * se[0];
+            ss[1] += fs * se[1];
+            if (D == 3) ss[2] += fs * se[2];
+            if (!penalty) return;
+            // Eq. 27 and Eq. 30 (reading R1): Chat grad W = dW [C e - (gbar.r) gbar/|gbar|]
+            const R sgn = (single && !same) ? R(-1) : R(1);
+            const R gb[3] = {R(0.5) * (ci.x + sgn * cj.x), R(0.5) * (ci.y + sgn * cj.y),
+                             R(0.5) * (ci.z + sgn * cj.z)};
+            const R gb2 = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
+            const R gbr = gb[0] * r[0] + gb[1] * r[1] + gb[2] * r[2];
+            const R inv_gb = gb2 > R(0) ? rsqrt_r<R>(gb2) : R(0);
+            const R C = same ? R(0) : R(1);
+            R q[3];
+            if (r3) {
+                const R sc = dW * (C - gbr * gbr * inv_gb * inv_r);
+                q[0] = sc * e[0];
+                q[1] = sc * e[1];
+                q[2] = sc * e[2];
+            } else {
+                const R t = gbr * inv_gb;
+                q[0] = dW * (C * e[0] - t * gb[0]);
+                q[1] = dW * (C * e[1] - t * gb[1]);
+                q[2] = dW * (C * e[2] - t * gb[2]);
+            }
+            // Nbar q = (n_i (n_i . q) + n_j (n_j . q)) / 2 with n = g / |g|
+            const R niq = (ci.x * q[0] + ci.y * q[1] + ci.z * q[2]) * ci.w * ci.w;
+            const R njq = (cj.x * q[0] + cj.y * q[1] + cj.z * q[2]) * cj.w * cj.w;
+            R Nq[3];
+            Nq[0] = R(0.5) * (ci.x * niq + cj.x * njq);
+            Nq[1] = R(0.5) * (ci.y * niq + cj.y * njq);
+            Nq[2] = R(0.5) * (ci.z * niq + cj.z * njq);
+            const R pc = (same ? xg : pen_x) * inv_r * Vj;
+            if (same) {
+                // Tbar q = q - Nbar q
+                ss[0] += pc * (q[0] - Nq[0]);
+                ss[1] += pc * (q[1] - Nq[1]);
+                if (D == 3) ss[2] += pc * (q[2] - Nq[2]);
+            } else {
+                ss[0] += pc * Nq[0];
+                ss[1] += pc * Nq[1];
+                if (D == 3) ss[2] += pc * Nq[2];
+            }
+        });
     for (int a = 0; a < D; ++a) {
         sp[a] = group_sum<G>(sp[a]);
         ss[a] = group_sum<G>(ss[a]);
@@ -1297,8 +1418,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     unsigned long long m0 = 0, m1 = 0;
     if (c.lane && g == 0) {
         const R inv_rho = R(1) / ti.x;
-        const Q4<R> av = ((const Q4<R>*)A.av)[i];
-        const R avv[3] = {av.x, av.y, av.z};
+        const R avv[3] = {av_i.x, av_i.y, av_i.z};
         double acc[3];
         for (int a = 0; a < 3; ++a)
             acc[a] = a < D ? (double)(R(-2) * inv_rho * sp[a]) + (double)(inv_rho * ss[a]) +
@@ -1318,7 +1438,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             double v2 = 0.0;
             bool bad = false;
             for (int a = 0; a < D; ++a) {
-                v[a] = A.vel[a][i] + dt * acc[a];
+                v[a] = vel_i[a] + dt * acc[a];
                 A.vel[a][i] = v[a];
                 v2 += v[a] * v[a];
                 bad |= !isfinite(v[a]);
@@ -1362,48 +1482,61 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
-    Slot c = slot_of_group<G>(A, g);
+    const int64_t i = group_slot<G>(g);
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    NbrList<G, Chunk<R, D>::N> nl;
+    nl.start(A, i, g);
+    const int cnt_i = A.ncount[i];
+    const Q4<R> gi_i = geo[i];
+    // FP64 state of the particle for the update that follows the sum
+    const double rho_i = A.rho[i], mass_i = A.mass[i];
+    double pos_i[3] = {0.0, 0.0, 0.0}, vel_i[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) {
+        pos_i[a] = A.pos[a][i];
+        vel_i[a] = A.vel[a][i];
+    }
+    const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
     const int st = Dy.state;
     if (A.mode == 0 && st != kSubstepping && st != kEnding) return;
     if (A.mode == 1 && !Dy.stepping) return;
     const SysConst& S = A.sc[c.s];
-    const int64_t i = c.i;
     // the substep this pass completes (its force pass already advanced ksub)
     const int64_t kk = A.mode ? 0 : Dy.ksub - 1;
     const int slot = (int)(kk & 1);
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
     const Q4<R>* vk = (const Q4<R>*)A.vbuf[slot ^ 1];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const R inv_c0 = (R)S.inv_c0;
-    Q4<R> gi{0, 0, 0, 0}, ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
-    int cnt = 0;
+    Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
     if (c.lane) {
-        gi = geo[i];
         ti = th[i];
         vi = vk[i];
-        cnt = A.ncount[i];
     }
+    const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
+    const int cnt = c.lane ? cnt_i : 0;
     R s = 0;
-    for (int k = g; k < cnt; k += G) {
-        const uint32_t j = nbr_at(A, i, k);
-        const Q4<R> gj = geo[j];
-        R r[3];
-        Geo<R>::template rij<D>(gi, gj, S, cellr, r);
-        const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const R inv_r = rsqrt_r<R>(r2);
-        const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
-        const Q4<R> tj = th[j];
-        const Q4<R> vj = vk[j];
-        const R vie = (vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
-        const R vje = (vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
-        // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e
-        const R Ustar = (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
-        s += (vie + Ustar) * dW * tj.y;
-    }
+    nl.run(
+        g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vk[j]}}; },
+        [&](uint32_t j, const Recs<R, 3>& rj) {
+            const Q4<R> gj = rj.q[0];
+            R r[3];
+            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const R inv_r = rsqrt_r<R>(r2);
+            const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
+            const Q4<R> tj = rj.q[1];
+            const Q4<R> vj = rj.q[2];
+            const R vie = (vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
+            const R vje = (vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
+            // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e
+            const R Ustar = (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
+            s += (vie + Ustar) * dW * tj.y;
+        });
     s = group_sum<G>(s);
     if (!c.lane || g != 0) return;
     const double drho = 2.0 * (double)ti.x * (double)s;
@@ -1412,16 +1545,17 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A)
         return;
     }
     const double dt = Dy.dt[kk & 1];
-    double rho = A.rho[i] + 0.5 * dt * drho;
-    for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt * A.vel[a][i];
+    double rho = rho_i + 0.5 * dt * drho;
+    for (int a = 0; a < D; ++a) pos_i[a] += 0.5 * dt * vel_i[a];
     if (st == kSubstepping) {
         const double dt2 = Dy.dt[(kk + 1) & 1];
         rho += 0.5 * dt2 * drho;
-        for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt2 * A.vel[a][i];
+        for (int a = 0; a < D; ++a) pos_i[a] += 0.5 * dt2 * vel_i[a];
         const int ph = Geo<R>::phase(gi);
         ((Q4<R>*)A.th[slot ^ 1])[i] =
-            Q4<R>{(R)rho, (R)(A.mass[i] / rho), (R)(S.c0sq * (rho - S.rho0[ph])), (R)0};
+            Q4<R>{(R)rho, (R)(mass_i / rho), (R)(S.c0sq * (rho - S.rho0[ph])), (R)0};
     }
+    for (int a = 0; a < D; ++a) A.pos[a][i] = pos_i[a];
     A.rho[i] = rho;
     A.drho[i] = drho;
     if (!(rho > 0.0)) flag_health(Dy, isfinite(rho) ? kHealthDensity : kHealthNonFinite);
