@@ -562,19 +562,23 @@ __global__ __launch_bounds__(kBlock) void k_copyback(DevArrays A)
 // the block's 64 slots lie in a few consecutive cells, so the union of their
 // 3^d stencils is a small box of cells whose particles are copied once per
 // block as FP32 offsets from their own cell corner.  A candidate is tested in
-// FP32 on these split positions; only candidates within a relative 1e-5 of the
-// cut-off (2h)^2 are decided by the exact FP64 predicate on the stored
-// positions, so the neighbour set is exactly the one of the FP64 predicate.
+// FP32 on these split positions.  Candidates within a relative 1e-5 of the
+// cut-off (2h)^2 are entered with a mark and afterwards decided by the exact
+// FP64 predicate on the stored positions (the list is compacted), so the
+// neighbour set is exactly the one of the FP64 predicate.  The three cells of
+// a stencil row are consecutive both in LDS and, unless the row wraps around
+// the periodic box, in the cell-sorted slots, so a row is scanned as one range.
 // Blocks whose union does not fit fall back to testing every candidate in FP64
-// from global memory; both paths produce the same list in the same order.
+// from global memory; both paths produce the same list in the same order
+// (stencil cells in z, y, x order, slots ascending within a cell).
 constexpr int kStageCells = 128;
-constexpr int kStageCap = 2560;
+constexpr int kStageCap = 2304;
+constexpr uint32_t kBandMark = 0x80000000u;  // list entry awaiting the exact test
 
 struct Stage {
-    float x[kStageCap];
-    float y[kStageCap];
-    float z[kStageCap];
-    int8_t ph[kStageCap];
+    // x, y, z offsets from the candidate's own cell corner; w holds the bits
+    // of (union-local x cell << 1) | phase
+    float4 q[kStageCap];
     int32_t off[kStageCells + 1];  // LDS offset of each union cell
     int32_t gs[kStageCells];       // first global slot of each union cell
     int32_t lo[3], hi[3];          // cell-coordinate bounds of the block's particles
@@ -654,13 +658,16 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
         const int cx = wrap_cell(L.lo[0] - 1 + lx, S.ncell[0]);
         const int cy = wrap_cell(L.lo[1] - 1 + ly, S.ncell[1]);
         const int64_t j = L.gs[lo] + (k - L.off[lo]);
-        L.x[k] = (float)(A.pos[0][j] - (double)cx * S.cell[0]);
-        L.y[k] = (float)(A.pos[1][j] - (double)cy * S.cell[1]);
+        float4 q;
+        q.x = (float)(A.pos[0][j] - (double)cx * S.cell[0]);
+        q.y = (float)(A.pos[1][j] - (double)cy * S.cell[1]);
+        q.z = 0.f;
         if (D == 3) {
             const int cz = wrap_cell(L.lo[2] - 1 + lz, S.ncell[2]);
-            L.z[k] = (float)(A.pos[2][j] - (double)cz * S.cell[2]);
+            q.z = (float)(A.pos[2][j] - (double)cz * S.cell[2]);
         }
-        L.ph[k] = (int8_t)A.phase[j];
+        q.w = __int_as_float((lx << 1) | (A.phase[j] & 1));
+        L.q[k] = q;
     }
     __syncthreads();
 }
@@ -686,12 +693,87 @@ __device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi,
     return r2;
 }
 
+// periodic image offset of the stencil cell holding slot j, for a particle in
+// cell ci: the stencil reaches one cell either way and wraps at the box edges
+template <int D>
+__device__ __forceinline__ void stencil_shift(const DevArrays& A, const SysConst& S, int64_t j, const int* ci,
+                                              double* k)
+{
+    for (int a = 0; a < 3; ++a) {
+        k[a] = 0.0;
+        if (a >= D) continue;
+        const int d = cell_of(A.pos[a][j], S, a) - ci[a];
+        if (d == S.ncell[a] - 1) k[a] = -S.box[a];
+        else if (d == -(S.ncell[a] - 1)) k[a] = S.box[a];
+    }
+}
+
+// Ordered append of the hits of G consecutive candidates tested by the lanes
+// of a group: the ballot keeps the list in candidate order.
+template <int G>
+__device__ __forceinline__ void append_hits(bool hit, uint32_t entry, int gshift, uint32_t below, uint32_t* out,
+                                            int kmax, int& cnt)
+{
+    const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
+    if (hit) {
+        const int at = cnt + __popc(gm & below);
+        if (at < kmax) out[(int64_t)at * kWave] = entry;
+    }
+    cnt += __popc(gm);
+}
+
+// Every candidate of the 3^d stencil tested by the exact FP64 predicate on
+// positions in global memory (blocks whose union does not fit in LDS, and the
+// rare list that overflowed before its marked entries were decided).
+template <int D, int G>
+__device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, const double* xi, const int* ci,
+                            int ph, bool live, int g, int gshift, uint32_t below, int64_t base, uint32_t* out,
+                            int& cnt, int& cross)
+{
+    const int zr = D == 3 ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz) {
+        int cz = ci[2] + dz;
+        double kz = 0.0;
+        if (D == 3) {
+            if (cz < 0) { cz += S.ncell[2]; kz = -S.box[2]; }
+            else if (cz >= S.ncell[2]) { cz -= S.ncell[2]; kz = S.box[2]; }
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int cy = ci[1] + dy;
+            double ky = 0.0;
+            if (cy < 0) { cy += S.ncell[1]; ky = -S.box[1]; }
+            else if (cy >= S.ncell[1]) { cy -= S.ncell[1]; ky = S.box[1]; }
+            for (int dx = -1; dx <= 1; ++dx) {
+                int cx = ci[0] + dx;
+                double kx = 0.0;
+                if (cx < 0) { cx += S.ncell[0]; kx = -S.box[0]; }
+                else if (cx >= S.ncell[0]) { cx -= S.ncell[0]; kx = S.box[0]; }
+                int64_t jb = 0, je = 0;
+                if (live) {
+                    const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
+                    jb = base + A.cell_start[gc];
+                    je = base + A.cell_start[gc + 1];
+                }
+                for (int64_t j0 = jb; j0 < je; j0 += G) {
+                    const int64_t j = j0 + g;
+                    bool hit = false;
+                    if (j < je && j != i) {
+                        hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
+                        if (hit) cross |= A.phase[j] != ph;
+                    }
+                    append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
+                }
+            }
+        }
+    }
+}
+
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
 {
-    // the candidates of a stencil cell are tested G at a time by the lanes of
+    // the candidates of a stencil row are tested G at a time by the lanes of
     // the particle's group; an ordered ballot keeps the list in candidate
-    // order (stencil cells in a fixed order, slots ascending within a cell)
+    // order
     constexpr int G = Lanes<D>::G;
     __shared__ Stage L;
     int g;
@@ -716,83 +798,95 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
         ph = A.phase[i];
     }
     stage_union<D>(A, S, L, base, live, ci, g);
-    const bool lds = L.ok;
-    float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
-    for (int a = 0; a < 3; ++a) {
-        cellf[a] = (float)S.cell[a];
-        if (a < D) oi[a] = (float)(xi[a] - (double)ci[a] * S.cell[a]);
-    }
-    const float cut_hi = (float)(S.cut2 * (1.0 + 1e-5)), cut_lo = (float)(S.cut2 * (1.0 - 1e-5));
     int cnt = 0;
     int cross = 0;
     uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
-    const int zr = D == 3 ? 1 : 0;
-    for (int dz = -zr; dz <= zr; ++dz) {
-        int cz = ci[2] + dz;
-        double kz = 0.0;
-        if (D == 3) {
-            if (cz < 0) { cz += S.ncell[2]; kz = -S.box[2]; }
-            else if (cz >= S.ncell[2]) { cz -= S.ncell[2]; kz = S.box[2]; }
+    bool marked = false;
+    if (L.ok) {  // block-uniform
+        float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
+        for (int a = 0; a < 3; ++a) {
+            cellf[a] = (float)S.cell[a];
+            if (a < D) oi[a] = (float)(xi[a] - (double)ci[a] * S.cell[a]);
         }
-        const float rz0 = oi[2] - (float)dz * cellf[2];
-        for (int dy = -1; dy <= 1; ++dy) {
-            int cy = ci[1] + dy;
-            double ky = 0.0;
-            if (cy < 0) { cy += S.ncell[1]; ky = -S.box[1]; }
-            else if (cy >= S.ncell[1]) { cy -= S.ncell[1]; ky = S.box[1]; }
-            const float ry0 = oi[1] - (float)dy * cellf[1];
-            for (int dx = -1; dx <= 1; ++dx) {
-                int cx = ci[0] + dx;
-                double kx = 0.0;
-                if (cx < 0) { cx += S.ncell[0]; kx = -S.box[0]; }
-                else if (cx >= S.ncell[0]) { cx -= S.ncell[0]; kx = S.box[0]; }
-                const float rx0 = oi[0] - (float)dx * cellf[0];
-                int64_t jb = 0, je = 0, gs0 = 0;
+        const float cut_hi = (float)(S.cut2 * (1.0 + 1e-5)), cut_lo = (float)(S.cut2 * (1.0 - 1e-5));
+        // the particle's union-local cell
+        const int lx = ci[0] - L.lo[0] + 1, ly = ci[1] - L.lo[1] + 1, lz = D == 3 ? ci[2] - L.lo[2] + 1 : 0;
+        const int zr = D == 3 ? 1 : 0;
+        for (int dz = -zr; dz <= zr; ++dz) {
+            const float rz0 = oi[2] - (float)dz * cellf[2];
+            for (int dy = -1; dy <= 1; ++dy) {
+                const float ry0 = oi[1] - (float)dy * cellf[1];
+                // the row's three cells
+                int u0 = 0, rb = 0, re = 0;
+                bool contiguous = true;
                 if (live) {
-                    if (lds) {
-                        const int lx = ci[0] + dx - (L.lo[0] - 1), ly = ci[1] + dy - (L.lo[1] - 1);
-                        const int lz = D == 3 ? ci[2] + dz - (L.lo[2] - 1) : 0;
-                        const int u = lx + L.dims[0] * (ly + L.dims[1] * lz);
-                        jb = L.off[u];
-                        je = L.off[u + 1];
-                        gs0 = L.gs[u] - jb;
-                    } else {
-                        const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
-                        jb = base + A.cell_start[gc];
-                        je = base + A.cell_start[gc + 1];
-                    }
+                    u0 = (lx - 1) + L.dims[0] * ((ly + dy) + L.dims[1] * (lz + dz));
+                    rb = L.off[u0];
+                    re = L.off[u0 + 3];
+                    contiguous = L.gs[u0 + 1] - L.gs[u0] == L.off[u0 + 1] - rb &&
+                                 L.gs[u0 + 2] - L.gs[u0 + 1] == L.off[u0 + 2] - L.off[u0 + 1];
                 }
-                for (int64_t j0 = jb; j0 < je; j0 += G) {
-                    const int64_t k = j0 + g;
-                    const int64_t j = lds ? gs0 + k : k;
-                    bool hit = false;
-                    int phj = 0;
-                    if (k < je && j != i) {
-                        if (lds) {
-                            const float ax = rx0 - L.x[k], ay = ry0 - L.y[k];
-                            const float az = D == 3 ? rz0 - L.z[k] : 0.f;
+                // a row that wraps around the box is scanned cell by cell
+                const int nseg = contiguous ? 1 : 3;
+                for (int sgm = 0; sgm < nseg; ++sgm) {
+                    const int kb = contiguous ? rb : L.off[u0 + sgm];
+                    const int ke = contiguous ? re : L.off[u0 + sgm + 1];
+                    const int64_t jofs = (int64_t)L.gs[contiguous ? u0 : u0 + sgm] - kb;
+                    for (int k0 = kb; k0 < ke; k0 += G) {
+                        const int k = k0 + g;
+                        bool hit = false, band = false;
+                        const int64_t j = jofs + k;
+                        if (k < ke && j != i) {
+                            const float4 q = L.q[k];
+                            const int w = __float_as_int(q.w);
+                            const float ax = (oi[0] - q.x) - (float)((w >> 1) - lx) * cellf[0];
+                            const float ay = ry0 - q.y;
+                            const float az = D == 3 ? rz0 - q.z : 0.f;
                             const float r2f = ax * ax + ay * ay + az * az;
-                            phj = L.ph[k];
-                            if (r2f < cut_lo) hit = true;
-                            else if (r2f < cut_hi) hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
-                        } else {
-                            phj = A.phase[j];
-                            hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
+                            hit = r2f < cut_hi;
+                            band = r2f >= cut_lo;
+                            if (hit) cross |= (w & 1) != ph;
                         }
+                        marked |= hit && band;
+                        append_hits<G>(hit, (uint32_t)j | (band ? kBandMark : 0u), gshift, below, out, A.kmax,
+                                       cnt);
                     }
-                    const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
-                    if (hit) {
-                        const int at = cnt + __popc(gm & below);
-                        if (at < A.kmax) out[(int64_t)at * kWave] = (uint32_t)j;
-                        cross |= phj != ph;
-                    }
-                    cnt += __popc(gm);
                 }
             }
         }
+    } else {
+        scan_global<D, G>(A, S, i, xi, ci, ph, live, g, gshift, below, base, out, cnt, cross);
+    }
+    int mk = marked;
+    for (int o = 1; o < G; o <<= 1) mk |= __shfl_xor(mk, o, 64);
+    if (mk && cnt > A.kmax) {  // group-uniform
+        // entries were lost before the marked ones were decided: rescan exactly
+        cnt = 0;
+        cross = 0;
+        scan_global<D, G>(A, S, i, xi, ci, ph, live, g, gshift, below, base, out, cnt, cross);
     }
     for (int o = 1; o < G; o <<= 1) cross |= __shfl_xor(cross, o, 64);
     if (!live || g != 0) return;
+    if (mk && cnt <= A.kmax) {
+        // entries near the cut-off: the exact FP64 predicate decides, in list
+        // order, and the list is compacted
+        int kept = 0;
+        int xc = 0;
+        for (int q = 0; q < cnt; ++q) {
+            uint32_t e = out[(int64_t)q * kWave];
+            if (e & kBandMark) {
+                e &= ~kBandMark;
+                double ks[3];
+                stencil_shift<D>(A, S, e, ci, ks);
+                if (!(exact_r2<D>(A, xi, e, ks[0], ks[1], ks[2]) < S.cut2)) continue;
+            }
+            xc |= A.phase[e] != ph;
+            out[(int64_t)kept * kWave] = e;
+            ++kept;
+        }
+        cnt = kept;
+        cross = xc;
+    }
     if (cnt > A.kmax) {
         flag_health(Dy, kHealthNeighbours);
         cnt = A.kmax;
