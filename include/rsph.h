@@ -211,6 +211,19 @@ enum {
 rsph_status rsph_set_kernel_timing(rsph_system* sys, int32_t kernel_mask);
 rsph_status rsph_read_kernel_timing(rsph_system* sys, int64_t* launches, double* ms);
 
+/* Launch mode of the stepping calls (rsph_step, rsph_pool_step) of the pool
+ * that holds sys.  RSPH_LAUNCH_GRAPH (the default): each launch cycle (the
+ * advection-step prologue and the acoustic substeps that follow it) is
+ * captured once as a HIP graph on the pool's stream and replayed; a graph is
+ * kept per substep count and per pool layout, and is captured again after an
+ * admission or release changes the layout.  RSPH_LAUNCH_EAGER: every kernel
+ * is launched individually.  Both modes launch the same kernels with the same
+ * arguments, so their results are identical bit for bit.  While kernel timing
+ * is on, launches are eager.  Synchronises the stream.  RSPH_EINVAL for an
+ * unknown mode. */
+enum { RSPH_LAUNCH_GRAPH = 0, RSPH_LAUNCH_EAGER = 1 };
+rsph_status rsph_set_launch_mode(rsph_system* sys, int32_t mode);
+
 /* Frees the system and its device memory.  NULL is ignored. */
 void rsph_destroy_system(rsph_system* sys);
 

@@ -77,6 +77,16 @@ struct TimedLaunch {
 
 }  // namespace
 
+// One launch cycle captured as a graph: valid for its substep count and for
+// the exact kernel arguments (array addresses and capacities) it was captured
+// with.
+struct CycleGraph {
+    int64_t m = -1;
+    DevArrays view{};
+    hipGraphExec_t exec = nullptr;
+};
+constexpr size_t kGraphCache = 6;
+
 struct rsph_pool {
     int dim = 2;
     int precision = RSPH_FP64;
@@ -103,6 +113,9 @@ struct rsph_pool {
     std::vector<hipEvent_t> event_pool;
     int64_t t_launches[RSPH_KERNEL_COUNT] = {};
     double t_ms[RSPH_KERNEL_COUNT] = {};
+    // launch cycles captured as HIP graphs, replayed while kernel timing is off
+    bool graphs = true;
+    std::vector<CycleGraph> cycle_graphs;
 };
 
 struct rsph_system {
@@ -226,8 +239,16 @@ struct Alloc {
     }
 };
 
+void drop_graphs(rsph_pool* P)
+{
+    for (auto& g : P->cycle_graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    P->cycle_graphs.clear();
+}
+
 void free_arrays(rsph_pool* P)
 {
+    drop_graphs(P);
     for (void* p : P->allocs) (void)hipFree(p);
     P->allocs.clear();
     P->bytes = 0;
@@ -583,7 +604,7 @@ constexpr int64_t kMaxSubsteps = 1000000;  // per advection step
 // then m acoustic substeps for systems inside an advection step.  Every kernel
 // checks its system's state on the device, so no host synchronisation is
 // needed between cycles.
-void launch_cycle(rsph_pool* P, int64_t m)
+void launch_cycle_eager(rsph_pool* P, int64_t m)
 {
     const Launch L = launch_of(P);
     if (P->timing && P->next_group + m + 1 > P->A.work_cap) collect_timing(P);
@@ -617,6 +638,46 @@ void launch_cycle(rsph_pool* P, int64_t m)
             launch_continuity(L, A, t.ev);
         }
     }
+}
+
+// A launch cycle, replayed from a captured graph unless kernel timing is on
+// (timed launches carry their own events) or graphs are switched off.  The
+// cycle holds kernel launches only, so its graph has kernel nodes only.
+void launch_cycle(rsph_pool* P, int64_t m)
+{
+    if (P->timing || !P->graphs) {
+        launch_cycle_eager(P, m);
+        return;
+    }
+    const DevArrays A = kernel_view(P);
+    CycleGraph* hit = nullptr;
+    for (auto& g : P->cycle_graphs)
+        if (g.m == m && std::memcmp(&g.view, &A, sizeof A) == 0) hit = &g;
+    if (!hit) {
+        if (P->cycle_graphs.size() >= kGraphCache) {
+            (void)hipGraphExecDestroy(P->cycle_graphs.front().exec);
+            P->cycle_graphs.erase(P->cycle_graphs.begin());
+        }
+        const int64_t group0 = P->next_group;
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            launch_cycle_eager(P, m);
+        } catch (...) {
+            (void)hipStreamEndCapture(P->stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHECK(hipStreamEndCapture(P->stream, &graph));
+        P->next_group = group0;
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHECK(e);
+        P->cycle_graphs.push_back(CycleGraph{m, A, exec});
+        hit = &P->cycle_graphs.back();
+    }
+    HIPCHECK(hipGraphLaunch(hit->exec, P->stream));
 }
 
 // Advances every system of the pool to its device-side target.  Returns the
@@ -1186,6 +1247,18 @@ rsph_status rsph_read_neighbours(rsph_system* s, int64_t n, int64_t cap, int64_t
             for (int q = 0; q < cnt[k]; ++q)
                 idx[dst + q] = id[nb[(w * A.kmax + q) * kWave + lane]];
         }
+    });
+}
+
+rsph_status rsph_set_launch_mode(rsph_system* s, int32_t mode)
+{
+    if (!s) return RSPH_EINVAL;
+    return guarded(&s->err, [&] {
+        if (mode != RSPH_LAUNCH_GRAPH && mode != RSPH_LAUNCH_EAGER) fail(RSPH_EINVAL, "unknown launch mode");
+        rsph_pool* P = s->pool;
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        P->graphs = mode == RSPH_LAUNCH_GRAPH;
+        if (!P->graphs) drop_graphs(P);
     });
 }
 

@@ -93,7 +93,7 @@ class Observables(C.Structure):
 SYMBOLS = [
     "rsph_params_default", "rsph_create_system", "rsph_set_particles", "rsph_set_drho",
     "rsph_step", "rsph_eval_rates", "rsph_read_observables", "rsph_read_particles",
-    "rsph_read_binning", "rsph_read_neighbours", "rsph_set_kernel_timing",
+    "rsph_read_binning", "rsph_read_neighbours", "rsph_set_kernel_timing", "rsph_set_launch_mode",
     "rsph_read_kernel_timing", "rsph_destroy_system", "rsph_status_string", "rsph_last_error",
     "rsph_pool_create", "rsph_pool_admit", "rsph_pool_step", "rsph_pool_bytes",
     "rsph_pool_release", "rsph_pool_destroy",
@@ -123,6 +123,7 @@ def lib():
     L.rsph_read_binning.argtypes = [vp, i64, vp, vp]
     L.rsph_read_neighbours.argtypes = [vp, i64, i64, vp, vp]
     L.rsph_set_kernel_timing.argtypes = [vp, i32]
+    L.rsph_set_launch_mode.argtypes = [vp, i32]
     L.rsph_read_kernel_timing.argtypes = [vp, vp, vp]
     L.rsph_destroy_system.argtypes = [vp]
     L.rsph_destroy_system.restype = None
@@ -252,6 +253,12 @@ class System:
         idx = np.zeros(self.n * cap_per, np.int64)
         _check(lib().rsph_read_neighbours(self.h, self.n, idx.shape[0], _p(start), _p(idx)), self.h)
         return start, idx[: start[-1]].copy()
+
+    def set_launch_mode(self, mode):
+        """'graph' (captured launch cycles, the default) or 'eager'; applies to
+        the whole pool that holds this system."""
+        code = {"graph": 0, "eager": 1}[mode]
+        _check(lib().rsph_set_launch_mode(self.h, code), self.h)
 
     def set_timing(self, kernels=None):
         """kernels: iterable of names from KERNELS (None = all, [] = off)."""
