@@ -86,16 +86,21 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(w, precision, steps, warmup, timed_kernels):
+def run_gpu(w, precision, steps, warmup, timed_kernels, launch="graph"):
+    """Warmup, then `steps` advection steps timed on the host clock (the
+    step call returns after the stream is synchronised).  With timed_kernels,
+    every launch of those kernels is bracketed by HIP events, which runs the
+    cycles eagerly."""
     p = w["params"]
     s = rsph.System(p, precision=precision)
+    s.set_launch_mode(launch)
     s.set_particles(w["pos"], w["vel"], w["phase"])
     if warmup:
         s.step(warmup)
     o0 = s.observables()
     s.set_timing(timed_kernels)
     t0 = time.perf_counter()
-    s.step(steps)  # returns after the stream is synchronised
+    s.step(steps)
     t1 = time.perf_counter()
     timing = s.timing()
     o1 = s.observables()
@@ -157,13 +162,58 @@ def cpu_baseline(w, outer_steps):
     }
 
 
+def served(args):
+    """Served form on the mixed droplet stream: the saturated job rate is taken
+    from a probe batch that arrives all at once; the full stream then arrives
+    as a Poisson process at 0.8 of that rate into a pool with a fixed HBM
+    budget.  Prints one JSON line."""
+    from paper_2503_16082_amd import serve
+    prec = rsph.MIXED if args.precision == "mixed" else rsph.FP64
+    descs = WL.served_mix(n_jobs=args.jobs, seed=0)
+    budget = int(args.budget_gb * (1 << 30))
+    probe = descs[:args.probe_jobs]
+    ps = serve.serve(probe, steps_per_job=args.probe_steps, rate_hz=None, budget_bytes=budget, precision=prec)
+    rate_sat = ps["jobs"] / ps["wall_s"] * args.probe_steps / args.steps_per_job
+    log(f"probe: {ps['jobs']} jobs x {args.probe_steps} steps in {ps['wall_s']:.2f}s -> saturated "
+        f"{rate_sat:.3f} jobs/s at {args.steps_per_job} steps per job")
+    rate = 0.8 * rate_sat
+    out = serve.serve(descs, steps_per_job=args.steps_per_job, rate_hz=rate, budget_bytes=budget,
+                      precision=prec, log=log)
+    line = {
+        "metric": "served particle-steps/s with p50/p99 per-step latency",
+        "value": out["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32" if prec == rsph.MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": "served_mix", "jobs": args.jobs, "steps_per_job": args.steps_per_job,
+                   "particles_per_job": "log-uniform 2,000-200,000", "arrival_rate_hz": rate,
+                   "hbm_budget_bytes": budget, "form": args.precision},
+        "step_latency_p50_ms": out["step_latency_p50_ms"],
+        "step_latency_p99_ms": out["step_latency_p99_ms"],
+        "turnaround_p50_s": out["turnaround_p50_s"],
+        "max_queue_depth": out["max_queue_depth"],
+        "jobs_done": out["jobs"],
+        "wall_s": out["wall_s"],
+        "saturated_job_rate_hz": rate_sat,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="square2d",
-                    choices=["square2d", "droplet2d", "droplet3d", "impact3d"])
+                    choices=["square2d", "droplet2d", "droplet3d", "impact3d", "served"])
+    ap.add_argument("--jobs", type=int, default=256, help="served: jobs in the stream")
+    ap.add_argument("--steps-per-job", type=int, default=200, help="served: advection steps per job")
+    ap.add_argument("--budget-gb", type=float, default=0.5, help="served: pool HBM budget")
+    ap.add_argument("--probe-jobs", type=int, default=24, help="served: jobs of the saturation probe")
+    ap.add_argument("--probe-steps", type=int, default=20, help="served: steps per probe job")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -175,38 +225,49 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "served":
+        served(args)
+        return
     w = workload(args.workload)
     n = w["pos"].shape[0]
     dim = w["params"]["dim"]
     prec = rsph.MIXED if args.precision == "mixed" else rsph.FP64
     log(f"workload {w['name']} n={n} precision={args.precision} steps={args.steps} warmup={args.warmup}")
 
-    s, r = run_gpu(w, prec, args.steps, args.warmup, ["force"])
+    # the timed region: graph replays, no per-launch events
+    s, r = run_gpu(w, prec, args.steps, args.warmup, [])
     s.close()
     secs = r["seconds"]
     value = n * args.steps / secs
-    f_launch, f_ms = r["timing"]["force"]
-    e_launch, e_ms = r["timing"]["event_floor"]
+    # the force-pass duration: the same steps again, every force launch
+    # bracketed by HIP events on the system's stream (the events lengthen the
+    # step, so they stay out of the timed region)
+    s, rt = run_gpu(w, prec, args.steps, args.warmup, ["force"])
+    s.close()
+    f_launch, f_ms = rt["timing"]["force"]
+    e_launch, e_ms = rt["timing"]["event_floor"]
     floor_ms = e_ms / max(e_launch, 1)
     # launches in which the system was inside an advection step, each bracketed
     # by HIP events recorded by its own dispatch
     f_avg_ms = f_ms / max(f_launch, 1)
     bulk_ops, surf_ops = FORCE_OPS[dim]
-    ops = r["pairs"] * bulk_ops + r["near_pairs"] * surf_ops
+    ops = rt["pairs"] * bulk_ops + rt["near_pairs"] * surf_ops
     tflops = ops / (f_avg_ms * 1e-3) / 1e12
     peak_tf = PEAK_TFLOPS["f32" if prec == rsph.MIXED else "f64"]
     per_p, per_pair, per_near = FORCE_BYTES[(dim, args.precision)]
-    algo_bytes = n * per_p + r["pairs"] * per_pair + r["near"] * per_near
+    algo_bytes = n * per_p + rt["pairs"] * per_pair + rt["near"] * per_near
     gbs = algo_bytes / (f_avg_ms * 1e-3) / 1e9
     log(f"gpu {secs:.3f}s substeps={r['substeps']} force launches={f_launch} avg={f_avg_ms * 1e3:.1f}us "
         f"bytes/launch={algo_bytes:.3e} -> {gbs:.1f} GB/s; ops/launch={ops:.3e} -> {tflops:.2f} TFLOP/s")
 
     extra = {}
     if prec == rsph.MIXED and not args.no_fp64_compare:
-        s64, r64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, ["force"])
+        s64, r64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, [])
         s64.close()
         v64 = n * args.steps / r64["seconds"]
-        l64, m64 = r64["timing"]["force"]
+        s64, rt64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, ["force"])
+        s64.close()
+        l64, m64 = rt64["timing"]["force"]
         extra["fp64_gpu_value"] = v64
         extra["mixed_over_fp64"] = value / v64
         extra["fp64_force_avg_us"] = m64 / max(l64, 1) * 1e3
