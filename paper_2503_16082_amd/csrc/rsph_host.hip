@@ -339,6 +339,8 @@ void alloc_arrays(rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
 {
     Alloc M{P};
     plan_arrays(M, P->dim, P->precision, P->A, P->d_mask, P->d_targets, P->work_dev, Pc, Cc, Sc);
+    // binning expects zero cell counts (each scan clears the counts it reads)
+    launch_fill_i32(launch_of(P), P->A.cell_cnt, Cc, 0);
     P->P_cap = Pc;
     P->C_cap = Cc;
     P->S_cap = Sc;
@@ -613,7 +615,6 @@ void launch_cycle_eager(rsph_pool* P, int64_t m)
     const int64_t g0 = P->next_group++;
     launch_cycle_begin(L, A, g0);
     rebuild(P, 0, g0);
-    launch_dt_advection(L, A);
     {
         TimeScope t(P, RSPH_KERNEL_ADVECTION, g0);
         launch_advection(L, A, t.ev);
@@ -681,18 +682,22 @@ void launch_cycle(rsph_pool* P, int64_t m)
 }
 
 // Advances every system of the pool to its device-side target.  Returns the
-// OR of the health bits.
+// OR of the health bits.  Cycles are launched in batches with one stream
+// synchronisation after each: the substeps launched per cycle follow the most
+// substeps any system needed in one advection step during the last batch (a
+// step that needs more simply continues in the next cycle).
 uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
 {
-    std::vector<SysDyn> d0 = read_dyn(P);
     int64_t cycles = std::max<int64_t>(outer_hint, 1);
+    int64_t batch = 4;
     for (;;) {
-        for (int64_t c = 0; c < cycles; ++c) launch_cycle(P, P->m_pred);
+        const int64_t c = std::min(cycles, batch);
+        for (int64_t k = 0; k < c; ++k) launch_cycle(P, P->m_pred);
         std::vector<SysDyn> d = read_dyn(P);
         uint32_t health = 0;
         int64_t remaining = 0;
         bool pending = false;
-        double sub_per_outer = 0.0;
+        int64_t m_seen = 0;
         for (size_t s = 0; s < d.size(); ++s) {
             health |= d[s].health;
             const long long left = d[s].target - d[s].n_outer;
@@ -700,15 +705,17 @@ uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
             if (d[s].health & kFaultBits) continue;
             if (left > 0 || inside) pending = true;
             remaining = std::max<int64_t>(remaining, left);
-            const long long dn = d[s].n_outer - d0[s].n_outer;
-            if (dn > 0) sub_per_outer = std::max(sub_per_outer, (double)(d[s].n_sub - d0[s].n_sub) / dn);
+            m_seen = std::max<int64_t>(m_seen, d[s].ksub_max);
             if (d[s].ksub > kMaxSubsteps) fail(RSPH_ENUMERIC, "more than 1e6 acoustic substeps in one advection step");
         }
-        if (sub_per_outer > 0) P->m_pred = std::min<int64_t>(4096, (int64_t)std::ceil(sub_per_outer));
+        if (m_seen > 0) {
+            P->m_pred = std::min<int64_t>(4096, m_seen);
+            launch_reset_ksub_max(launch_of(P), P->A);
+        }
         // faulted systems stay idle on the device; the others run to their targets
         if (!pending) return health;
         cycles = std::max<int64_t>(remaining, 1);
-        d0 = d;
+        batch = std::min<int64_t>(batch * 2, 64);
     }
 }
 
@@ -810,6 +817,7 @@ void reset_dyn(rsph_system* s, bool keep_clock)
     if (keep_clock) HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
     d.health = 0;
     d.stepping = 0;
+    d.ksub_max = 0;
     d.state = kBoundary;
     d.ksub = 0;
     if (!keep_clock) {

@@ -107,7 +107,7 @@ struct SysDyn {
     int32_t state;                   // kIdle ... kEnded
     int32_t stepping;                // 1 while the advection-step prologue runs for this system
     uint32_t health;
-    int32_t pad;
+    int32_t ksub_max;                // most substeps in one advection step since the host last looked
     long long ksub;                  // substeps started in the current advection step
     long long n_sub;
     long long n_outer;
@@ -198,9 +198,9 @@ void launch_empty(const Launch& L, Ev ev);
 void launch_cycle_begin(const Launch& L, const DevArrays& A, int64_t group);
 void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask);
 void launch_set_targets(const Launch& L, const DevArrays& A, const long long* targets);
+void launch_reset_ksub_max(const Launch& L, const DevArrays& A);
 void launch_bin(const Launch& L, const DevArrays& A);
 void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev);
-void launch_dt_advection(const Launch& L, const DevArrays& A);
 int lanes_per_particle(int dim);
 void launch_advection(const Launch& L, const DevArrays& A, Ev ev);
 void launch_shift(const Launch& L, const DevArrays& A, Ev ev);

@@ -444,8 +444,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(int32_t* part, int64_t
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t* in, int64_t n,
-                                                       const int32_t* part, int32_t* out)
+// the final phase also clears the counts for the next histogram
+__global__ __launch_bounds__(kBlock) void k_scan_final(int32_t* in, int64_t n, const int32_t* part,
+                                                       int32_t* out)
 {
     __shared__ int lds[4];
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -454,6 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t* in, int64_
     for (int k = 0; k < kScanItems; ++k) {
         int64_t idx = base + k;
         v[k] = idx < n ? in[idx] : 0;
+        if (idx < n) in[idx] = 0;
         s += v[k];
     }
     int total;
@@ -464,6 +466,39 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t* in, int64_
         ex += v[k];
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = ex;
+}
+
+// exclusive scan of at most kScanSmall counts by one block, which clears them
+constexpr int kScanSmallThreads = 1024;
+constexpr int kScanSmall = kScanSmallThreads * kScanItems;
+__global__ __launch_bounds__(kScanSmallThreads) void k_scan_small(int32_t* in, int64_t n, int32_t* out)
+{
+    __shared__ int lds[kScanSmallThreads / kWave];
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k;
+        v[k] = idx < n ? in[idx] : 0;
+        if (idx < n) in[idx] = 0;
+        s += v[k];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wv] = x;
+    __syncthreads();
+    int ex = x - s;
+    for (int k = 0; k < wv; ++k) ex += lds[k];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k;
+        if (idx < n) out[idx] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == kScanSmallThreads - 1) out[n] = ex;
 }
 
 // scatter in arrival order (the cell-relative rank of the histogram atomics)
@@ -965,6 +1000,8 @@ __global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
 // (Eq. 15), near-interface flag
 // ---------------------------------------------------------------------------
 
+__device__ void begin_advection_step(const DevArrays& A, const SysConst& S, SysDyn& D);
+
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
 {
@@ -972,8 +1009,13 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     int g;
     Slot c = slot_of_group<G>(A, g);
     if (c.s < 0) return;
-    if (!A.sd[c.s].stepping) return;  // wave-uniform
+    SysDyn& Dy = A.sd[c.s];
+    if (!Dy.stepping) return;  // block-uniform
     const SysConst& S = A.sc[c.s];
+    // the system's first block also sets the advection step (Eqs. 16, 18) from
+    // the per-wave |v| maxima of the gather; no pass of this kernel reads the
+    // fields it writes
+    if (A.mode == 0 && logical_block() * (kBlock / G) == S.p_off) begin_advection_step(A, S, Dy);
     const int64_t i = c.i;
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[1];
@@ -1238,12 +1280,11 @@ __device__ __forceinline__ void reduce_vmax(const DevArrays& A, const SysConst& 
     vmax[1] = __longlong_as_double((long long)m1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_dt_advection(DevArrays A)
+// start of an advection step: per-fluid max |v| over the system, the advection
+// step (Eqs. 16, 18) and the first acoustic step (Eqs. 17, 18); called by every
+// thread of one block of the system
+__device__ void begin_advection_step(const DevArrays& A, const SysConst& S, SysDyn& D)
 {
-    const int s = blockIdx.x;
-    SysDyn& D = A.sd[s];
-    const SysConst& S = A.sc[s];
-    if (!D.stepping) return;  // block-uniform
     double vmax[2];
     reduce_vmax(A, S, kWave, vmax);
     if (threadIdx.x != 0) return;
@@ -1305,6 +1346,13 @@ __global__ __launch_bounds__(kBlock) void k_dt_substep(DevArrays A, int64_t grou
         D.state = kEnding;
         D.n_outer += 1;
     }
+    if (D.state == kEnding && k + 1 > D.ksub_max) D.ksub_max = (int32_t)(k + 1);
+}
+
+__global__ void k_reset_ksub_max(DevArrays A)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < A.nsys) A.sd[s].ksub_max = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1820,6 +1868,11 @@ void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mas
     hipLaunchKernelGGL(k_set_stepping, sys_grid(A.nsys), dim3(64), 0, L.stream, A, mask);
 }
 
+void launch_reset_ksub_max(const Launch& L, const DevArrays& A)
+{
+    hipLaunchKernelGGL(k_reset_ksub_max, sys_grid(A.nsys), dim3(64), 0, L.stream, A);
+}
+
 void launch_set_targets(const Launch& L, const DevArrays& A, const long long* targets)
 {
     hipLaunchKernelGGL(k_set_targets, sys_grid(A.nsys), dim3(64), 0, L.stream, A, targets);
@@ -1827,18 +1880,24 @@ void launch_set_targets(const Launch& L, const DevArrays& A, const long long* ta
 
 void launch_bin(const Launch& L, const DevArrays& A)
 {
+    // the cell counts are zero on entry: cleared when the arrays are
+    // allocated and by every scan that consumes them
     const int64_t ncells = A.C;
-    launch_fill_i32(L, A.cell_cnt, ncells, 0);
     if (L.dim == 2)
         hipLaunchKernelGGL(k_key<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     else
         hipLaunchKernelGGL(k_key<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    const int64_t ntiles = (ncells + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
-                       ncells, A.scan_part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, L.stream, A.scan_part, ntiles);
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
-                       ncells, A.scan_part, A.cell_start);
+    if (ncells <= kScanSmall) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanSmallThreads), 0, L.stream, A.cell_cnt, ncells,
+                           A.cell_start);
+    } else {
+        const int64_t ntiles = (ncells + kScanTile - 1) / kScanTile;
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
+                           ncells, A.scan_part);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, L.stream, A.scan_part, ntiles);
+        hipLaunchKernelGGL(k_scan_final, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
+                           ncells, A.scan_part, A.cell_start);
+    }
     hipLaunchKernelGGL(k_scatter, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     hipLaunchKernelGGL(k_rank, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     if (L.dim == 2) {
@@ -1875,11 +1934,6 @@ void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev)
 }
 
 int lanes_per_particle(int dim) { return dim == 2 ? G2 : G3; }
-
-void launch_dt_advection(const Launch& L, const DevArrays& A)
-{
-    hipLaunchKernelGGL(k_dt_advection, dim3((unsigned)A.nsys), dim3(kBlock), 0, L.stream, A);
-}
 
 void launch_advection(const Launch& L, const DevArrays& A, Ev ev)
 {
