@@ -132,13 +132,15 @@ struct Geo;
 
 template <>
 struct Geo<double> {
-    __device__ static Q4<double> make(const double* x, int ph, const SysConst& S, const int* c)
+    // w = phase + 2 * (particle has a neighbour of the other fluid)
+    __device__ static Q4<double> make(const double* x, int ph, bool iface, const SysConst& S, const int* c)
     {
         (void)S;
         (void)c;
-        return Q4<double>{x[0], x[1], x[2], (double)ph};
+        return Q4<double>{x[0], x[1], x[2], (double)(ph + (iface ? 2 : 0))};
     }
-    __device__ static int phase(const Q4<double>& g) { return (int)g.w; }
+    __device__ static int phase(const Q4<double>& g) { return (int)g.w & 1; }
+    __device__ static bool interface(const Q4<double>& g) { return ((int)g.w >> 1) != 0; }
     template <int D>
     __device__ static void rij(const Q4<double>& gi, const Q4<double>& gj, const SysConst& S,
                                const double* cellr, double* r)
@@ -165,15 +167,18 @@ struct Geo<double> {
 
 template <>
 struct Geo<float> {
-    __device__ static Q4<float> make(const double* x, int ph, const SysConst& S, const int* c)
+    // tag: cell x, y, z in 10 bits each, bit 30 = particle has a neighbour of
+    // the other fluid, bit 31 = phase
+    __device__ static Q4<float> make(const double* x, int ph, bool iface, const SysConst& S, const int* c)
     {
         float o[3];
         for (int a = 0; a < 3; ++a) o[a] = (float)(x[a] - (double)c[a] * S.cell[a]);
         uint32_t tag = (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20) |
-                       ((uint32_t)ph << 31);
+                       ((uint32_t)(iface ? 1 : 0) << 30) | ((uint32_t)ph << 31);
         return Q4<float>{o[0], o[1], o[2], __uint_as_float(tag)};
     }
     __device__ static int phase(const Q4<float>& g) { return (int)(__float_as_uint(g.w) >> 31); }
+    __device__ static bool interface(const Q4<float>& g) { return ((__float_as_uint(g.w) >> 30) & 1u) != 0; }
     template <int D>
     __device__ static void rij(const Q4<float>& gi, const Q4<float>& gj, const SysConst& S,
                                const float* cellr, float* r)
@@ -930,7 +935,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     A.flags[i] = cross ? kFlagInterface : 0;
     Q4<R>* vb = (Q4<R>*)A.vbuf[0];
     vb[i] = Q4<R>{(R)A.vel[0][i], (R)A.vel[1][i], D == 3 ? (R)A.vel[2][i] : (R)0, (R)0};
-    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, S, ci);
+    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
     ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
     if (A.mode == 1)
         for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
@@ -993,6 +998,9 @@ __global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
     const double V = A.mass[i] / rho;
     const double p = S.c0sq * (rho - S.rho0[ph]);
     ((Q4<R>*)A.th[1])[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
+    // the volume also rides in the spare component of the velocity record read
+    // by the advection pass
+    reinterpret_cast<R*>((Q4<R>*)A.vbuf[0] + i)[3] = (R)V;
 }
 
 // ---------------------------------------------------------------------------
@@ -1036,16 +1044,16 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
     for_neighbours<G, 2>(
-        A, i, g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vb[j]}}; },
-        [&](uint32_t j, const Recs<R, 3>& rj) {
+        A, i, g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
+        [&](uint32_t j, const Recs<R, 2>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
             Geo<R>::template rij<D>(gi, gj, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
-            const R Vj = rj.q[1].y;
-            const Q4<R> vj = rj.q[2];
+            const Q4<R> vj = rj.q[1];
+            const R Vj = vj.w;  // volume, stored beside the velocity
             const R eta_j = Geo<R>::phase(gj) == phi ? eta_i : eta_o;
             const R es = eta_i + eta_j;
             const R eta_bar = es > R(0) ? R(2) * eta_i * eta_j / es : R(0);
@@ -1062,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
                 M[4] += gg * r[1] * r[2];
                 M[5] += gg * r[2] * r[2];
             }
-            near |= A.flags[j] & kFlagInterface;
+            near |= Geo<R>::interface(gj);
         });
     for (int a = 0; a < D; ++a) av[a] = group_sum<G>(av[a]);
     M[0] = group_sum<G>(M[0]);
@@ -1114,8 +1122,11 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             B[1] = B[2] = B[4] = R(0);
         }
     }
-    ((Q4<R>*)A.bm[0])[i] = Q4<R>{B[0], B[1], B[2], B[3]};
-    ((Q4<R>*)A.bm[1])[i] = Q4<R>{B[4], B[5], (R)0, (R)0};
+    // the volume rides in a spare component of the B records read by the shift
+    // pass (B02 = 0 in 2D)
+    const R Vi = th[i].y;
+    ((Q4<R>*)A.bm[0])[i] = Q4<R>{B[0], B[1], D == 2 ? Vi : B[2], B[3]};
+    ((Q4<R>*)A.bm[1])[i] = Q4<R>{B[4], B[5], D == 3 ? Vi : (R)0, (R)0};
     A.flags[i] = (A.flags[i] & kFlagInterface) | (near ? kFlagNearInterface : 0);
     if (A.mode == 1) {
         for (int a = 0; a < 3; ++a) A.r_accv[3 * i + a] = a < D ? (double)(&a4.x)[a] : 0.0;
@@ -1158,15 +1169,21 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
     }
     R s[3] = {0, 0, 0};
     for_neighbours<G, Chunk<R, D>::N>(
-        A, i, g, cnt, [&](uint32_t j) { return Recs<R, 4>{{geo[j], th[j], b0[j], b1[j]}}; },
-        [&](uint32_t j, const Recs<R, 4>& rj) {
+        A, i, g, cnt,
+        [&](uint32_t j) {
+            if constexpr (D == 3) return Recs<R, 3>{{geo[j], b0[j], b1[j]}};
+            else return Recs<R, 2>{{geo[j], b0[j]}};
+        },
+        [&](uint32_t j, const Recs<R, D>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
             Geo<R>::template rij<D>(gi, gj, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
-            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * rj.q[1].y * inv_r;  // dW V_j / r
-            const Q4<R> Bj0 = rj.q[2], Bj1 = rj.q[3];
+            const Q4<R> Bj0 = rj.q[1];
+            const Q4<R> Bj1 = D == 3 ? rj.q[D - 1] : Q4<R>{0, 0, 0, 0};
+            const R Vj = D == 2 ? Bj0.z : Bj1.z;  // volume, stored beside B
+            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * Vj * inv_r;  // dW V_j / r
             // (B_i + B_j) r_ij, symmetric storage 00 01 02 11 12 22
             const R m00 = Bi0.x + Bj0.x, m01 = Bi0.y + Bj0.y, m11 = Bi0.w + Bj0.w;
             if (D == 2) {
