@@ -849,6 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
             if (a < D) oi[a] = (float)(xi[a] - (double)ci[a] * S.cell[a]);
         }
         const float cut_hi = (float)(S.cut2 * (1.0 + 1e-5)), cut_lo = (float)(S.cut2 * (1.0 - 1e-5));
+        const int i32 = (int)i;
         // the particle's union-local cell
         const int lx = ci[0] - L.lo[0] + 1, ly = ci[1] - L.lo[1] + 1, lz = D == 3 ? ci[2] - L.lo[2] + 1 : 0;
         const int zr = D == 3 ? 1 : 0;
@@ -871,22 +872,23 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                 for (int sgm = 0; sgm < nseg; ++sgm) {
                     const int kb = contiguous ? rb : L.off[u0 + sgm];
                     const int ke = contiguous ? re : L.off[u0 + sgm + 1];
-                    const int64_t jofs = (int64_t)L.gs[contiguous ? u0 : u0 + sgm] - kb;
+                    // slots fit in 32 bits (the slot capacity is checked on the host)
+                    const int jofs = L.gs[contiguous ? u0 : u0 + sgm] - kb;
+#pragma unroll 2
                     for (int k0 = kb; k0 < ke; k0 += G) {
+                        // lanes past the range read the range's first entry and discard it
                         const int k = k0 + g;
-                        bool hit = false, band = false;
-                        const int64_t j = jofs + k;
-                        if (k < ke && j != i) {
-                            const float4 q = L.q[k];
-                            const int w = __float_as_int(q.w);
-                            const float ax = (oi[0] - q.x) - (float)((w >> 1) - lx) * cellf[0];
-                            const float ay = ry0 - q.y;
-                            const float az = D == 3 ? rz0 - q.z : 0.f;
-                            const float r2f = ax * ax + ay * ay + az * az;
-                            hit = r2f < cut_hi;
-                            band = r2f >= cut_lo;
-                            if (hit) cross |= (w & 1) != ph;
-                        }
+                        const bool valid = k < ke;
+                        const float4 q = L.q[valid ? k : kb];
+                        const int w = __float_as_int(q.w);
+                        const float ax = (oi[0] - q.x) - (float)((w >> 1) - lx) * cellf[0];
+                        const float ay = ry0 - q.y;
+                        const float az = D == 3 ? rz0 - q.z : 0.f;
+                        const float r2f = ax * ax + ay * ay + az * az;
+                        const int j = jofs + k;
+                        const bool hit = valid && j != i32 && r2f < cut_hi;
+                        const bool band = r2f >= cut_lo;
+                        cross |= hit && (w & 1) != ph;
                         marked |= hit && band;
                         append_hits<G>(hit, (uint32_t)j | (band ? kBandMark : 0u), gshift, below, out, A.kmax,
                                        cnt);
