@@ -135,6 +135,33 @@ def oscillating_ellipse_2d(n_particles, aspect, ratio, gamma, seed, R=0.2, rho_k
             "phase": phase, "R": R}
 
 
+def oscillating_drop_2d(n_side=60, ratio=1000.0, V0=1.0, gamma=1.0, seed=0, R=0.2, r0=0.05, rho_k=1.0,
+                        eta_k=0.05, amp=0.05):
+    """Oscillating drop of section 5.1: a disc of radius R centred in the
+    periodic unit square, started with the divergence-free velocity field of
+    Eq. 34 (centred on the drop, scale r0) on every particle.  Phase k has
+    rho_k, eta_k; phase l has rho_k / ratio and eta_k / min(ratio, 100)
+    (ratio 1000: rho 1e-3, eta 5e-4).  n_side = 60 gives R / dp = 12."""
+    dp = 1.0 / n_side
+    pts0 = lattice(2, (n_side, n_side), dp)
+    d0 = pts0 - 0.5
+    phase = np.where((d0 * d0).sum(axis=1) < R * R, 0, 1).astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    x = pos[:, 0] - 0.5
+    y = pos[:, 1] - 0.5
+    r = np.sqrt(x * x + y * y)
+    decay = np.exp(-r / r0)
+    rs = np.maximum(r, 1e-300)
+    vel = np.stack([V0 * (x / r0) * (1.0 - y * y / (r0 * rs)) * decay,
+                    -V0 * (y / r0) * (1.0 - x * x / (r0 * rs)) * decay], axis=1)
+    umax = float(np.sqrt((vel * vel).sum(axis=1)).max())
+    rho = (rho_k, rho_k / ratio)
+    eta = (eta_k, eta_k / min(ratio, 100.0))
+    p = base_params(2, (1.0, 1.0), dp, rho, eta, gamma, capillary_c0(2, gamma, rho_k, R, umax))
+    return {"name": "oscillating_drop_2d", "params": p, "pos": pos, "vel": vel, "phase": phase, "R": R}
+
+
 def served_mix(n_jobs=256, seed=0, n_min=2000, n_max=200000):
     """Job descriptions of the served mix: log-uniform particle counts,
     aspect ratio U(1.1, 1.5), density ratio from {10, 100, 1000}, gamma U(0.5, 2)."""
