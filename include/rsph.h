@@ -62,7 +62,9 @@ enum {
 #define RSPH_NO_PENALTY 1u             /* Eq. 26 instead of Eq. 33 */
 #define RSPH_NO_SHIFT 2u               /* no transport-velocity position correction (Eq. 14) */
 #define RSPH_NO_DENSITY_SUMMATION 4u   /* density by the continuity equation only */
-#define RSPH_GBAR_SINGLE_FIELD 8u      /* cross-phase mean colour gradient (grad C_i - grad C_j)/2 */
+#define RSPH_GBAR_OWN_PHASE_AVERAGE 8u /* mean colour gradient of a cross-phase pair as printed in Eq. 27,
+                                          (grad C_i + grad C_j)/2 of the two own-phase fields, instead of the
+                                          default one-field mean (grad C_i - grad C_j)/2 */
 #define RSPH_PENALTY_R3 16u            /* alternative reading of the penalty tensor (Eq. 30) */
 #define RSPH_NO_SURFACE 32u            /* no surface stress and no penalty */
 

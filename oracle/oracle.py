@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 NO_PENALTY = 1
 NO_SHIFT = 2
 NO_DENSITY_SUMMATION = 4
-GBAR_SINGLE_FIELD = 8
+GBAR_OWN_PHASE_AVERAGE = 8
 PENALTY_R3 = 16
 NO_SURFACE = 32
 

@@ -45,7 +45,7 @@
 #define ORC_NO_PENALTY 1u
 #define ORC_NO_SHIFT 2u
 #define ORC_NO_DENSITY_SUMMATION 4u
-#define ORC_GBAR_SINGLE_FIELD 8u
+#define ORC_GBAR_OWN_PHASE_AVERAGE 8u
 #define ORC_PENALTY_R3 16u
 #define ORC_NO_SURFACE 32u
 
@@ -638,9 +638,14 @@ static void momentum_rates(const orc_params* P, const nb_t* nb, int64_t i, const
         /* Eq. 27 and Eq. 30 (reading R1): Chat_ij grad W = dW [C_ij e - (gbar . r_ij) gbar/|gbar|] */
         double Cij = same ? 0.0 : 1.0;
         double gbar[3] = {0, 0, 0};
+        /* Eq. 25 predicts C_ij from one colour field, the one that is 1 in i's
+         * fluid: a neighbour of the other fluid computed its gradient (Eq. 22)
+         * for the field that is 1 in its own fluid, so it enters negated.  The
+         * flag GBAR_OWN_PHASE_AVERAGE averages the two own-phase gradients as
+         * printed. */
         for (int a = 0; a < d; ++a) {
             double gj = gradC[3 * j + a];
-            if ((P->flags & ORC_GBAR_SINGLE_FIELD) && !same) gj = -gj;
+            if (!(P->flags & ORC_GBAR_OWN_PHASE_AVERAGE) && !same) gj = -gj;
             gbar[a] = 0.5 * (gradC[3 * i + a] + gj);
         }
         double gnorm = 0.0, gdotr = 0.0;

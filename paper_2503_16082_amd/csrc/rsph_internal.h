@@ -31,7 +31,7 @@ constexpr int kMaxLanes = 16;  // lanes per particle slot in the pair passes (at
 constexpr uint32_t kNoPenalty = 1u;
 constexpr uint32_t kNoShift = 2u;
 constexpr uint32_t kNoDensitySummation = 4u;
-constexpr uint32_t kGbarSingleField = 8u;
+constexpr uint32_t kGbarOwnPhaseAverage = 8u;
 constexpr uint32_t kPenaltyR3 = 16u;
 constexpr uint32_t kNoSurface = 32u;
 

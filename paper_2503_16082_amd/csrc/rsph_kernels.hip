@@ -1481,7 +1481,9 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     const bool surface = c.lane && (fl & kFlagNearInterface) && !(S.flags & kNoSurface);
     const Q4<R> ci = surface ? ci_i : Q4<R>{0, 0, 0, 0};
     const bool penalty = !(S.flags & kNoPenalty);
-    const bool single = (S.flags & kGbarSingleField) != 0;
+    // cross pairs: the neighbour's gradient enters negated (one colour field,
+    // Eq. 25) unless the printed own-phase average is asked for
+    const bool single = (S.flags & kGbarOwnPhaseAverage) == 0;
     const bool r3 = (S.flags & kPenaltyR3) != 0;
     const R gamma = (R)S.gamma;
     const R xg = (R)(S.xi * S.gamma);

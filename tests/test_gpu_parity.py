@@ -149,7 +149,7 @@ def test_eval_rates_parity(case, precision):
     compare_rates(g, ref, precision, f"{case}/p{precision}")
 
 
-@pytest.mark.parametrize("flags", [rsph.NO_PENALTY, rsph.GBAR_SINGLE_FIELD, rsph.PENALTY_R3,
+@pytest.mark.parametrize("flags", [rsph.NO_PENALTY, rsph.GBAR_OWN_PHASE_AVERAGE, rsph.PENALTY_R3,
                                    rsph.NO_SURFACE])
 def test_eval_rates_parity_method_switches(flags):
     w = WL.static_droplet_2d(n_side=40, R=0.2, seed=1)

@@ -483,7 +483,7 @@ def test_xi_rule():
 # momentum conservation (the pair forces are antisymmetric)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("flags", [0, "single", "r3"])
+@pytest.mark.parametrize("flags", [0, "average", "r3"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_momentum_conservation_per_evaluation(dim, flags):
     """sum_i m_i a_i = 0 for the pressure, surface (with penalty) and viscous
@@ -493,7 +493,7 @@ def test_momentum_conservation_per_evaluation(dim, flags):
     else:
         w = WL.static_droplet_3d(n_side=14, R=0.3, seed=3)
     p = w["params"]
-    p["oracle_flags"] = {0: 0, "single": O.GBAR_SINGLE_FIELD, "r3": O.PENALTY_R3}[flags]
+    p["oracle_flags"] = {0: 0, "average": O.GBAR_OWN_PHASE_AVERAGE, "r3": O.PENALTY_R3}[flags]
     n = w["pos"].shape[0]
     rng = np.random.default_rng(11)
     pos = O.wrap(p, w["pos"])
