@@ -74,6 +74,99 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------------------
+# profiling utilities: the copy reference of the byte counters, the traffic
+# line of the force pass, and the kernel-trace summary tables of profiles/
+# ---------------------------------------------------------------------------
+
+COPY_BYTES = 1 << 30
+
+
+def copy_probe():
+    """One 1 GiB device-to-device copy: the reference by which FETCH_SIZE and
+    WRITE_SIZE are scaled (run under rocprofv3 --pmc)."""
+    import torch
+    x = torch.ones(COPY_BYTES // 4, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES}), flush=True)
+
+
+def pmc_per_dispatch(csv_path, name_part, counter):
+    """Counter value of every dispatch of the kernels whose name contains
+    name_part (summed over the rows rocprofv3 writes for one dispatch)."""
+    import csv
+    import collections
+    vals = collections.defaultdict(float)
+    for row in csv.DictReader(open(csv_path)):
+        if name_part in row["Kernel_Name"] and row["Counter_Name"] == counter:
+            vals[int(row["Dispatch_Id"])] += float(row["Counter_Value"])
+    return [vals[k] for k in sorted(vals)]
+
+
+def active_mean(v):
+    """Mean over the dispatches that did work (above a quarter of the largest:
+    a launch cycle also issues substep launches that exit at once)."""
+    top = max(v)
+    act = [x for x in v if x > 0.25 * top]
+    return sum(act) / len(act), len(act)
+
+
+def pmc_traffic(args):
+    import hashlib
+    f_csv, w_csv, cf_csv, cw_csv = args.pmc_traffic
+    dim = 2 if args.workload in ("square2d", "droplet2d") else 3
+    kname = f"k_force<{'float' if args.precision == 'mixed' else 'double'}, {dim}>"
+    fetch, nf = active_mean(pmc_per_dispatch(f_csv, kname, "FETCH_SIZE"))
+    write, nw = active_mean(pmc_per_dispatch(w_csv, kname, "WRITE_SIZE"))
+    cf = max(pmc_per_dispatch(cf_csv, "copyBuffer", "FETCH_SIZE"))
+    cw = max(pmc_per_dispatch(cw_csv, "copyBuffer", "WRITE_SIZE"))
+    f_scale = COPY_BYTES / (cf * 1024.0)
+    w_scale = COPY_BYTES / (cw * 1024.0)
+    fetch_b = fetch * 1024.0 * f_scale
+    write_b = write * 1024.0 * w_scale
+    name = workload(args.workload)["name"]
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    lines = []
+    if os.path.exists(TRAFFIC_FILE):
+        lines = [l for l in open(TRAFFIC_FILE).read().splitlines()
+                 if not (len(l.split()) == 5 and l.split()[0] == name and l.split()[1] == args.precision)]
+    lines.append(f"{name} {args.precision} {sha} {fetch_b:.0f} {write_b:.0f}")
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"workload": name, "form": args.precision, "kernel": kname, "dispatches": [nf, nw],
+                      "fetch_kib": fetch, "write_kib": write, "copy_fetch_kib": cf, "copy_write_kib": cw,
+                      "fetch_scale": f_scale, "write_scale": w_scale, "fetch_bytes": fetch_b,
+                      "write_bytes": write_b}), flush=True)
+
+
+def trace_summary(db):
+    """Markdown table of a rocprofv3 kernel-trace database: per kernel, the
+    average over every dispatch and over the dispatches that did work."""
+    import collections
+    import re
+    import sqlite3
+    cur = sqlite3.connect(db).cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    ni, si, ei = cols.index("name"), cols.index("start"), cols.index("end")
+    agg = collections.defaultdict(list)
+    for r in cur.execute("select * from kernels").fetchall():
+        agg[r[ni]].append((r[ei] - r[si]) / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    out = ["| kernel | calls | avg us (all) | total ms | share | active calls | avg us (active) |",
+           "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        if sum(v) / tot < 0.002:
+            continue
+        nm = re.sub(r"^void ", "", k).replace("rsph::", "")
+        nm = re.sub(r"\((rsph::)?DevArrays.*", "", nm)
+        act = [x for x in v if x > 0.25 * max(v)]
+        out.append(f"| `{nm}` | {len(v)} | {sum(v) / len(v):.2f} | {sum(v) / 1e3:.3f} | "
+                   f"{100 * sum(v) / tot:.1f}% | {len(act)} | {sum(act) / len(act):.2f} |")
+    print("\n".join(out))
+
+
 def workload(name):
     if name == "square2d":
         return WL.square_droplet_2d(n_side=200)
@@ -218,7 +311,22 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-accel-check", action="store_true",
+                    help="skip the single-evaluation acceleration check against the oracle")
+    ap.add_argument("--copy-probe", action="store_true", help="1 GiB device copy (counter reference)")
+    ap.add_argument("--pmc-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the force-pass traffic line of --workload/--precision from rocprofv3 --pmc output")
+    ap.add_argument("--trace-summary", metavar="DB", help="markdown table of a rocprofv3 kernel-trace database")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.pmc_traffic:
+        pmc_traffic(args)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the method's hot path is single-GPU here; "
@@ -272,10 +380,11 @@ def main():
         extra["mixed_over_fp64"] = value / v64
         extra["fp64_force_avg_us"] = m64 / max(l64, 1) * 1e3
         log(f"fp64 gpu {r64['seconds']:.3f}s -> {v64:.3e} particle-steps/s, mixed/fp64 = {value / v64:.2f}")
-    try:
-        extra["accel_err_vs_fp64_oracle"] = accel_error(w, prec)
-    except Exception as e:  # the oracle is a checker, not the product
-        log(f"accel error check skipped: {e}")
+    if not args.no_accel_check:
+        try:
+            extra["accel_err_vs_fp64_oracle"] = accel_error(w, prec)
+        except Exception as e:  # the oracle is a checker, not the product
+            log(f"accel error check skipped: {e}")
 
     cpu = None
     if not args.no_cpu_baseline:
