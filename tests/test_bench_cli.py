@@ -1,0 +1,92 @@
+"""bench.py without a GPU: the single-GPU contract, and the profiling utilities
+that turn rocprofv3 output into the summaries and the traffic figure."""
+import csv
+import hashlib
+import os
+import sqlite3
+import subprocess
+import sys
+import types
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_trace_summary_table(tmp_path, capsys):
+    db = tmp_path / "run_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start integer, end integer)")
+    rows = []
+    t = 0
+    for k in range(10):  # 6 active force launches of 10 us, 4 idle ones of 1 us
+        d = 10000 if k < 6 else 1000
+        rows.append(("void rsph::k_force<float, 2>(rsph::DevArrays)", t, t + d))
+        t += d + 500
+    rows.append(("rsph::k_dt_substep(rsph::DevArrays, long, int)", t, t + 3000))
+    con.executemany("insert into kernels values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    bench.trace_summary(str(db))
+    out = capsys.readouterr().out.splitlines()
+    force = [l for l in out if "k_force<float, 2>" in l][0].split("|")
+    cells = [c.strip() for c in force]
+    assert cells[2] == "10"                    # calls
+    assert float(cells[3]) == (6 * 10 + 4 * 1) / 10  # avg over all dispatches, us
+    assert cells[6] == "6"                     # active calls
+    assert float(cells[7]) == 10.0             # active average
+    assert any("k_dt_substep" in l for l in out)
+
+
+def write_counters(path, kernel, counter, per_dispatch):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, v in enumerate(per_dispatch):
+            # two rows per dispatch, as for a counter summed over instances
+            for half in (0.5, 0.5):
+                w.writerow({"Dispatch_Id": d + 1, "Kernel_Name": kernel, "Counter_Name": counter,
+                            "Counter_Value": v * half})
+
+
+def test_pmc_traffic_line(tmp_path, monkeypatch):
+    kern = "void rsph::k_force<float, 2>(rsph::DevArrays)"
+    f_csv, w_csv = tmp_path / "f.csv", tmp_path / "w.csv"
+    cf_csv, cw_csv = tmp_path / "cf.csv", tmp_path / "cw.csv"
+    write_counters(f_csv, kern, "FETCH_SIZE", [4000.0, 4000.0, 10.0])   # KiB; the last is idle
+    write_counters(w_csv, kern, "WRITE_SIZE", [1000.0, 1000.0, 5.0])
+    copy = "__amd_rocclr_copyBuffer"
+    write_counters(cf_csv, copy, "FETCH_SIZE", [(1 << 20) / 2])  # reads half of 1 GiB in KiB
+    write_counters(cw_csv, copy, "WRITE_SIZE", [1 << 20])
+    traffic = tmp_path / "traffic.txt"
+    traffic.write_text("square_droplet_2d mixed oldsha 1 2\nother_workload mixed sha 3 4\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(traffic))
+    args = types.SimpleNamespace(pmc_traffic=[str(f_csv), str(w_csv), str(cf_csv), str(cw_csv)],
+                                 workload="square2d", precision="mixed")
+    bench.pmc_traffic(args)
+    lines = traffic.read_text().splitlines()
+    assert "other_workload mixed sha 3 4" in lines
+    mine = [l.split() for l in lines if l.startswith("square_droplet_2d mixed")]
+    assert len(mine) == 1
+    sha = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()
+    assert mine[0][2] == sha
+    assert float(mine[0][3]) == 4000.0 * 1024 * 2.0   # fetch scaled by the copy's factor 2
+    assert float(mine[0][4]) == 1000.0 * 1024 * 1.0
+    assert bench.recorded_traffic("square_droplet_2d", "mixed") == 4000.0 * 1024 * 2.0 + 1000.0 * 1024
+
+
+def test_bench_line_keys_documented():
+    # the keys the driver reads are produced by the default mode
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    for key in ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"]:
+        assert f'"{key}"' in src, key
