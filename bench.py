@@ -141,6 +141,56 @@ def pmc_traffic(args):
                       "write_bytes": write_b}), flush=True)
 
 
+def counter_summary(csv_paths):
+    """Markdown table of the vector-memory and ALU utilisation of the pair
+    kernels from rocprofv3 --pmc output (several runs, one counter group each;
+    per kernel the dispatch with the most waves; busy fractions are counter
+    totals per CU over the GPU-active cycles of one XCD)."""
+    import collections
+    import csv
+    import re
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(list)))
+    for path in csv_paths:
+        for row in csv.DictReader(open(path)):
+            k = re.sub(r"\(.*", "", row["Kernel_Name"]).replace("void ", "").replace("rsph::", "")
+            per[path][(k, int(row["Dispatch_Id"]))][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    # the GPU agent's XCD and CU counts: GRBM_GUI_ACTIVE is summed over the XCDs
+    n_xcc, cu = 1, 256
+    agent_csv = os.path.join(os.path.dirname(csv_paths[0]), "run_agent_info.csv")
+    if os.path.exists(agent_csv):
+        for row in csv.DictReader(open(agent_csv)):
+            if row.get("Vendor_Name") == "AMD" and row.get("Name", "").startswith("gfx"):
+                n_xcc, cu = int(row["Num_Xcc"]), int(row["Cu_Count"])
+    kern = collections.defaultdict(dict)
+    for path, disp in per.items():
+        best = {}
+        for (k, d), cs in disp.items():
+            waves = sum(cs.get("SQ_WAVES", [0.0]))
+            key = sum(cs.get("GRBM_GUI_ACTIVE", [0.0])) if not waves else waves
+            if k not in best or key > best[k][0]:
+                best[k] = (key, cs)
+        for k, (_, cs) in best.items():
+            for c, v in cs.items():
+                kern[k][c] = sum(v) / n_xcc if c == "GRBM_GUI_ACTIVE" else sum(v)
+    out = ["| kernel | cycles per XCD | VALU busy | TA busy | TD busy | L1 hit | L2 hit | VALU instr/wave | VMEM rd/wave |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(kern):
+        c = kern[k]
+        if not any(t in k for t in ("k_force", "k_continuity", "k_colour", "k_neighbours", "k_density",
+                                    "k_advection", "k_shift")):
+            continue
+        gui = c.get("GRBM_GUI_ACTIVE", float("nan"))
+        waves = c.get("SQ_WAVES", float("nan"))
+        f = lambda x: f"{100 * x:.0f} %" if x == x else "-"
+        tcp, req = c.get("TCP_TOTAL_CACHE_ACCESSES", float("nan")), c.get("TCP_TCC_READ_REQ", float("nan"))
+        hit, miss = c.get("TCC_HIT_sum", float("nan")), c.get("TCC_MISS_sum", float("nan"))
+        out.append(f"| `{k}` | {gui:.3e} | {f(c.get('SQ_ACTIVE_INST_VALU', float('nan')) / cu / gui)} | "
+                   f"{f(c.get('TA_TA_BUSY', float('nan')) / cu / gui)} | {f(c.get('TD_TD_BUSY', float('nan')) / cu / gui)} | "
+                   f"{f(1 - req / tcp)} | {f(hit / (hit + miss))} | {c.get('SQ_INSTS_VALU', float('nan')) / waves:.0f} | "
+                   f"{c.get('SQ_INSTS_VMEM_RD', float('nan')) / waves:.1f} |")
+    print("\n".join(out))
+
+
 def trace_summary(db):
     """Markdown table of a rocprofv3 kernel-trace database: per kernel, the
     average over every dispatch and over the dispatches that did work."""
@@ -317,6 +367,8 @@ def main():
     ap.add_argument("--pmc-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the force-pass traffic line of --workload/--precision from rocprofv3 --pmc output")
     ap.add_argument("--trace-summary", metavar="DB", help="markdown table of a rocprofv3 kernel-trace database")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="markdown table of pair-kernel utilisation from rocprofv3 --pmc output")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -326,6 +378,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

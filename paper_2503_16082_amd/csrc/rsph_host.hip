@@ -302,6 +302,7 @@ size_t plan_arrays(Alloc& M, int dim, int precision, DevArrays& A, int32_t*& mas
     A.flags = M.take<uint8_t>(Pc);
     A.nbr = M.take<uint32_t>(Pc * (size_t)A.kmax);
     A.ncount = M.take<int32_t>(Pc);
+    A.xd = M.take<double>(Pc * 4);
     A.r_acc = M.take<double>(3 * Pc);
     A.r_accp = M.take<double>(3 * Pc);
     A.r_accs = M.take<double>(3 * Pc);
@@ -339,8 +340,10 @@ void alloc_arrays(rsph_pool* P, int64_t Pc, int64_t Cc, int Sc)
 {
     Alloc M{P};
     plan_arrays(M, P->dim, P->precision, P->A, P->d_mask, P->d_targets, P->work_dev, Pc, Cc, Sc);
-    // binning expects zero cell counts (each scan clears the counts it reads)
+    // binning expects zero cell counts (each scan clears the counts it reads);
+    // kernel timing expects clear per-launch-group work flags
     launch_fill_i32(launch_of(P), P->A.cell_cnt, Cc, 0);
+    launch_fill_i32(launch_of(P), P->work_dev, P->A.work_cap, 0);
     P->P_cap = Pc;
     P->C_cap = Cc;
     P->S_cap = Sc;

@@ -156,6 +156,7 @@ struct DevArrays {
     uint8_t* flags;
     uint32_t* nbr;
     int32_t* ncount;
+    double* xd;      // frozen FP64 position {x, y, z, 0} per slot, read by the density summation
     // rates written by an evaluation (FP64, slot order)
     double* r_acc;    // 3 * P
     double* r_accp;

@@ -938,6 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     Q4<R>* vb = (Q4<R>*)A.vbuf[0];
     vb[i] = Q4<R>{(R)A.vel[0][i], (R)A.vel[1][i], D == 3 ? (R)A.vel[2][i] : (R)0, (R)0};
     ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
+    ((double4*)A.xd)[i] = double4{xi[0], xi[1], xi[2], 0.0};
     ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
     if (A.mode == 1)
         for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
@@ -968,7 +969,11 @@ __global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
     double wsum = 0.0;
     int coincident = 0, close = 0;
     for_neighbours<G, Chunk<R, D>::N>(
-        A, i, g, cnt, [&](uint32_t j) { return Pos3{{A.pos[0][j], A.pos[1][j], D == 3 ? A.pos[2][j] : 0.0}}; },
+        A, i, g, cnt,
+        [&](uint32_t j) {
+            const double4 q = ((const double4*)A.xd)[j];  // one 32-byte record per neighbour
+            return Pos3{{q.x, q.y, q.z}};
+        },
         [&](uint32_t j, const Pos3& rj) {
             double r2 = 0.0;
             for (int a = 0; a < D; ++a) {

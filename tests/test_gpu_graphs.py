@@ -98,3 +98,26 @@ def test_invalid_launch_mode():
     r = rsph.lib().rsph_set_launch_mode(s.h, 7)
     assert rsph.STATUS[r] == "EINVAL"
     s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kernel_timing_counts_only_launches_with_work(dim):
+    """A system created where an earlier one freed its memory: the timed force
+    and continuity launches that count are exactly the substeps taken."""
+    w = WL.static_droplet_2d(n_side=40, seed=31) if dim == 2 else WL.static_droplet_3d(n_side=16, seed=31)
+    first = rsph.System(w["params"], precision=1)
+    first.set_particles(w["pos"], w["vel"], w["phase"])
+    first.step(2)
+    first.close()
+    s = rsph.System(w["params"], precision=1)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(1)
+    n0 = s.observables()["n_sub"]
+    s.set_timing(["force", "continuity"])
+    s.step(3)
+    t = s.timing()
+    dn = s.observables()["n_sub"] - n0
+    say(f"timing dim={dim}: substeps {dn}, force launches {t['force'][0]}, continuity {t['continuity'][0]}")
+    assert t["force"][0] == dn
+    assert t["continuity"][0] == dn
+    s.close()
