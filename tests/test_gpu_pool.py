@@ -167,3 +167,51 @@ def test_serving_loop_continuous_batching():
         ref = alone(serve.build_job(descs[k]), 4, 1)
         for f in ["pos", "vel", "rho"]:
             assert np.array_equal(out["results"][k][f], ref[f])
+
+
+def test_empty_and_overfull_inputs_rejected():
+    w = WL.static_droplet_2d(n_side=30, seed=12)
+    s = rsph.System(w["params"])
+    with pytest.raises(rsph.RsphError) as e:
+        s.set_particles(np.zeros((0, 2)), np.zeros((0, 2)), np.zeros(0, np.int32))
+    assert e.value.name == "EINVAL"
+    # particles 2.5 times denser than dp: about 130 neighbours within 2h, more
+    # than a 2D list holds (64)
+    p = dict(w["params"])
+    n_side = 75
+    pos = WL.lattice(2, (n_side, n_side), 1.0 / n_side)
+    with pytest.raises(rsph.RsphError) as e:
+        s.set_particles(pos, np.zeros_like(pos), np.zeros(len(pos), np.int32))
+    assert e.value.name == "EINVAL"
+    assert "neighbours" in rsph.lib().rsph_last_error(s.h).decode()
+    # the system is still usable with valid particles
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(1)
+    assert s.observables()["health"] == 0
+    s.close()
+
+
+def test_tiny_and_ragged_systems_in_one_pool():
+    """Systems of 1, 7, 65 and 130 particles (slot ranges padded to 64) beside a
+    2,500-particle one, stepped together: each equals the same system alone."""
+    rng = np.random.default_rng(5)
+    jobs = []
+    for n in (1, 7, 65, 130):
+        p = WL.base_params(2, (1.0, 1.0), 0.02, (1000.0, 1.0), (0.1, 1e-3), 1.0, 2.0)
+        side = int(np.ceil(np.sqrt(n)))
+        pts = WL.lattice(2, (side, side), 0.05)[:n] + 0.3
+        phase = (rng.uniform(size=n) < 0.5).astype(np.int32)
+        vel = 0.01 * rng.normal(size=(n, 2))
+        jobs.append({"params": p, "pos": pts, "vel": vel, "phase": phase})
+    jobs.append(WL.static_droplet_2d(n_side=50, seed=13))
+    steps = [3, 2, 3, 1, 2]
+    for prec in (0, 1):
+        pool = rsph.Pool(2, precision=prec)
+        members = [pool.admit(w["params"], w["pos"], w["vel"], w["phase"]) for w in jobs]
+        pool.step(members, steps)
+        for w, s, n in zip(jobs, members, steps):
+            ref = alone(w, n, prec)
+            assert s.observables()["n_outer"] == n
+            for k in ["pos", "vel", "rho"]:
+                assert np.array_equal(s.read(k), ref[k]), (len(w["pos"]), k)
+        pool.close()
