@@ -576,7 +576,9 @@ DevArrays kernel_view(rsph_pool* P)
     return A;
 }
 
-// binning and neighbour lists for the systems whose stepping flag is set
+// binning and neighbour lists: in step mode for the systems that the key pass
+// puts at the start of an advection step, otherwise for the systems whose
+// stepping flag the caller set
 void rebuild(rsph_pool* P, int mode, int64_t group)
 {
     const Launch L = launch_of(P);
@@ -585,7 +587,7 @@ void rebuild(rsph_pool* P, int mode, int64_t group)
     {
         TimeScope t(P, RSPH_KERNEL_BIN, group);
         t.begin_range();
-        launch_bin(L, A);
+        launch_bin(L, A, group);
         t.end_range();
     }
     TimeScope t(P, RSPH_KERNEL_NEIGHBOURS, group);
@@ -616,7 +618,6 @@ void launch_cycle_eager(rsph_pool* P, int64_t m)
     DevArrays A = kernel_view(P);
     A.mode = 0;
     const int64_t g0 = P->next_group++;
-    launch_cycle_begin(L, A, g0);
     rebuild(P, 0, g0);
     {
         TimeScope t(P, RSPH_KERNEL_ADVECTION, g0);

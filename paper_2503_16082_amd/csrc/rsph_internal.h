@@ -128,7 +128,7 @@ struct DevArrays {
     double* mass;
     int32_t* id;
     int32_t* phase;
-    // second copy for the counting sort
+    // snapshot taken by the key pass, permuted back by the gather
     double* pos2[3];
     double* vel2[3];
     double* rho2;
@@ -196,11 +196,10 @@ struct Ev {
 
 void launch_fill_i32(const Launch& L, int32_t* p, int64_t n, int32_t v);
 void launch_empty(const Launch& L, Ev ev);
-void launch_cycle_begin(const Launch& L, const DevArrays& A, int64_t group);
 void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask);
 void launch_set_targets(const Launch& L, const DevArrays& A, const long long* targets);
 void launch_reset_ksub_max(const Launch& L, const DevArrays& A);
-void launch_bin(const Launch& L, const DevArrays& A);
+void launch_bin(const Launch& L, const DevArrays& A, int64_t group);
 void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev);
 int lanes_per_particle(int dim);
 void launch_advection(const Launch& L, const DevArrays& A, Ev ev);

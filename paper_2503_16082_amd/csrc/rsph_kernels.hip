@@ -374,24 +374,61 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* p, int64_t n, int3
     if (i < n) p[i] = v;
 }
 
+// Start of a launch cycle (step mode): systems that finished an advection
+// step go back to the boundary, or to idle once their target is reached or
+// after a fault; systems at the boundary with steps left run this cycle's
+// prologue.  The new state depends only on fields no thread of the key pass
+// writes (step count, target, health) and maps every state it can produce to
+// itself, so each thread evaluates it for its own system and the system's
+// first slot stores it: a thread that reads the stored state gets the same
+// answer as one that reads the old state.
+__device__ __forceinline__ int cycle_state(const SysDyn& D)
+{
+    const int st = D.state;
+    if (st == kSubstepping) return st;
+    const bool done = D.n_outer >= D.target || (D.health & ~kHealthClose);
+    return done ? kIdle : kBoundary;
+}
+
+// Cell key of every particle of a stepping system, its rank among the
+// particles of its cell in atomic order, and a snapshot of the state into the
+// second buffer, from which the gather then permutes it back.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_key(DevArrays A)
+__global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
 {
     Slot c = slot_of(A);
     if (!c.lane) return;
-    if (!A.sd[c.s].stepping) return;
+    SysDyn& Dy = A.sd[c.s];
     const SysConst& S = A.sc[c.s];
+    if (A.mode == 0) {
+        const int st = cycle_state(Dy);
+        if (c.i == S.p_off) {
+            Dy.state = st;
+            Dy.stepping = st == kBoundary;
+            if (st == kBoundary && A.work) atomicOr(A.work + group, 1);
+        }
+        if (st != kBoundary) return;
+    } else if (!Dy.stepping) {
+        return;
+    }
+    const int64_t i = c.i;
     int ck[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) {
-        double x = A.pos[a][c.i];
+        double x = A.pos[a][i];
         if (x < 0.0) x = __dadd_rn(x, S.box[a]);
         if (x >= S.box[a]) x = __dsub_rn(x, S.box[a]);
-        A.pos[a][c.i] = x;
+        A.pos2[a][i] = x;
+        A.vel2[a][i] = A.vel[a][i];
         ck[a] = cell_of(x, S, a);
     }
+    A.rho2[i] = A.rho[i];
+    A.drho2[i] = A.drho[i];
+    A.mass2[i] = A.mass[i];
+    A.id2[i] = A.id[i];
+    A.phase2[i] = A.phase[i];
     uint32_t key = (uint32_t)(ck[0] + S.ncell[0] * (ck[1] + S.ncell[1] * ck[2]));
-    A.key[c.i] = key;
-    A.rank[c.i] = atomicAdd(&A.cell_cnt[S.c_off + key], 1);
+    A.key[i] = key;
+    A.rank[i] = atomicAdd(&A.cell_cnt[S.c_off + key], 1);
 }
 
 // exclusive scan of cell_cnt[0..n) into cell_start[0..n], three phases
@@ -530,14 +567,14 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A)
     const uint32_t key = A.key[c.i];
     const int64_t base = S.p_off - A.cell_start[S.c_off];
     const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
-    const int32_t me = A.id[c.i];
+    const int32_t me = A.id2[c.i];
     int r = 0;
-    for (int64_t k = b; k < e; ++k) r += A.id[A.tmp[k]] < me;
+    for (int64_t k = b; k < e; ++k) r += A.id2[A.tmp[k]] < me;
     A.perm[b + r] = (int32_t)c.i;
 }
 
-// state gather into the second buffer, plus the per-fluid |v| max for the
-// advection time step
+// state gather from the snapshot into the primary arrays, in sorted order,
+// plus the per-fluid |v| max for the advection time step
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
 {
@@ -549,17 +586,17 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
         const int64_t src = A.perm[c.i];
         double v2 = 0.0;
         for (int a = 0; a < D; ++a) {
-            A.pos2[a][c.i] = A.pos[a][src];
-            double v = A.vel[a][src];
-            A.vel2[a][c.i] = v;
+            A.pos[a][c.i] = A.pos2[a][src];
+            double v = A.vel2[a][src];
+            A.vel[a][c.i] = v;
             v2 += v * v;
         }
-        A.rho2[c.i] = A.rho[src];
-        A.drho2[c.i] = A.drho[src];
-        A.mass2[c.i] = A.mass[src];
-        A.id2[c.i] = A.id[src];
-        const int ph = A.phase[src];
-        A.phase2[c.i] = ph;
+        A.rho[c.i] = A.rho2[src];
+        A.drho[c.i] = A.drho2[src];
+        A.mass[c.i] = A.mass2[src];
+        A.id[c.i] = A.id2[src];
+        const int ph = A.phase2[src];
+        A.phase[c.i] = ph;
         unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
         if (ph == 0) m0 = bits;
         else m1 = bits;
@@ -571,26 +608,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
         A.vpart[2 * w] = m0;
         A.vpart[2 * w + 1] = m1;
     }
-}
-
-// the sorted copy back into the primary arrays (systems outside the prologue
-// are not touched)
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_copyback(DevArrays A)
-{
-    Slot c = slot_of(A);
-    if (!c.lane) return;
-    if (!A.sd[c.s].stepping) return;
-    const int64_t i = c.i;
-    for (int a = 0; a < D; ++a) {
-        A.pos[a][i] = A.pos2[a][i];
-        A.vel[a][i] = A.vel2[a][i];
-    }
-    A.rho[i] = A.rho2[i];
-    A.drho[i] = A.drho2[i];
-    A.mass[i] = A.mass2[i];
-    A.id[i] = A.id2[i];
-    A.phase[i] = A.phase2[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1242,24 +1259,6 @@ __device__ __forceinline__ bool dt_collapsed(const SysConst& S, double dt_ac)
     return !(dt_ac > 1e-12 * S.cfl_ac * S.h * S.inv_c0);
 }
 
-// start of a launch cycle: systems that finished an advection step go back to
-// the boundary (or to idle once their target is reached); systems at the
-// boundary with steps left run the prologue of this cycle
-__global__ void k_cycle_begin(DevArrays A, int64_t group)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= A.nsys) return;
-    SysDyn& D = A.sd[s];
-    int st = D.state;
-    if (st == kEnding || st == kEnded) st = kBoundary;
-    if (st == kBoundary && D.n_outer >= D.target) st = kIdle;
-    if (st == kIdle && D.n_outer < D.target) st = kBoundary;
-    if (st == kBoundary && (D.health & ~kHealthClose)) st = kIdle;  // faulted: stop
-    D.state = st;
-    D.stepping = st == kBoundary;
-    if (D.stepping && A.work) atomicOr(A.work + group, 1);
-}
-
 __global__ void k_set_stepping(DevArrays A, const int32_t* mask)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1884,11 +1883,6 @@ void launch_fill_i32(const Launch& L, int32_t* p, int64_t n, int32_t v)
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, flat_grid(n), dim3(kBlock), 0, L.stream, p, n, v);
 }
 
-void launch_cycle_begin(const Launch& L, const DevArrays& A, int64_t group)
-{
-    hipLaunchKernelGGL(k_cycle_begin, sys_grid(A.nsys), dim3(64), 0, L.stream, A, group);
-}
-
 void launch_set_stepping(const Launch& L, const DevArrays& A, const int32_t* mask)
 {
     hipLaunchKernelGGL(k_set_stepping, sys_grid(A.nsys), dim3(64), 0, L.stream, A, mask);
@@ -1904,15 +1898,15 @@ void launch_set_targets(const Launch& L, const DevArrays& A, const long long* ta
     hipLaunchKernelGGL(k_set_targets, sys_grid(A.nsys), dim3(64), 0, L.stream, A, targets);
 }
 
-void launch_bin(const Launch& L, const DevArrays& A)
+void launch_bin(const Launch& L, const DevArrays& A, int64_t group)
 {
     // the cell counts are zero on entry: cleared when the arrays are
     // allocated and by every scan that consumes them
     const int64_t ncells = A.C;
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_key<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+        hipLaunchKernelGGL(k_key<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, group);
     else
-        hipLaunchKernelGGL(k_key<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+        hipLaunchKernelGGL(k_key<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, group);
     if (ncells <= kScanSmall) {
         hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanSmallThreads), 0, L.stream, A.cell_cnt, ncells,
                            A.cell_start);
@@ -1926,13 +1920,10 @@ void launch_bin(const Launch& L, const DevArrays& A)
     }
     hipLaunchKernelGGL(k_scatter, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     hipLaunchKernelGGL(k_rank, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    if (L.dim == 2) {
+    if (L.dim == 2)
         hipLaunchKernelGGL(k_gather<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-        hipLaunchKernelGGL(k_copyback<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    } else {
+    else
         hipLaunchKernelGGL(k_gather<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-        hipLaunchKernelGGL(k_copyback<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    }
 }
 
 #define RSPH_DISPATCH(KERNEL, LANES2, LANES3, EV, ...)                                                 \
