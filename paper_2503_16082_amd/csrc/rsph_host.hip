@@ -464,6 +464,8 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
     std::vector<SysDyn> sd(S);
     std::vector<int32_t> wave(A.P / kWave, -1);
     std::vector<int32_t> csys(A.C, -1);
+    const int lanes = lanes_per_particle(P->dim);
+    A.dt_pass = 0;
     for (int k = 0; k < S; ++k) {
         rsph_system* s = members[k];
         SysDyn d{};
@@ -475,6 +477,10 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
         s->sc.p_off = s->p_off;
         s->sc.p_n = s->has_particles ? s->n : 0;
         s->sc.c_off = s->c_off;
+        // per-block |v| partials of the force pass: small systems reduce them
+        // inside every continuity block instead of in a pass of their own
+        s->sc.fuse_dt = s->p_cap * lanes / kBlock <= kFuseDtEntries;
+        if (!s->sc.fuse_dt) A.dt_pass = 1;
         sc[k] = s->sc;
         sd[k] = d;
         for (int64_t w = s->p_off / kWave; w < (s->p_off + s->p_cap) / kWave; ++w) wave[w] = k;
@@ -637,10 +643,10 @@ void launch_cycle_eager(rsph_pool* P, int64_t m)
             TimeScope t(P, RSPH_KERNEL_FORCE, g);
             launch_force(L, A, t.ev);
         }
-        launch_dt_substep(L, A, g);
+        if (A.dt_pass) launch_dt_substep(L, A, g);
         {
             TimeScope t(P, RSPH_KERNEL_CONTINUITY, g);
-            launch_continuity(L, A, t.ev);
+            launch_continuity(L, A, t.ev, g);
         }
     }
 }
@@ -823,6 +829,7 @@ void reset_dyn(rsph_system* s, bool keep_clock)
     d.stepping = 0;
     d.ksub_max = 0;
     d.state = kBoundary;
+    d.sub_state = kIdle;
     d.ksub = 0;
     if (!keep_clock) {
         d.t = d.tau = d.dt_ad = d.dt_last = 0.0;
@@ -1085,7 +1092,7 @@ rsph_status rsph_eval_rates(rsph_system* s)
         launch_shift(L, A, Ev{});
         launch_colour(L, A, Ev{});
         launch_force(L, A, Ev{});
-        launch_continuity(L, A, Ev{});
+        launch_continuity(L, A, Ev{}, -1);
         clear_after_rebuild(s);
         s->rates_valid = true;
     });

@@ -22,6 +22,9 @@ namespace rsph {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+// systems with at most this many force-pass blocks (65,536 slots at 4 lanes per
+// particle) end their substeps inside the continuity pass
+constexpr int64_t kFuseDtEntries = 1024;
 constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lattice)
 constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
 constexpr int kMaxCellsPerAxis = 1024;
@@ -53,7 +56,7 @@ struct SysConst {
     int32_t dim;
     uint32_t flags;
     int32_t ncell[3];
-    int32_t pad0;
+    int32_t fuse_dt;  // 1: the continuity pass ends each substep itself (small systems)
     int64_t p_off;   // first slot
     int64_t p_n;     // particles
     int64_t c_off;   // first global cell
@@ -86,11 +89,13 @@ struct SysConst {
     double close2;        // (1e-3 dp)^2
 };
 
-// Advection-step state of a system (device resident, changed only by the
-// one-thread-per-system kernels):
+// Advection-step state of a system (device resident; each change is made by
+// one thread per system):
 //   idle -> boundary (outer-step target not reached) -> substepping (after the
-//   advection-step prologue) -> ending (the substep that completes the
-//   advection step, its continuity pass still to run) -> ended -> boundary/idle.
+//   advection-step prologue) -> ended -> boundary/idle.  A system whose
+//   substeps are ended by the separate substep pass goes through ending (the
+//   substep that completes the advection step, its continuity pass still to
+//   run) before ended.
 constexpr int32_t kIdle = 0;
 constexpr int32_t kBoundary = 1;
 constexpr int32_t kSubstepping = 2;
@@ -113,6 +118,12 @@ struct SysDyn {
     long long n_outer;
     long long target;                // advection steps to reach
     double dt_last;
+    // the substep as its force pass found it (stored by the system's first
+    // force block, read by the continuity pass that ends the substep)
+    int32_t sub_state;
+    uint32_t sub_health;
+    long long sub_ksub;
+    double sub_tau;
 };
 
 struct DevArrays {
@@ -120,6 +131,8 @@ struct DevArrays {
     int64_t C;       // global cell capacity
     int32_t kmax;
     int32_t mode;    // 0 = step, 1 = evaluate rates only (no state update)
+    int32_t dt_pass; // 1: some system's substeps are ended by the separate substep pass
+    int32_t pad1;
     // FP64 state, structure of arrays
     double* pos[3];
     double* vel[3];
@@ -207,7 +220,7 @@ void launch_shift(const Launch& L, const DevArrays& A, Ev ev);
 void launch_colour(const Launch& L, const DevArrays& A, Ev ev);
 void launch_force(const Launch& L, const DevArrays& A, Ev ev);
 void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group);
-void launch_continuity(const Launch& L, const DevArrays& A, Ev ev);
+void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group);
 void launch_observables(const Launch& L, const DevArrays& A);
 
 constexpr int kObsPart = 16;  // partial sums per wave and pass

@@ -1271,21 +1271,34 @@ __global__ void k_set_targets(DevArrays A, const long long* targets)
     if (s < A.nsys && targets[s] >= 0) A.sd[s].target = targets[s];
 }
 
-// per-fluid max |v| of one system from its partials: one entry per
+// Per-fluid maxima of |v| over one system from its partials, one entry per
 // `slots_per_entry` slots (64 for the per-wave partials of the gather, 256 / G
-// for the per-block partials of the force pass); one 256-thread block per
-// system, result in every thread
-__device__ __forceinline__ void reduce_vmax(const DevArrays& A, const SysConst& S, int slots_per_entry,
-                                            double* vmax)
+// for the per-block partials of the force pass), as FP64 bit patterns: |v| is
+// non-negative, so their integer order is the numeric one, and a non-finite
+// |v| compares above every finite one.  Every thread of the 256-thread block
+// takes part and gets the result; U partials per thread are in flight at a
+// time.
+template <int U>
+__device__ __forceinline__ void reduce_vmax_bits(const DevArrays& A, const SysConst& S, int64_t slots_per_entry,
+                                                 unsigned long long* m)
 {
     __shared__ unsigned long long red[2 * (kBlock / kWave)];
     const int64_t e0 = S.p_off / slots_per_entry;
     const int64_t e1 = (S.p_off + ((S.p_n + kWave - 1) / kWave) * kWave) / slots_per_entry;
+    const ulonglong2* vp = (const ulonglong2*)A.vpart;
     unsigned long long m0 = 0, m1 = 0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-        const unsigned long long a = A.vpart[2 * e], b = A.vpart[2 * e + 1];
-        m0 = a > m0 ? a : m0;
-        m1 = b > m1 ? b : m1;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += U * kBlock) {
+        ulonglong2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = e + (int64_t)u * kBlock;
+            v[u] = k < e1 ? vp[k] : make_ulonglong2(0ull, 0ull);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            m0 = v[u].x > m0 ? v[u].x : m0;
+            m1 = v[u].y > m1 ? v[u].y : m1;
+        }
     }
     m0 = wave_max_u64(m0);
     m1 = wave_max_u64(m1);
@@ -1299,8 +1312,21 @@ __device__ __forceinline__ void reduce_vmax(const DevArrays& A, const SysConst& 
         m0 = red[2 * k] > m0 ? red[2 * k] : m0;
         m1 = red[2 * k + 1] > m1 ? red[2 * k + 1] : m1;
     }
-    vmax[0] = __longlong_as_double((long long)m0);
-    vmax[1] = __longlong_as_double((long long)m1);
+    // identical in every lane: held in scalar registers
+    m[0] = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(m0 >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m0);
+    m[1] = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(m1 >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m1);
+}
+
+template <int U>
+__device__ __forceinline__ void reduce_vmax(const DevArrays& A, const SysConst& S, int64_t slots_per_entry,
+                                            double* vmax)
+{
+    unsigned long long m[2];
+    reduce_vmax_bits<U>(A, S, slots_per_entry, m);
+    vmax[0] = __longlong_as_double((long long)m[0]);
+    vmax[1] = __longlong_as_double((long long)m[1]);
 }
 
 // start of an advection step: per-fluid max |v| over the system, the advection
@@ -1309,7 +1335,7 @@ __device__ __forceinline__ void reduce_vmax(const DevArrays& A, const SysConst& 
 __device__ void begin_advection_step(const DevArrays& A, const SysConst& S, SysDyn& D)
 {
     double vmax[2];
-    reduce_vmax(A, S, kWave, vmax);
+    reduce_vmax<4>(A, S, kWave, vmax);
     if (threadIdx.x != 0) return;
     D.vmax[0] = vmax[0];
     D.vmax[1] = vmax[1];
@@ -1332,13 +1358,60 @@ __device__ void begin_advection_step(const DevArrays& A, const SysConst& S, SysD
     }
 }
 
-// after the force pass of substep k: advance the clock, choose the step of
-// substep k + 1 or end the advection step
+// End of substep k of an advection step: the clock advances by the substep's
+// acoustic step; the next one follows from the per-fluid |v| maxima of the
+// substep's velocity update (Eqs. 17, 18), clipped so that the advection step
+// ends exactly at its length, unless that length is reached, the acoustic step
+// collapsed or a velocity is not finite.
+struct SubstepEnd {
+    double tau;      // time into the advection step after substep k
+    double dt_next;  // acoustic step of substep k + 1
+    bool next;       // substep k + 1 follows
+    bool collapse;
+};
+
+__device__ __forceinline__ SubstepEnd end_substep(const SysConst& S, double dt_ad, double tau, double dt,
+                                                  uint32_t health, const double* vmax)
+{
+    SubstepEnd e;
+    e.tau = tau + dt;
+    const double dt_ac = dt_acoustic(S, vmax);
+    e.collapse = dt_collapsed(S, dt_ac) || (health & kHealthNonFinite) || !isfinite(vmax[0]) ||
+                 !isfinite(vmax[1]);
+    e.next = !e.collapse && e.tau < dt_ad * (1.0 - 1e-12);
+    e.dt_next = e.next ? fmin(dt_ac, dt_ad - e.tau) : 0.0;
+    return e;
+}
+
+// stores the end of substep k (one thread per system)
+__device__ __forceinline__ void commit_substep(SysDyn& D, long long k, double dt, const double* vmax,
+                                               const SubstepEnd& e, int32_t end_state)
+{
+    D.tau = e.tau;
+    D.t += dt;
+    D.n_sub += 1;
+    D.ksub = k + 1;
+    D.dt_last = dt;
+    D.vmax[0] = vmax[0];
+    D.vmax[1] = vmax[1];
+    if (e.next) {
+        D.dt[(k + 1) & 1] = e.dt_next;
+        return;
+    }
+    if (e.collapse) atomicOr(&D.health, kHealthDtCollapse);
+    D.state = end_state;
+    D.n_outer += 1;
+    if (k + 1 > D.ksub_max) D.ksub_max = (int32_t)(k + 1);
+}
+
+// after the force pass of substep k, for systems whose continuity pass does
+// not end the substep itself (one block per system)
 __global__ __launch_bounds__(kBlock) void k_dt_substep(DevArrays A, int64_t group, int G)
 {
     const int s = blockIdx.x;
     SysDyn& D = A.sd[s];
     const SysConst& S = A.sc[s];
+    if (S.fuse_dt) return;
     const int st = D.state;
     if (st == kEnding) {
         if (threadIdx.x == 0) D.state = kEnded;
@@ -1346,30 +1419,12 @@ __global__ __launch_bounds__(kBlock) void k_dt_substep(DevArrays A, int64_t grou
     }
     if (st != kSubstepping) return;  // block-uniform
     double vmax[2];
-    reduce_vmax(A, S, kBlock / G, vmax);
+    reduce_vmax<16>(A, S, kBlock / G, vmax);
     if (threadIdx.x != 0) return;
     if (A.work) atomicOr(A.work + group, 1);
     const long long k = D.ksub;
     const double dt = D.dt[k & 1];
-    D.tau += dt;
-    D.t += dt;
-    D.n_sub += 1;
-    D.ksub = k + 1;
-    D.dt_last = dt;
-    D.vmax[0] = vmax[0];
-    D.vmax[1] = vmax[1];
-    const double dt_ac = dt_acoustic(S, vmax);
-    if (dt_collapsed(S, dt_ac) || (D.health & kHealthNonFinite)) {
-        atomicOr(&D.health, kHealthDtCollapse);
-        D.state = kEnding;
-        D.n_outer += 1;
-    } else if (D.tau < D.dt_ad * (1.0 - 1e-12)) {
-        D.dt[(k + 1) & 1] = fmin(dt_ac, D.dt_ad - D.tau);
-    } else {
-        D.state = kEnding;
-        D.n_outer += 1;
-    }
-    if (D.state == kEnding && k + 1 > D.ksub_max) D.ksub_max = (int32_t)(k + 1);
+    commit_substep(D, k, dt, vmax, end_substep(S, D.dt_ad, D.tau, dt, D.health, vmax), kEnding);
 }
 
 __global__ void k_reset_ksub_max(DevArrays A)
@@ -1398,7 +1453,15 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     const Q4<R> gi_i = geo[i];
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
-    const SysDyn& Dy = A.sd[c.s];
+    SysDyn& Dy = A.sd[c.s];
+    if (A.mode == 0 && threadIdx.x == 0 && logical_block() * (kBlock / G) == A.sc[c.s].p_off) {
+        // the substep as it starts, for the continuity pass that ends it (no
+        // pass before that reads these fields)
+        Dy.sub_state = Dy.state;
+        Dy.sub_health = Dy.health;
+        Dy.sub_ksub = Dy.ksub;
+        Dy.sub_tau = Dy.tau;
+    }
     if (!substep_on(Dy, A.mode)) return;
     const bool on = c.lane && (fl & kFlagInterface);
     if (!__any(on)) return;  // wave without interface particles
@@ -1645,7 +1708,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 // ---------------------------------------------------------------------------
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A)
+__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t group)
 {
     constexpr int G = Lanes<D>::G;
     int g;
@@ -1667,12 +1730,27 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A)
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
-    const int st = Dy.state;
-    if (A.mode == 0 && st != kSubstepping && st != kEnding) return;
-    if (A.mode == 1 && !Dy.stepping) return;
     const SysConst& S = A.sc[c.s];
-    // the substep this pass completes (its force pass already advanced ksub)
-    const int64_t kk = A.mode ? 0 : Dy.ksub - 1;
+    // the substep this pass completes
+    int64_t kk = 0;
+    int st = kSubstepping;
+    const bool fused = A.mode == 0 && S.fuse_dt;
+    unsigned long long vbits[2] = {0ull, 0ull};
+    if (A.mode == 1) {
+        if (!Dy.stepping) return;
+    } else if (fused) {
+        // This pass ends the substep: every block reduces the system's |v|
+        // maxima of the force pass and decides from the substep as it started
+        // (after the pair sum below), so all blocks decide alike.
+        if (Dy.sub_state != kSubstepping) return;  // block-uniform
+        kk = Dy.sub_ksub;
+        reduce_vmax_bits<4>(A, S, kBlock / G, vbits);
+    } else {
+        // the substep pass has ended the substep (and advanced ksub)
+        st = Dy.state;
+        if (st != kSubstepping && st != kEnding) return;
+        kk = Dy.ksub - 1;
+    }
     const int slot = (int)(kk & 1);
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
     const Q4<R>* vk = (const Q4<R>*)A.vbuf[slot ^ 1];
@@ -1705,17 +1783,35 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A)
             s += (vie + Ustar) * dW * tj.y;
         });
     s = group_sum<G>(s);
+    // the acoustic steps of this substep and, if another one follows in the
+    // advection step, of the next
+    const double dt = Dy.dt[kk & 1];
+    double dt2 = 0.0;
+    bool next = st == kSubstepping;
+    if (fused) {
+        const double vmax[2] = {__longlong_as_double((long long)vbits[0]),
+                                __longlong_as_double((long long)vbits[1])};
+        const SubstepEnd e = end_substep(S, Dy.dt_ad, Dy.sub_tau, dt, Dy.sub_health, vmax);
+        next = e.next;
+        dt2 = e.dt_next;
+        // the system's first block stores the decision (no block of this
+        // pass reads the fields it changes)
+        if (threadIdx.x == 0 && logical_block() * (kBlock / G) == S.p_off) {
+            if (A.work) atomicOr(A.work + group, 1);
+            commit_substep(Dy, kk, dt, vmax, e, kEnded);
+        }
+    } else if (next) {
+        dt2 = Dy.dt[(kk + 1) & 1];
+    }
     if (!c.lane || g != 0) return;
     const double drho = 2.0 * (double)ti.x * (double)s;
     if (A.mode == 1) {
         A.r_drho[i] = drho;
         return;
     }
-    const double dt = Dy.dt[kk & 1];
     double rho = rho_i + 0.5 * dt * drho;
     for (int a = 0; a < D; ++a) pos_i[a] += 0.5 * dt * vel_i[a];
-    if (st == kSubstepping) {
-        const double dt2 = Dy.dt[(kk + 1) & 1];
+    if (next) {
         rho += 0.5 * dt2 * drho;
         for (int a = 0; a < D; ++a) pos_i[a] += 0.5 * dt2 * vel_i[a];
         const int ph = Geo<R>::phase(gi);
@@ -1969,9 +2065,9 @@ void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group)
                        lanes_per_particle(L.dim));
 }
 
-void launch_continuity(const Launch& L, const DevArrays& A, Ev ev)
+void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group)
 {
-    RSPH_DISPATCH(k_continuity, G2, G3, ev, A);
+    RSPH_DISPATCH(k_continuity, G2, G3, ev, A, group);
 }
 
 void launch_observables(const Launch& L, const DevArrays& A)

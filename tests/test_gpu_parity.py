@@ -204,10 +204,14 @@ def test_single_particle_and_single_phase_edge_cases():
 # trajectories
 # ---------------------------------------------------------------------------
 
-def test_fp64_trajectory_matches_oracle():
-    w = WL.static_droplet_2d(n_side=50, R=0.2, seed=0)
+@pytest.mark.parametrize("n_side", [50, 260])
+def test_fp64_trajectory_matches_oracle(n_side):
+    """4 advection steps of the static droplet.  At 2,500 particles the
+    continuity pass ends each substep; at 67,600 (more than 1,024 force-pass
+    blocks) a pass of its own does."""
+    w = WL.static_droplet_2d(n_side=n_side, R=0.2, seed=0)
     p = w["params"]
-    say("trajectory static droplet 2D, 4 advection steps")
+    say(f"trajectory static droplet 2D n={len(w['pos'])}, 4 advection steps")
     st = O.State(p, w["pos"], w["vel"], w["phase"])
     st.step(4)
     s = rsph.System(p, precision=0)

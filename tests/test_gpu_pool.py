@@ -57,6 +57,28 @@ def test_pool_matches_alone_bitwise(precision):
     pool.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_and_small_systems_in_one_pool(precision):
+    """A system of 67,600 particles, whose substeps a pass of their own ends,
+    beside small ones whose continuity pass ends them: each equals itself
+    alone bit for bit."""
+    ws = [WL.static_droplet_2d(n_side=260, seed=8),
+          WL.oscillating_ellipse_2d(2500, 1.3, 1000.0, 1.0, seed=9),
+          WL.oscillating_ellipse_2d(4900, 1.1, 100.0, 1.5, seed=10)]
+    steps = [3, 4, 2]
+    say(f"large and small systems precision={precision}")
+    pool = rsph.Pool(2, precision=precision)
+    members = [pool.admit(w["params"], w["pos"], w["vel"], w["phase"]) for w in ws]
+    pool.step(members, steps)
+    for w, s, n in zip(ws, members, steps):
+        ref = alone(w, n, precision)
+        o = s.observables()
+        assert o["n_outer"] == n and o["n_sub"] == ref["obs"]["n_sub"] and o["t"] == ref["obs"]["t"]
+        for k in ["pos", "vel", "rho", "drho"]:
+            assert np.array_equal(s.read(k), ref[k]), k
+    pool.close()
+
+
 def test_pool_admission_budget_release_and_continuation():
     ws = jobs()
     probe = rsph.Pool(2, precision=1)
