@@ -574,7 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A)
 }
 
 // state gather from the snapshot into the primary arrays, in sorted order,
-// plus the per-fluid |v| max for the advection time step
+// plus the packed positions and the per-fluid |v| max for the advection time
+// step
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
 {
@@ -585,12 +586,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
     if (c.lane) {
         const int64_t src = A.perm[c.i];
         double v2 = 0.0;
+        double x[3] = {0.0, 0.0, 0.0};
         for (int a = 0; a < D; ++a) {
-            A.pos[a][c.i] = A.pos2[a][src];
+            x[a] = A.pos2[a][src];
+            A.pos[a][c.i] = x[a];
             double v = A.vel2[a][src];
             A.vel[a][c.i] = v;
             v2 += v * v;
         }
+        // one 32-byte position record per slot, read by the neighbour pass
+        ((double4*)A.xd)[c.i] = double4{x[0], x[1], x[2], 0.0};
         A.rho[c.i] = A.rho2[src];
         A.drho[c.i] = A.drho2[src];
         A.mass[c.i] = A.mass2[src];
@@ -620,9 +625,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
 // 3^d stencils is a small box of cells whose particles are copied once per
 // block as FP32 offsets from their own cell corner.  A candidate is tested in
 // FP32 on these split positions.  Candidates within a relative 1e-5 of the
-// cut-off (2h)^2 are entered with a mark and afterwards decided by the exact
-// FP64 predicate on the stored positions (the list is compacted), so the
-// neighbour set is exactly the one of the FP64 predicate.  The three cells of
+// cut-off (2h)^2 are decided on the spot by the exact FP64 predicate on the
+// stored positions, so the neighbour set is exactly the one of the FP64
+// predicate.  The three cells of
 // a stencil row are consecutive both in LDS and, unless the row wraps around
 // the periodic box, in the cell-sorted slots, so a row is scanned as one range.
 // Blocks whose union does not fit fall back to testing every candidate in FP64
@@ -630,7 +635,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
 // (stencil cells in z, y, x order, slots ascending within a cell).
 constexpr int kStageCells = 128;
 constexpr int kStageCap = 2304;
-constexpr uint32_t kBandMark = 0x80000000u;  // list entry awaiting the exact test
 
 struct Stage {
     // x, y, z offsets from the candidate's own cell corner; w holds the bits
@@ -645,6 +649,30 @@ struct Stage {
 };
 
 __device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// FP64 position of slot j from its packed record (16 bytes read in 2D)
+template <int D>
+__device__ __forceinline__ void load_pos(const DevArrays& A, int64_t j, double* x)
+{
+    if constexpr (D == 2) {
+        const double2 q = ((const double2*)A.xd)[2 * j];
+        x[0] = q.x;
+        x[1] = q.y;
+        x[2] = 0.0;
+    } else {
+        const double4 q = ((const double4*)A.xd)[j];
+        x[0] = q.x;
+        x[1] = q.y;
+        x[2] = q.z;
+    }
+}
+
+// periodic image offset along axis a of the stencil cell c (unwrapped: one
+// cell either way of the particle's own)
+__device__ __forceinline__ double image_offset(const SysConst& S, int c, int a)
+{
+    return c < 0 ? -S.box[a] : (c >= S.ncell[a] ? S.box[a] : 0.0);
+}
 
 template <int D>
 __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& S, Stage& L,
@@ -715,13 +743,15 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
         const int cx = wrap_cell(L.lo[0] - 1 + lx, S.ncell[0]);
         const int cy = wrap_cell(L.lo[1] - 1 + ly, S.ncell[1]);
         const int64_t j = L.gs[lo] + (k - L.off[lo]);
+        double xj[3];
+        load_pos<D>(A, j, xj);
         float4 q;
-        q.x = (float)(A.pos[0][j] - (double)cx * S.cell[0]);
-        q.y = (float)(A.pos[1][j] - (double)cy * S.cell[1]);
+        q.x = (float)(xj[0] - (double)cx * S.cell[0]);
+        q.y = (float)(xj[1] - (double)cy * S.cell[1]);
         q.z = 0.f;
         if (D == 3) {
             const int cz = wrap_cell(L.lo[2] - 1 + lz, S.ncell[2]);
-            q.z = (float)(A.pos[2][j] - (double)cz * S.cell[2]);
+            q.z = (float)(xj[2] - (double)cz * S.cell[2]);
         }
         q.w = __int_as_float((lx << 1) | (A.phase[j] & 1));
         L.q[k] = q;
@@ -736,33 +766,20 @@ template <int D>
 __device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi, int64_t j, double kx,
                                            double ky, double kz)
 {
-    double d = __dsub_rn(xi[0], A.pos[0][j]);
+    double xj[3];
+    load_pos<D>(A, j, xj);
+    double d = __dsub_rn(xi[0], xj[0]);
     if (kx != 0.0) d = __dsub_rn(d, kx);
     double r2 = __dmul_rn(d, d);
-    d = __dsub_rn(xi[1], A.pos[1][j]);
+    d = __dsub_rn(xi[1], xj[1]);
     if (ky != 0.0) d = __dsub_rn(d, ky);
     r2 = __dadd_rn(r2, __dmul_rn(d, d));
     if (D == 3) {
-        d = __dsub_rn(xi[2], A.pos[2][j]);
+        d = __dsub_rn(xi[2], xj[2]);
         if (kz != 0.0) d = __dsub_rn(d, kz);
         r2 = __dadd_rn(r2, __dmul_rn(d, d));
     }
     return r2;
-}
-
-// periodic image offset of the stencil cell holding slot j, for a particle in
-// cell ci: the stencil reaches one cell either way and wraps at the box edges
-template <int D>
-__device__ __forceinline__ void stencil_shift(const DevArrays& A, const SysConst& S, int64_t j, const int* ci,
-                                              double* k)
-{
-    for (int a = 0; a < 3; ++a) {
-        k[a] = 0.0;
-        if (a >= D) continue;
-        const int d = cell_of(A.pos[a][j], S, a) - ci[a];
-        if (d == S.ncell[a] - 1) k[a] = -S.box[a];
-        else if (d == -(S.ncell[a] - 1)) k[a] = S.box[a];
-    }
 }
 
 // Ordered append of the hits of G consecutive candidates tested by the lanes
@@ -780,8 +797,7 @@ __device__ __forceinline__ void append_hits(bool hit, uint32_t entry, int gshift
 }
 
 // Every candidate of the 3^d stencil tested by the exact FP64 predicate on
-// positions in global memory (blocks whose union does not fit in LDS, and the
-// rare list that overflowed before its marked entries were decided).
+// positions in global memory (blocks whose union does not fit in LDS).
 template <int D, int G>
 __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, const double* xi, const int* ci,
                             int ph, bool live, int g, int gshift, uint32_t below, int64_t base, uint32_t* out,
@@ -825,6 +841,66 @@ __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, co
     }
 }
 
+// Kernel sum sigma_i = W(0) + sum_j W_ij over particle i's list, the
+// normalised density summation rho_i = rho0_i sigma_i / sigma0, and the
+// {rho, V, p} record of the advection-step passes; flags pairs closer than
+// 1e-9 h.  FP64 in both forms: the density decides the pressure
+// c0^2 (rho - rho0), which amplifies a density error by rho / (rho - rho0).
+// Every lane of the group takes part; the lane that stores (lane 0 of a live
+// slot) gets true and the volume V.
+template <typename R, int D, int G>
+__device__ __forceinline__ bool density_summation(const DevArrays& A, const SysConst& S, SysDyn& Dy, int64_t i,
+                                                  int g, bool live, int cnt, const double* xi, double& V)
+{
+    double wsum = 0.0;
+    int coincident = 0, close = 0;
+    for_neighbours<G, Chunk<R, D>::N>(
+        A, i, g, live ? cnt : 0,
+        [&](uint32_t j) {
+            const double4 q = ((const double4*)A.xd)[j];  // one 32-byte record per neighbour
+            return Pos3{{q.x, q.y, q.z}};
+        },
+        [&](uint32_t j, const Pos3& rj) {
+            double r2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                double d = xi[a] - rj.x[a];
+                if (d > S.half_box[a]) d -= S.box[a];
+                else if (d < -S.half_box[a]) d += S.box[a];
+                r2 += d * d;
+            }
+            wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
+            coincident |= r2 < S.coincident2;
+            close |= r2 < S.close2;
+        });
+    wsum = group_sum<G>(wsum);
+    for (int o = 1; o < G; o <<= 1) {
+        coincident |= __shfl_xor(coincident, o, 64);
+        close |= __shfl_xor(close, o, 64);
+    }
+    if (!live || g != 0) return false;
+    if (coincident) flag_health(Dy, kHealthCoincident);
+    if (close) flag_health(Dy, kHealthClose);
+    const double sigma = S.w0 + wsum;
+    const int ph = A.phase[i];
+    double rho = A.rho[i];
+    if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
+        rho = S.rho0[ph] * sigma / S.sigma0;
+        A.rho[i] = rho;
+    }
+    if (A.mode == 1) A.r_sigma[i] = sigma;
+    V = A.mass[i] / rho;
+    const double p = S.c0sq * (rho - S.rho0[ph]);
+    ((Q4<R>*)A.th[1])[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
+    return true;
+}
+
+// In 2D the neighbour pass ends with the density summation over the new list
+// (after a block barrier, the entries written by the other lanes of the group
+// visible): the list is short, and at small sizes a pass costs mostly its
+// launch.  In 3D the summation is a pass of its own: it gathers some 75
+// positions per particle, and the LDS staging of the neighbour pass holds that
+// pass to 4 blocks per CU, half the occupancy the gather-bound sum runs at
+// alone.
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
 {
@@ -844,13 +920,14 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     const int gshift = (threadIdx.x & 63) & ~(G - 1);
     const uint32_t below = (1u << g) - 1u;
     const int64_t base = S.p_off - A.cell_start[S.c_off];
-    double xi[3] = {0.0, 0.0, 0.0};
+    double xi[3] = {0.0, 0.0, 0.0}, vel_i[3] = {0.0, 0.0, 0.0};
     int ci[3] = {0, 0, 0};
     int ph = 0;
     if (live) {
+        load_pos<D>(A, i, xi);
         for (int a = 0; a < D; ++a) {
-            xi[a] = A.pos[a][i];
             ci[a] = cell_of(xi[a], S, a);
+            vel_i[a] = A.vel[a][i];
         }
         ph = A.phase[i];
     }
@@ -858,7 +935,6 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     int cnt = 0;
     int cross = 0;
     uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
-    bool marked = false;
     if (L.ok) {  // block-uniform
         float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
         for (int a = 0; a < 3; ++a) {
@@ -872,8 +948,10 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
         const int zr = D == 3 ? 1 : 0;
         for (int dz = -zr; dz <= zr; ++dz) {
             const float rz0 = oi[2] - (float)dz * cellf[2];
+            const double kz = D == 3 ? image_offset(S, ci[2] + dz, 2) : 0.0;
             for (int dy = -1; dy <= 1; ++dy) {
                 const float ry0 = oi[1] - (float)dy * cellf[1];
+                const double ky = image_offset(S, ci[1] + dy, 1);
                 // the row's three cells
                 int u0 = 0, rb = 0, re = 0;
                 bool contiguous = true;
@@ -898,17 +976,17 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                         const bool valid = k < ke;
                         const float4 q = L.q[valid ? k : kb];
                         const int w = __float_as_int(q.w);
-                        const float ax = (oi[0] - q.x) - (float)((w >> 1) - lx) * cellf[0];
+                        const int dx = (w >> 1) - lx;
+                        const float ax = (oi[0] - q.x) - (float)dx * cellf[0];
                         const float ay = ry0 - q.y;
                         const float az = D == 3 ? rz0 - q.z : 0.f;
                         const float r2f = ax * ax + ay * ay + az * az;
                         const int j = jofs + k;
-                        const bool hit = valid && j != i32 && r2f < cut_hi;
-                        const bool band = r2f >= cut_lo;
+                        bool hit = valid && j != i32 && r2f < cut_hi;
+                        if (hit && r2f >= cut_lo)  // within the FP32 error of the cut-off
+                            hit = exact_r2<D>(A, xi, j, image_offset(S, ci[0] + dx, 0), ky, kz) < S.cut2;
                         cross |= hit && (w & 1) != ph;
-                        marked |= hit && band;
-                        append_hits<G>(hit, (uint32_t)j | (band ? kBandMark : 0u), gshift, below, out, A.kmax,
-                                       cnt);
+                        append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
                     }
                 }
             }
@@ -916,56 +994,30 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     } else {
         scan_global<D, G>(A, S, i, xi, ci, ph, live, g, gshift, below, base, out, cnt, cross);
     }
-    int mk = marked;
-    for (int o = 1; o < G; o <<= 1) mk |= __shfl_xor(mk, o, 64);
-    if (mk && cnt > A.kmax) {  // group-uniform
-        // entries were lost before the marked ones were decided: rescan exactly
-        cnt = 0;
-        cross = 0;
-        scan_global<D, G>(A, S, i, xi, ci, ph, live, g, gshift, below, base, out, cnt, cross);
-    }
     for (int o = 1; o < G; o <<= 1) cross |= __shfl_xor(cross, o, 64);
-    if (!live || g != 0) return;
-    if (mk && cnt <= A.kmax) {
-        // entries near the cut-off: the exact FP64 predicate decides, in list
-        // order, and the list is compacted
-        int kept = 0;
-        int xc = 0;
-        for (int q = 0; q < cnt; ++q) {
-            uint32_t e = out[(int64_t)q * kWave];
-            if (e & kBandMark) {
-                e &= ~kBandMark;
-                double ks[3];
-                stencil_shift<D>(A, S, e, ci, ks);
-                if (!(exact_r2<D>(A, xi, e, ks[0], ks[1], ks[2]) < S.cut2)) continue;
-            }
-            xc |= A.phase[e] != ph;
-            out[(int64_t)kept * kWave] = e;
-            ++kept;
-        }
-        cnt = kept;
-        cross = xc;
-    }
-    if (cnt > A.kmax) {
-        flag_health(Dy, kHealthNeighbours);
+    if (cnt > A.kmax) {  // group-uniform
+        if (live && g == 0) flag_health(Dy, kHealthNeighbours);
         cnt = A.kmax;
     }
+    double V = 0.0;
+    bool store = live && g == 0;
+    if constexpr (D == 2) {
+        __syncthreads();
+        store = density_summation<R, D, G>(A, S, Dy, i, g, live, cnt, xi, V);
+    }
+    if (!store) return;
     A.ncount[i] = cnt;
     A.flags[i] = cross ? kFlagInterface : 0;
-    Q4<R>* vb = (Q4<R>*)A.vbuf[0];
-    vb[i] = Q4<R>{(R)A.vel[0][i], (R)A.vel[1][i], D == 3 ? (R)A.vel[2][i] : (R)0, (R)0};
-    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
-    ((double4*)A.xd)[i] = double4{xi[0], xi[1], xi[2], 0.0};
-    ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
     if (A.mode == 1)
         for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
+    // the volume rides in the spare component of the velocity record read by
+    // the advection pass (in 3D stored by the density pass)
+    ((Q4<R>*)A.vbuf[0])[i] = Q4<R>{(R)vel_i[0], (R)vel_i[1], (R)vel_i[2], (R)V};
+    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
+    ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
 }
 
-// Kernel sum sigma_i = W(0) + sum_j W_ij over the frozen list, the normalised
-// density summation rho_i = rho0_i sigma_i / sigma0, and the {rho, V, p}
-// records of the advection-step passes; flags pairs closer than 1e-9 h.  FP64
-// in both forms: the density decides the pressure c0^2 (rho - rho0), which
-// amplifies a density error by rho / (rho - rho0).
+// the density summation as a pass of its own (3D)
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
 {
@@ -983,48 +1035,9 @@ __global__ __launch_bounds__(kBlock) void k_density(DevArrays A)
         for (int a = 0; a < D; ++a) xi[a] = A.pos[a][i];
         cnt = A.ncount[i];
     }
-    double wsum = 0.0;
-    int coincident = 0, close = 0;
-    for_neighbours<G, Chunk<R, D>::N>(
-        A, i, g, cnt,
-        [&](uint32_t j) {
-            const double4 q = ((const double4*)A.xd)[j];  // one 32-byte record per neighbour
-            return Pos3{{q.x, q.y, q.z}};
-        },
-        [&](uint32_t j, const Pos3& rj) {
-            double r2 = 0.0;
-            for (int a = 0; a < D; ++a) {
-                double d = xi[a] - rj.x[a];
-                if (d > S.half_box[a]) d -= S.box[a];
-                else if (d < -S.half_box[a]) d += S.box[a];
-                r2 += d * d;
-            }
-            wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
-            coincident |= r2 < S.coincident2;
-            close |= r2 < S.close2;
-        });
-    wsum = group_sum<G>(wsum);
-    for (int o = 1; o < G; o <<= 1) {
-        coincident |= __shfl_xor(coincident, o, 64);
-        close |= __shfl_xor(close, o, 64);
-    }
-    if (!c.lane || g != 0) return;
-    if (coincident) flag_health(Dy, kHealthCoincident);
-    if (close) flag_health(Dy, kHealthClose);
-    const double sigma = S.w0 + wsum;
-    const int ph = A.phase[i];
-    double rho = A.rho[i];
-    if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
-        rho = S.rho0[ph] * sigma / S.sigma0;
-        A.rho[i] = rho;
-    }
-    if (A.mode == 1) A.r_sigma[i] = sigma;
-    const double V = A.mass[i] / rho;
-    const double p = S.c0sq * (rho - S.rho0[ph]);
-    ((Q4<R>*)A.th[1])[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
-    // the volume also rides in the spare component of the velocity record read
-    // by the advection pass
-    reinterpret_cast<R*>((Q4<R>*)A.vbuf[0] + i)[3] = (R)V;
+    double V = 0.0;
+    if (density_summation<R, D, G>(A, S, Dy, i, g, c.lane, cnt, xi, V))
+        reinterpret_cast<R*>((Q4<R>*)A.vbuf[0] + i)[3] = (R)V;
 }
 
 // ---------------------------------------------------------------------------
@@ -1920,14 +1933,35 @@ __global__ __launch_bounds__(kBlock) void k_obs_final(DevArrays A, int pass)
     const SysConst& S = A.sc[s];
     const int64_t w0 = S.p_off / kWave, w1 = (S.p_off + S.p_n + kWave - 1) / kWave;
     double* o = A.obs_out + (int64_t)s * kObsOut;
+    // thread t accumulates waves t, t + 256, ... in that order, every quantity
+    // at once: the 128-byte records of U waves are in flight together
+    constexpr int U = 2;
+    static_assert(kObsPart % 2 == 0, "16-byte loads");
+    double acc[kObsPart];
+    for (int k = 0; k < kObsPart; ++k) acc[k] = 0.0;
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += U * kBlock) {
+        double2 r[U][kObsPart / 2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t wu = w + (int64_t)u * kBlock;
+            const double2* src = (const double2*)(A.obs_part + (wu < w1 ? wu : w) * kObsPart);
+#pragma unroll
+            for (int k = 0; k < kObsPart / 2; ++k) r[u][k] = src[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (w + (int64_t)u * kBlock >= w1) break;
+#pragma unroll
+            for (int k = 0; k < kObsPart; ++k) {
+                const double v = (k & 1) ? r[u][k >> 1].y : r[u][k >> 1].x;
+                const bool is_max = pass == 0 && (k == 8 || k == 9);
+                acc[k] = is_max ? fmax(acc[k], v) : acc[k] + v;
+            }
+        }
+    }
     for (int k = 0; k < kObsPart; ++k) {
         const bool is_max = pass == 0 && (k == 8 || k == 9);
-        double acc = 0.0;
-        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) {
-            const double v = A.obs_part[w * kObsPart + k];
-            acc = is_max ? fmax(acc, v) : acc + v;
-        }
-        lds[threadIdx.x] = acc;
+        lds[threadIdx.x] = acc[k];
         __syncthreads();
         for (int h = kBlock / 2; h > 0; h >>= 1) {
             if (threadIdx.x < h)
@@ -2043,7 +2077,12 @@ constexpr int G3 = Lanes<3>::G;
 void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev)
 {
     RSPH_DISPATCH(k_neighbours, G2, G3, ev, A);
-    RSPH_DISPATCH(k_density, G2, G3, Ev{}, A);
+    if (L.dim == 3) {
+        if (L.fp64)
+            go(k_density<double, 3>, slot_grid(A.P, G3), dim3(kBlock), L.stream, Ev{}, A);
+        else
+            go(k_density<float, 3>, slot_grid(A.P, G3), dim3(kBlock), L.stream, Ev{}, A);
+    }
 }
 
 int lanes_per_particle(int dim) { return dim == 2 ? G2 : G3; }
