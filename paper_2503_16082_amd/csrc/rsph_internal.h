@@ -141,7 +141,7 @@ struct DevArrays {
     double* mass;
     int32_t* id;
     int32_t* phase;
-    // snapshot taken by the key pass, permuted back by the gather
+    // snapshot taken by the key pass, moved back in sorted order by the rank pass
     double* pos2[3];
     double* vel2[3];
     double* rho2;
@@ -152,7 +152,7 @@ struct DevArrays {
     // binning
     uint32_t* key;
     int32_t* rank;
-    int32_t* perm;
+    int32_t* perm;  // caller-order slot of each sorted slot (read back for the binning check)
     int32_t* tmp;   // slots in arrival order within each cell
     int32_t* cell_cnt;
     int32_t* cell_start;  // C + 1

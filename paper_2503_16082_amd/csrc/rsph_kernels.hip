@@ -365,7 +365,7 @@ __device__ __forceinline__ bool substep_on(const SysDyn& D, int mode)
 
 // ---------------------------------------------------------------------------
 // binning: cell key, counting sort (histogram, scan, scatter), ordering of
-// each cell by the caller's particle index, gather of the state
+// each cell by the caller's particle index, move of the state into that order
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* p, int64_t n, int32_t v)
@@ -392,7 +392,7 @@ __device__ __forceinline__ int cycle_state(const SysDyn& D)
 
 // Cell key of every particle of a stepping system, its rank among the
 // particles of its cell in atomic order, and a snapshot of the state into the
-// second buffer, from which the gather then permutes it back.
+// second buffer, from which the rank pass then moves it into sorted order.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
 {
@@ -510,39 +510,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(int32_t* in, int64_t n, c
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = ex;
 }
 
-// exclusive scan of at most kScanSmall counts by one block, which clears them
-constexpr int kScanSmallThreads = 1024;
-constexpr int kScanSmall = kScanSmallThreads * kScanItems;
-__global__ __launch_bounds__(kScanSmallThreads) void k_scan_small(int32_t* in, int64_t n, int32_t* out)
-{
-    __shared__ int lds[kScanSmallThreads / kWave];
-    const int64_t base = (int64_t)threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t idx = base + k;
-        v[k] = idx < n ? in[idx] : 0;
-        if (idx < n) in[idx] = 0;
-        s += v[k];
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int x = s;
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) lds[wv] = x;
-    __syncthreads();
-    int ex = x - s;
-    for (int k = 0; k < wv; ++k) ex += lds[k];
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t idx = base + k;
-        if (idx < n) out[idx] = ex;
-        ex += v[k];
-    }
-    if (threadIdx.x == kScanSmallThreads - 1) out[n] = ex;
-}
-
 // scatter in arrival order (the cell-relative rank of the histogram atomics)
 __global__ __launch_bounds__(kBlock) void k_scatter(DevArrays A)
 {
@@ -555,54 +522,93 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevArrays A)
     A.tmp[dest] = (int32_t)c.i;
 }
 
-// Final, canonical order: within its cell a particle's rank is the number of
-// cell members with a smaller caller index (ids are unique), so the sorted
-// order is (cell, id) whatever order the atomics produced.
-__global__ __launch_bounds__(kBlock) void k_rank(DevArrays A)
+// Grids of at most kScanSmall cells: every block of the scatter scans all the
+// cell counts in LDS itself, in place of a scan pass; block 0 stores the cell
+// starts for the passes that follow, and the rank pass clears the counts.
+constexpr int kScanSmall = 8192;
+constexpr int kScanSmallItems = kScanSmall / kBlock;
+__global__ __launch_bounds__(kBlock) void k_scatter_small(DevArrays A, int64_t n)
 {
-    Slot c = slot_of(A);
-    if (!c.lane) return;
-    if (!A.sd[c.s].stepping) return;
+    __shared__ int32_t st[kScanSmall + 1];
+    __shared__ int lds[kBlock / kWave];
+    // the slot's own loads first, so that their latency overlaps the scan
+    const Slot c = slot_of(A);
+    uint32_t key = 0;
+    int32_t rk = 0;
+    bool on = c.lane && A.sd[c.s].stepping;
+    if (on) {
+        key = A.key[c.i];
+        rk = A.rank[c.i];
+    }
+    const int64_t base = (int64_t)threadIdx.x * kScanSmallItems;
+    int v[kScanSmallItems];
+    int sum = 0;
+    for (int k = 0; k < kScanSmallItems; ++k) {
+        const int64_t idx = base + k;
+        v[k] = idx < n ? A.cell_cnt[idx] : 0;
+        sum += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(sum, lds, total);
+    for (int k = 0; k < kScanSmallItems; ++k) {
+        const int64_t idx = base + k;
+        if (idx < n) st[idx] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) st[n] = total;
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int64_t k = threadIdx.x; k <= n; k += kBlock) A.cell_start[k] = st[k];
+    if (!on) return;
     const SysConst& S = A.sc[c.s];
-    const uint32_t key = A.key[c.i];
-    const int64_t base = S.p_off - A.cell_start[S.c_off];
-    const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
-    const int32_t me = A.id2[c.i];
-    int r = 0;
-    for (int64_t k = b; k < e; ++k) r += A.id2[A.tmp[k]] < me;
-    A.perm[b + r] = (int32_t)c.i;
+    const int64_t dest = S.p_off + (st[S.c_off + key] - st[S.c_off]) + rk;
+    A.tmp[dest] = (int32_t)c.i;
 }
 
-// state gather from the snapshot into the primary arrays, in sorted order,
-// plus the packed positions and the per-fluid |v| max for the advection time
-// step
+// Final, canonical order: within its cell a particle's rank is the number of
+// cell members with a smaller caller index (ids are unique), so the sorted
+// order is (cell, id) whatever order the atomics produced.  Each particle then
+// moves its state from the snapshot into its sorted slot of the primary arrays
+// and writes its packed position record; the per-fluid |v| maxima of each 64
+// source slots go to the partials of the advection time step.  On grids
+// scanned inside the scatter this pass clears the cell counts (clear_n cells).
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_gather(DevArrays A)
+__global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
 {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < clear_n; k += (int64_t)gridDim.x * kBlock)
+        A.cell_cnt[k] = 0;
     Slot c = slot_of(A);
     if (c.s < 0) return;
     if (!A.sd[c.s].stepping) return;  // wave-uniform
     unsigned long long m0 = 0, m1 = 0;
     if (c.lane) {
-        const int64_t src = A.perm[c.i];
-        double v2 = 0.0;
+        const int64_t i = c.i;
+        const SysConst& S = A.sc[c.s];
+        const uint32_t key = A.key[i];
+        const int64_t base = S.p_off - A.cell_start[S.c_off];
+        const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
+        const int32_t me = A.id2[i];
+        int r = 0;
+        for (int64_t k = b; k < e; ++k) r += A.id2[A.tmp[k]] < me;
+        const int64_t d = b + r;
+        A.perm[d] = (int32_t)i;
         double x[3] = {0.0, 0.0, 0.0};
+        double v2 = 0.0;
         for (int a = 0; a < D; ++a) {
-            x[a] = A.pos2[a][src];
-            A.pos[a][c.i] = x[a];
-            double v = A.vel2[a][src];
-            A.vel[a][c.i] = v;
+            x[a] = A.pos2[a][i];
+            A.pos[a][d] = x[a];
+            const double v = A.vel2[a][i];
+            A.vel[a][d] = v;
             v2 += v * v;
         }
-        // one 32-byte position record per slot, read by the neighbour pass
-        ((double4*)A.xd)[c.i] = double4{x[0], x[1], x[2], 0.0};
-        A.rho[c.i] = A.rho2[src];
-        A.drho[c.i] = A.drho2[src];
-        A.mass[c.i] = A.mass2[src];
-        A.id[c.i] = A.id2[src];
-        const int ph = A.phase2[src];
-        A.phase[c.i] = ph;
-        unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
+        ((double4*)A.xd)[d] = double4{x[0], x[1], x[2], 0.0};
+        A.rho[d] = A.rho2[i];
+        A.drho[d] = A.drho2[i];
+        A.mass[d] = A.mass2[i];
+        A.id[d] = me;
+        const int ph = A.phase2[i];
+        A.phase[d] = ph;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
         if (ph == 0) m0 = bits;
         else m1 = bits;
     }
@@ -854,7 +860,9 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
 {
     double wsum = 0.0;
     int coincident = 0, close = 0;
-    for_neighbours<G, Chunk<R, D>::N>(
+    // in 2D every lane's few entries are gathered at once
+    constexpr int CH = D == 2 ? 4 : Chunk<R, D>::N;
+    for_neighbours<G, CH>(
         A, i, g, live ? cnt : 0,
         [&](uint32_t j) {
             const double4 q = ((const double4*)A.xd)[j];  // one 32-byte record per neighbour
@@ -2031,15 +2039,15 @@ void launch_set_targets(const Launch& L, const DevArrays& A, const long long* ta
 void launch_bin(const Launch& L, const DevArrays& A, int64_t group)
 {
     // the cell counts are zero on entry: cleared when the arrays are
-    // allocated and by every scan that consumes them
+    // allocated and by every binning after the scan has consumed them
     const int64_t ncells = A.C;
     if (L.dim == 2)
         hipLaunchKernelGGL(k_key<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, group);
     else
         hipLaunchKernelGGL(k_key<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, group);
-    if (ncells <= kScanSmall) {
-        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanSmallThreads), 0, L.stream, A.cell_cnt, ncells,
-                           A.cell_start);
+    const bool small = ncells <= kScanSmall;
+    if (small) {
+        hipLaunchKernelGGL(k_scatter_small, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, ncells);
     } else {
         const int64_t ntiles = (ncells + kScanTile - 1) / kScanTile;
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
@@ -2047,13 +2055,13 @@ void launch_bin(const Launch& L, const DevArrays& A, int64_t group)
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, L.stream, A.scan_part, ntiles);
         hipLaunchKernelGGL(k_scan_final, dim3((unsigned)ntiles), dim3(kBlock), 0, L.stream, A.cell_cnt,
                            ncells, A.scan_part, A.cell_start);
+        hipLaunchKernelGGL(k_scatter, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
     }
-    hipLaunchKernelGGL(k_scatter, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
-    hipLaunchKernelGGL(k_rank, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+    const int64_t clear_n = small ? ncells : 0;
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_gather<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+        hipLaunchKernelGGL(k_rank<2>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, clear_n);
     else
-        hipLaunchKernelGGL(k_gather<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A);
+        hipLaunchKernelGGL(k_rank<3>, slot_grid(A.P), dim3(kBlock), 0, L.stream, A, clear_n);
 }
 
 #define RSPH_DISPATCH(KERNEL, LANES2, LANES3, EV, ...)                                                 \
