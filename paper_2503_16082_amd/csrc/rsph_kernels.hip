@@ -1066,7 +1066,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     if (!Dy.stepping) return;  // block-uniform
     const SysConst& S = A.sc[c.s];
     // the system's first block also sets the advection step (Eqs. 16, 18) from
-    // the per-wave |v| maxima of the gather; no pass of this kernel reads the
+    // the per-wave |v| maxima of the rank pass; no pass of this kernel reads the
     // fields it writes
     if (A.mode == 0 && logical_block() * (kBlock / G) == S.p_off) begin_advection_step(A, S, Dy);
     const int64_t i = c.i;
@@ -1293,7 +1293,7 @@ __global__ void k_set_targets(DevArrays A, const long long* targets)
 }
 
 // Per-fluid maxima of |v| over one system from its partials, one entry per
-// `slots_per_entry` slots (64 for the per-wave partials of the gather, 256 / G
+// `slots_per_entry` slots (64 for the per-wave partials of the rank pass, 256 / G
 // for the per-block partials of the force pass), as FP64 bit patterns: |v| is
 // non-negative, so their integer order is the numeric one, and a non-finite
 // |v| compares above every finite one.  Every thread of the 256-thread block
