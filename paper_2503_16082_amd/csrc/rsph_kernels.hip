@@ -272,6 +272,32 @@ template <typename R, int D>
 struct Chunk {
     static constexpr int N = D == 2 ? RSPH_CHUNK_2D : (sizeof(R) == 4 ? RSPH_CHUNK_3D : 2);
 };
+// per-pass choices in 2D (the advection pass takes 2 in both dimensions)
+#ifndef RSPH_CHUNK_2D_COLOUR
+#define RSPH_CHUNK_2D_COLOUR RSPH_CHUNK_2D
+#endif
+#ifndef RSPH_CHUNK_2D_FORCE
+#define RSPH_CHUNK_2D_FORCE RSPH_CHUNK_2D
+#endif
+#ifndef RSPH_CHUNK_2D_CONTINUITY
+#define RSPH_CHUNK_2D_CONTINUITY RSPH_CHUNK_2D
+#endif
+#ifndef RSPH_CHUNK_2D_SHIFT
+#define RSPH_CHUNK_2D_SHIFT RSPH_CHUNK_2D
+#endif
+#ifndef RSPH_CHUNK_2D_ADVECTION
+#define RSPH_CHUNK_2D_ADVECTION 2
+#endif
+enum class Pass { Colour, Force, Continuity, Shift, Advection };
+template <typename R, int D, Pass P>
+struct PassChunk {
+    static constexpr int N2 = P == Pass::Colour       ? RSPH_CHUNK_2D_COLOUR
+                              : P == Pass::Force      ? RSPH_CHUNK_2D_FORCE
+                              : P == Pass::Continuity ? RSPH_CHUNK_2D_CONTINUITY
+                              : P == Pass::Shift      ? RSPH_CHUNK_2D_SHIFT
+                                                      : RSPH_CHUNK_2D_ADVECTION;
+    static constexpr int N = D == 2 ? N2 : (P == Pass::Advection ? 2 : Chunk<R, D>::N);
+};
 // at least 4 lanes: a 256-thread block then covers at most 64 slots, i.e. lies
 // inside one system, which the per-block partial maxima rely on
 static_assert(RSPH_LANES_2D >= 4 && RSPH_LANES_3D >= 4, "lanes per slot");
@@ -627,9 +653,10 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
 // ---------------------------------------------------------------------------
 
 // Neighbour lists.  The candidates of one block's particles are staged in LDS:
-// the block's 64 slots lie in a few consecutive cells, so the union of their
-// 3^d stencils is a small box of cells whose particles are copied once per
-// block as FP32 offsets from their own cell corner.  A candidate is tested in
+// the block's 64 slots lie in a few consecutive cells of one or two cell rows,
+// so the union of their 3^d stencils is at most two small boxes of cells whose
+// particles are copied once per block as FP32 offsets from their own cell
+// corner.  A candidate is tested in
 // FP32 on these split positions.  Candidates within a relative 1e-5 of the
 // cut-off (2h)^2 are decided on the spot by the exact FP64 predicate on the
 // stored positions, so the neighbour set is exactly the one of the FP64
@@ -642,14 +669,20 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
 constexpr int kStageCells = 128;
 constexpr int kStageCap = 2304;
 
+// The union is kept as two boxes: one for the particles in the cell row
+// (y, z) of the block's first particle, one for the rest.  A block that runs
+// from the end of one row into the start of the next thus stages two compact
+// boxes instead of one box as wide as the grid.
 struct Stage {
     // x, y, z offsets from the candidate's own cell corner; w holds the bits
-    // of (union-local x cell << 1) | phase
+    // of (box-local x cell << 1) | phase
     float4 q[kStageCap];
-    int32_t off[kStageCells + 1];  // LDS offset of each union cell
+    int32_t off[kStageCells + 1];  // LDS offset of each union cell (box 0's cells, then box 1's)
     int32_t gs[kStageCells];       // first global slot of each union cell
-    int32_t lo[3], hi[3];          // cell-coordinate bounds of the block's particles
-    int32_t dims[3];               // union box extent (cells)
+    int32_t lo[2][3], hi[2][3];    // per box: cell-coordinate bounds of its particles
+    int32_t dims[2][3];            // per box: extent (cells)
+    int32_t ubase[2];              // per box: its first union cell
+    int32_t row0;                  // cell row y + ny z of the block's first particle
     int32_t ok;
     int32_t wsum[kBlock / kWave];
 };
@@ -681,32 +714,45 @@ __device__ __forceinline__ double image_offset(const SysConst& S, int c, int a)
 }
 
 template <int D>
-__device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& S, Stage& L,
-                                            int64_t base, bool live, const int* ci, int g)
+__device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S, Stage& L, int64_t base,
+                                           bool live, const int* ci, int g)
 {
     const int t = threadIdx.x;
-    if (t < 3) {
-        L.lo[t] = 0x7fffffff;
-        L.hi[t] = -0x7fffffff;
+    if (t < 6) {
+        L.lo[t / 3][t % 3] = 0x7fffffff;
+        L.hi[t / 3][t % 3] = -0x7fffffff;
     }
+    if (t == 0) L.row0 = 0x7fffffff;
     __syncthreads();
+    const int row = ci[1] + S.ncell[1] * ci[2];
+    if (live && g == 0) atomicMin(&L.row0, row);
+    __syncthreads();
+    const int box = row != L.row0;
     if (live && g == 0)
         for (int a = 0; a < D; ++a) {
-            atomicMin(&L.lo[a], ci[a]);
-            atomicMax(&L.hi[a], ci[a]);
+            atomicMin(&L.lo[box][a], ci[a]);
+            atomicMax(&L.hi[box][a], ci[a]);
         }
     __syncthreads();
-    const int ux = L.hi[0] - L.lo[0] + 3, uy = L.hi[1] - L.lo[1] + 3;
-    const int uz = D == 3 ? L.hi[2] - L.lo[2] + 3 : 1;
-    const int ncu = ux * uy * uz;
-    const bool fits_cells = L.hi[0] >= L.lo[0] && ncu <= kStageCells;
+    int ux[2], uy[2], uz[2], nb[2];
+    for (int q = 0; q < 2; ++q) {
+        const bool used = L.hi[q][0] >= L.lo[q][0];
+        ux[q] = used ? L.hi[q][0] - L.lo[q][0] + 3 : 0;
+        uy[q] = used ? L.hi[q][1] - L.lo[q][1] + 3 : 0;
+        uz[q] = used ? (D == 3 ? L.hi[q][2] - L.lo[q][2] + 3 : 1) : 0;
+        nb[q] = ux[q] * uy[q] * uz[q];
+    }
+    const int ncu = nb[0] + nb[1];
+    const bool fits_cells = nb[0] > 0 && ncu <= kStageCells;
     // per union cell: count and first slot (one thread per cell), then offsets
     int cnt = 0, gs = 0;
     if (fits_cells && t < ncu) {
-        const int lx = t % ux, ly = (t / ux) % uy, lz = t / (ux * uy);
-        const int cx = wrap_cell(L.lo[0] - 1 + lx, S.ncell[0]);
-        const int cy = wrap_cell(L.lo[1] - 1 + ly, S.ncell[1]);
-        const int cz = D == 3 ? wrap_cell(L.lo[2] - 1 + lz, S.ncell[2]) : 0;
+        const int q = t >= nb[0];
+        const int u = t - (q ? nb[0] : 0);
+        const int lx = u % ux[q], ly = (u / ux[q]) % uy[q], lz = u / (ux[q] * uy[q]);
+        const int cx = wrap_cell(L.lo[q][0] - 1 + lx, S.ncell[0]);
+        const int cy = wrap_cell(L.lo[q][1] - 1 + ly, S.ncell[1]);
+        const int cz = D == 3 ? wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]) : 0;
         const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
         const int a0 = A.cell_start[gc];
         cnt = A.cell_start[gc + 1] - a0;
@@ -729,13 +775,17 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
     if (t == 0) {
         const int total = L.wsum[0] + L.wsum[1];
         L.ok = fits_cells && total <= kStageCap;
-        L.dims[0] = ux;
-        L.dims[1] = uy;
-        L.dims[2] = uz;
+        for (int q = 0; q < 2; ++q) {
+            L.dims[q][0] = ux[q];
+            L.dims[q][1] = uy[q];
+            L.dims[q][2] = uz[q];
+        }
+        L.ubase[0] = 0;
+        L.ubase[1] = nb[0];
         if (fits_cells) L.off[ncu] = total;
     }
     __syncthreads();
-    if (!L.ok) return;  // block-uniform
+    if (!L.ok) return box;  // block-uniform
     const int total = L.off[ncu];
     for (int k = t; k < total; k += kBlock) {
         // union cell holding entry k: binary search over the offsets
@@ -745,24 +795,27 @@ __device__ __forceinline__ void stage_union(const DevArrays& A, const SysConst& 
             if (L.off[mid] <= k) lo = mid;
             else hi = mid;
         }
-        const int lx = lo % ux, ly = (lo / ux) % uy, lz = lo / (ux * uy);
-        const int cx = wrap_cell(L.lo[0] - 1 + lx, S.ncell[0]);
-        const int cy = wrap_cell(L.lo[1] - 1 + ly, S.ncell[1]);
+        const int q = lo >= nb[0];
+        const int u = lo - (q ? nb[0] : 0);
+        const int lx = u % ux[q], ly = (u / ux[q]) % uy[q], lz = u / (ux[q] * uy[q]);
+        const int cx = wrap_cell(L.lo[q][0] - 1 + lx, S.ncell[0]);
+        const int cy = wrap_cell(L.lo[q][1] - 1 + ly, S.ncell[1]);
         const int64_t j = L.gs[lo] + (k - L.off[lo]);
         double xj[3];
         load_pos<D>(A, j, xj);
-        float4 q;
-        q.x = (float)(xj[0] - (double)cx * S.cell[0]);
-        q.y = (float)(xj[1] - (double)cy * S.cell[1]);
-        q.z = 0.f;
+        float4 c4;
+        c4.x = (float)(xj[0] - (double)cx * S.cell[0]);
+        c4.y = (float)(xj[1] - (double)cy * S.cell[1]);
+        c4.z = 0.f;
         if (D == 3) {
-            const int cz = wrap_cell(L.lo[2] - 1 + lz, S.ncell[2]);
-            q.z = (float)(xj[2] - (double)cz * S.cell[2]);
+            const int cz = wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]);
+            c4.z = (float)(xj[2] - (double)cz * S.cell[2]);
         }
-        q.w = __int_as_float((lx << 1) | (A.phase[j] & 1));
-        L.q[k] = q;
+        c4.w = __int_as_float((lx << 1) | (A.phase[j] & 1));
+        L.q[k] = c4;
     }
     __syncthreads();
+    return box;
 }
 
 // exact neighbour predicate: x_i - x_j, minus the periodic image offset of the
@@ -939,7 +992,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
         }
         ph = A.phase[i];
     }
-    stage_union<D>(A, S, L, base, live, ci, g);
+    const int box = stage_union<D>(A, S, L, base, live, ci, g);
     int cnt = 0;
     int cross = 0;
     uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
@@ -951,8 +1004,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
         }
         const float cut_hi = (float)(S.cut2 * (1.0 + 1e-5)), cut_lo = (float)(S.cut2 * (1.0 - 1e-5));
         const int i32 = (int)i;
-        // the particle's union-local cell
-        const int lx = ci[0] - L.lo[0] + 1, ly = ci[1] - L.lo[1] + 1, lz = D == 3 ? ci[2] - L.lo[2] + 1 : 0;
+        // the particle's cell, local to its box
+        const int lx = ci[0] - L.lo[box][0] + 1, ly = ci[1] - L.lo[box][1] + 1;
+        const int lz = D == 3 ? ci[2] - L.lo[box][2] + 1 : 0;
         const int zr = D == 3 ? 1 : 0;
         for (int dz = -zr; dz <= zr; ++dz) {
             const float rz0 = oi[2] - (float)dz * cellf[2];
@@ -964,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                 int u0 = 0, rb = 0, re = 0;
                 bool contiguous = true;
                 if (live) {
-                    u0 = (lx - 1) + L.dims[0] * ((ly + dy) + L.dims[1] * (lz + dz));
+                    u0 = L.ubase[box] + (lx - 1) + L.dims[box][0] * ((ly + dy) + L.dims[box][1] * (lz + dz));
                     rb = L.off[u0];
                     re = L.off[u0 + 3];
                     contiguous = L.gs[u0 + 1] - L.gs[u0] == L.off[u0 + 1] - rb &&
@@ -1088,7 +1142,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     }
     const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
-    for_neighbours<G, 2>(
+    for_neighbours<G, PassChunk<R, D, Pass::Advection>::N>(
         A, i, g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
         [&](uint32_t j, const Recs<R, 2>& rj) {
             const Q4<R> gj = rj.q[0];
@@ -1213,7 +1267,7 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
         cnt = A.ncount[i];
     }
     R s[3] = {0, 0, 0};
-    for_neighbours<G, Chunk<R, D>::N>(
+    for_neighbours<G, PassChunk<R, D, Pass::Shift>::N>(
         A, i, g, cnt,
         [&](uint32_t j) {
             if constexpr (D == 3) return Recs<R, 3>{{geo[j], b0[j], b1[j]}};
@@ -1467,7 +1521,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     if (i >= A.P) return;
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
-    NbrList<G, Chunk<R, D>::N> nl;
+    NbrList<G, PassChunk<R, D, Pass::Colour>::N> nl;
     nl.start(A, i, g);
     const int fl = A.flags[i];
     const int cnt_i = A.ncount[i];
@@ -1536,7 +1590,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* col = (const Q4<R>*)A.col;
-    NbrList<G, Chunk<R, D>::N> nl;
+    NbrList<G, PassChunk<R, D, Pass::Force>::N> nl;
     nl.start(A, i, g);
     const int fl = A.flags[i];
     const int cnt_i = A.ncount[i];
@@ -1737,7 +1791,7 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
     if (i >= A.P) return;
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
-    NbrList<G, Chunk<R, D>::N> nl;
+    NbrList<G, PassChunk<R, D, Pass::Continuity>::N> nl;
     nl.start(A, i, g);
     const int cnt_i = A.ncount[i];
     const Q4<R> gi_i = geo[i];
