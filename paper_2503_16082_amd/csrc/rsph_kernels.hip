@@ -422,7 +422,17 @@ __device__ __forceinline__ int cycle_state(const SysDyn& D)
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
 {
-    Slot c = slot_of(A);
+    const int64_t i = logical_block() * kBlock + threadIdx.x;
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
+    double x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) {
+        x[a] = A.pos[a][i];
+        v[a] = A.vel[a][i];
+    }
+    const double rho = A.rho[i], drho = A.drho[i], mass = A.mass[i];
+    const int32_t id = A.id[i], phase = A.phase[i];
+    const Slot c = lookup_slot(A, i);
     if (!c.lane) return;
     SysDyn& Dy = A.sd[c.s];
     const SysConst& S = A.sc[c.s];
@@ -437,21 +447,20 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
     } else if (!Dy.stepping) {
         return;
     }
-    const int64_t i = c.i;
     int ck[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) {
-        double x = A.pos[a][i];
-        if (x < 0.0) x = __dadd_rn(x, S.box[a]);
-        if (x >= S.box[a]) x = __dsub_rn(x, S.box[a]);
-        A.pos2[a][i] = x;
-        A.vel2[a][i] = A.vel[a][i];
-        ck[a] = cell_of(x, S, a);
+        double xa = x[a];
+        if (xa < 0.0) xa = __dadd_rn(xa, S.box[a]);
+        if (xa >= S.box[a]) xa = __dsub_rn(xa, S.box[a]);
+        A.pos2[a][i] = xa;
+        A.vel2[a][i] = v[a];
+        ck[a] = cell_of(xa, S, a);
     }
-    A.rho2[i] = A.rho[i];
-    A.drho2[i] = A.drho[i];
-    A.mass2[i] = A.mass[i];
-    A.id2[i] = A.id[i];
-    A.phase2[i] = A.phase[i];
+    A.rho2[i] = rho;
+    A.drho2[i] = drho;
+    A.mass2[i] = mass;
+    A.id2[i] = id;
+    A.phase2[i] = phase;
     uint32_t key = (uint32_t)(ck[0] + S.ncell[0] * (ck[1] + S.ncell[1] * ck[2]));
     A.key[i] = key;
     A.rank[i] = atomicAdd(&A.cell_cnt[S.c_off + key], 1);
@@ -603,36 +612,41 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
 {
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < clear_n; k += (int64_t)gridDim.x * kBlock)
         A.cell_cnt[k] = 0;
-    Slot c = slot_of(A);
+    const int64_t i = logical_block() * kBlock + threadIdx.x;
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
+    const uint32_t key = A.key[i];
+    const int32_t me = A.id2[i];
+    double x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) {
+        x[a] = A.pos2[a][i];
+        v[a] = A.vel2[a][i];
+    }
+    const double rho = A.rho2[i], drho = A.drho2[i], mass = A.mass2[i];
+    const int ph = A.phase2[i];
+    const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     if (!A.sd[c.s].stepping) return;  // wave-uniform
     unsigned long long m0 = 0, m1 = 0;
     if (c.lane) {
-        const int64_t i = c.i;
         const SysConst& S = A.sc[c.s];
-        const uint32_t key = A.key[i];
         const int64_t base = S.p_off - A.cell_start[S.c_off];
         const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
-        const int32_t me = A.id2[i];
         int r = 0;
         for (int64_t k = b; k < e; ++k) r += A.id2[A.tmp[k]] < me;
         const int64_t d = b + r;
         A.perm[d] = (int32_t)i;
-        double x[3] = {0.0, 0.0, 0.0};
         double v2 = 0.0;
         for (int a = 0; a < D; ++a) {
-            x[a] = A.pos2[a][i];
             A.pos[a][d] = x[a];
-            const double v = A.vel2[a][i];
-            A.vel[a][d] = v;
-            v2 += v * v;
+            A.vel[a][d] = v[a];
+            v2 += v[a] * v[a];
         }
         ((double4*)A.xd)[d] = double4{x[0], x[1], x[2], 0.0};
-        A.rho[d] = A.rho2[i];
-        A.drho[d] = A.drho2[i];
-        A.mass[d] = A.mass2[i];
+        A.rho[d] = rho;
+        A.drho[d] = drho;
+        A.mass[d] = mass;
         A.id[d] = me;
-        const int ph = A.phase2[i];
         A.phase[d] = ph;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
         if (ph == 0) m0 = bits;
@@ -944,12 +958,13 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
     const double sigma = S.w0 + wsum;
     const int ph = A.phase[i];
     double rho = A.rho[i];
+    const double mass = A.mass[i];
     if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
         rho = S.rho0[ph] * sigma / S.sigma0;
         A.rho[i] = rho;
     }
     if (A.mode == 1) A.r_sigma[i] = sigma;
-    V = A.mass[i] / rho;
+    V = mass / rho;
     const double p = S.c0sq * (rho - S.rho0[ph]);
     ((Q4<R>*)A.th[1])[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
     return true;
@@ -1114,7 +1129,17 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
-    Slot c = slot_of_group<G>(A, g);
+    const int64_t i = group_slot<G>(g);
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
+    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    const Q4<R>* th = (const Q4<R>*)A.th[1];
+    const Q4<R>* vb = (const Q4<R>*)A.vbuf[0];
+    NbrList<G, PassChunk<R, D, Pass::Advection>::N> nl;
+    nl.start(A, i, g);
+    const Q4<R> gi_i = geo[i], vi_i = vb[i];
+    const int cnt_i = A.ncount[i];
+    const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
     if (!Dy.stepping) return;  // block-uniform
@@ -1123,10 +1148,6 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     // the per-wave |v| maxima of the rank pass; no pass of this kernel reads the
     // fields it writes
     if (A.mode == 0 && logical_block() * (kBlock / G) == S.p_off) begin_advection_step(A, S, Dy);
-    const int64_t i = c.i;
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
-    const Q4<R>* th = (const Q4<R>*)A.th[1];
-    const Q4<R>* vb = (const Q4<R>*)A.vbuf[0];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     R av[3] = {0, 0, 0};
@@ -1135,15 +1156,15 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     Q4<R> gi{0, 0, 0, 0}, vi{0, 0, 0, 0};
     int cnt = 0, phi = 0;
     if (c.lane) {
-        gi = geo[i];
-        vi = vb[i];
+        gi = gi_i;
+        vi = vi_i;
         phi = Geo<R>::phase(gi);
-        cnt = A.ncount[i];
+        cnt = cnt_i;
     }
     const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
-    for_neighbours<G, PassChunk<R, D, Pass::Advection>::N>(
-        A, i, g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
+    nl.run(
+        g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
         [&](uint32_t j, const Recs<R, 2>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
@@ -1246,29 +1267,36 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
-    Slot c = slot_of_group<G>(A, g);
-    if (c.s < 0) return;
-    SysDyn& Dy = A.sd[c.s];
-    if (!Dy.stepping) return;
-    const SysConst& S = A.sc[c.s];
-    const int64_t i = c.i;
+    const int64_t i = group_slot<G>(g);
+    if (i >= A.P) return;
+    // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[1];
     const Q4<R>* b0 = (const Q4<R>*)A.bm[0];
     const Q4<R>* b1 = (const Q4<R>*)A.bm[1];
+    NbrList<G, PassChunk<R, D, Pass::Shift>::N> nl;
+    nl.start(A, i, g);
+    const Q4<R> gi_i = geo[i], b0_i = b0[i];
+    const Q4<R> b1_i = D == 3 ? b1[i] : Q4<R>{0, 0, 0, 0};
+    const int cnt_i = A.ncount[i];
+    const Slot c = lookup_slot(A, i);
+    if (c.s < 0) return;
+    SysDyn& Dy = A.sd[c.s];
+    if (!Dy.stepping) return;
+    const SysConst& S = A.sc[c.s];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     Q4<R> gi{0, 0, 0, 0}, Bi0{0, 0, 0, 0}, Bi1{0, 0, 0, 0};
     int cnt = 0;
     if (c.lane) {
-        gi = geo[i];
-        Bi0 = b0[i];
-        Bi1 = b1[i];
-        cnt = A.ncount[i];
+        gi = gi_i;
+        Bi0 = b0_i;
+        Bi1 = b1_i;
+        cnt = cnt_i;
     }
     R s[3] = {0, 0, 0};
-    for_neighbours<G, PassChunk<R, D, Pass::Shift>::N>(
-        A, i, g, cnt,
+    nl.run(
+        g, cnt,
         [&](uint32_t j) {
             if constexpr (D == 3) return Recs<R, 3>{{geo[j], b0[j], b1[j]}};
             else return Recs<R, 2>{{geo[j], b0[j]}};
