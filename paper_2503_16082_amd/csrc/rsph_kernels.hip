@@ -1374,35 +1374,38 @@ __global__ void k_set_targets(DevArrays A, const long long* targets)
     if (s < A.nsys && targets[s] >= 0) A.sd[s].target = targets[s];
 }
 
-// Per-fluid maxima of |v| over one system from its partials, one entry per
-// `slots_per_entry` slots (64 for the per-wave partials of the rank pass, 256 / G
-// for the per-block partials of the force pass), as FP64 bit patterns: |v| is
-// non-negative, so their integer order is the numeric one, and a non-finite
-// |v| compares above every finite one.  Every thread of the 256-thread block
-// takes part and gets the result; U partials per thread are in flight at a
-// time.
+// U partials per thread: entries e0 + t + u * 256 of the system's range
 template <int U>
-__device__ __forceinline__ void reduce_vmax_bits(const DevArrays& A, const SysConst& S, int64_t slots_per_entry,
-                                                 unsigned long long* m)
+struct VParts {
+    ulonglong2 v[U];
+};
+
+template <int U>
+__device__ __forceinline__ void vmax_load(const DevArrays& A, int64_t e, int64_t e1, VParts<U>& p)
+{
+    const ulonglong2* vp = (const ulonglong2*)A.vpart;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = e + (int64_t)u * kBlock;
+        p.v[u] = k < e1 ? vp[k] : make_ulonglong2(0ull, 0ull);
+    }
+}
+
+template <int U>
+__device__ __forceinline__ void vmax_fold(const VParts<U>& p, unsigned long long& m0, unsigned long long& m1)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        m0 = p.v[u].x > m0 ? p.v[u].x : m0;
+        m1 = p.v[u].y > m1 ? p.v[u].y : m1;
+    }
+}
+
+// block maximum of the threads' values; identical in every lane, so held in
+// scalar registers
+__device__ __forceinline__ void vmax_block(unsigned long long m0, unsigned long long m1, unsigned long long* m)
 {
     __shared__ unsigned long long red[2 * (kBlock / kWave)];
-    const int64_t e0 = S.p_off / slots_per_entry;
-    const int64_t e1 = (S.p_off + ((S.p_n + kWave - 1) / kWave) * kWave) / slots_per_entry;
-    const ulonglong2* vp = (const ulonglong2*)A.vpart;
-    unsigned long long m0 = 0, m1 = 0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += U * kBlock) {
-        ulonglong2 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t k = e + (int64_t)u * kBlock;
-            v[u] = k < e1 ? vp[k] : make_ulonglong2(0ull, 0ull);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            m0 = v[u].x > m0 ? v[u].x : m0;
-            m1 = v[u].y > m1 ? v[u].y : m1;
-        }
-    }
     m0 = wave_max_u64(m0);
     m1 = wave_max_u64(m1);
     const int wv = threadIdx.x >> 6;
@@ -1415,11 +1418,39 @@ __device__ __forceinline__ void reduce_vmax_bits(const DevArrays& A, const SysCo
         m0 = red[2 * k] > m0 ? red[2 * k] : m0;
         m1 = red[2 * k + 1] > m1 ? red[2 * k + 1] : m1;
     }
-    // identical in every lane: held in scalar registers
     m[0] = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(m0 >> 32)) << 32) |
            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m0);
     m[1] = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(m1 >> 32)) << 32) |
            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m1);
+}
+
+// first and one-past-last partial entry of a system
+__device__ __forceinline__ void vmax_range(const SysConst& S, int64_t slots_per_entry, int64_t& e0, int64_t& e1)
+{
+    e0 = S.p_off / slots_per_entry;
+    e1 = (S.p_off + ((S.p_n + kWave - 1) / kWave) * kWave) / slots_per_entry;
+}
+
+// Per-fluid maxima of |v| over one system from its partials, one entry per
+// `slots_per_entry` slots (64 for the per-wave partials of the rank pass, 256 / G
+// for the per-block partials of the force pass), as FP64 bit patterns: |v| is
+// non-negative, so their integer order is the numeric one, and a non-finite
+// |v| compares above every finite one.  Every thread of the 256-thread block
+// takes part and gets the result; U partials per thread are in flight at a
+// time.
+template <int U>
+__device__ __forceinline__ void reduce_vmax_bits(const DevArrays& A, const SysConst& S, int64_t slots_per_entry,
+                                                 unsigned long long* m)
+{
+    int64_t e0, e1;
+    vmax_range(S, slots_per_entry, e0, e1);
+    unsigned long long m0 = 0, m1 = 0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += U * kBlock) {
+        VParts<U> p;
+        vmax_load<U>(A, e, e1, p);
+        vmax_fold<U>(p, m0, m1);
+    }
+    vmax_block(m0, m1, m);
 }
 
 template <int U>
@@ -1839,6 +1870,11 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
     int st = kSubstepping;
     const bool fused = A.mode == 0 && S.fuse_dt;
     unsigned long long vbits[2] = {0ull, 0ull};
+    // a fused system's partials: at most 4 per thread, which 2D loads before
+    // the pair sum and folds after it (3D reduces them at once: its pair sum
+    // has no registers to spare)
+    static_assert(kFuseDtEntries <= 4 * kBlock, "partials of a fused system");
+    VParts<4> vp;
     if (A.mode == 1) {
         if (!Dy.stepping) return;
     } else if (fused) {
@@ -1847,7 +1883,13 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         // (after the pair sum below), so all blocks decide alike.
         if (Dy.sub_state != kSubstepping) return;  // block-uniform
         kk = Dy.sub_ksub;
-        reduce_vmax_bits<4>(A, S, kBlock / G, vbits);
+        if constexpr (D == 2) {
+            int64_t e0, e1;
+            vmax_range(S, kBlock / G, e0, e1);
+            vmax_load<4>(A, e0 + threadIdx.x, e1, vp);
+        } else {
+            reduce_vmax_bits<4>(A, S, kBlock / G, vbits);
+        }
     } else {
         // the substep pass has ended the substep (and advanced ksub)
         st = Dy.state;
@@ -1892,6 +1934,11 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
     double dt2 = 0.0;
     bool next = st == kSubstepping;
     if (fused) {
+        if constexpr (D == 2) {
+            unsigned long long m0 = 0, m1 = 0;
+            vmax_fold<4>(vp, m0, m1);
+            vmax_block(m0, m1, vbits);
+        }
         const double vmax[2] = {__longlong_as_double((long long)vbits[0]),
                                 __longlong_as_double((long long)vbits[1])};
         const SubstepEnd e = end_substep(S, Dy.dt_ad, Dy.sub_tau, dt, Dy.sub_health, vmax);
