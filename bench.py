@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -315,9 +316,16 @@ def served(args):
     descs = WL.served_mix(n_jobs=args.jobs, seed=0)
     budget = int(args.budget_gb * (1 << 30))
     probe = descs[:args.probe_jobs]
-    ps = serve.serve(probe, steps_per_job=args.probe_steps, rate_hz=None, budget_bytes=budget, precision=prec)
-    rate_sat = ps["jobs"] / ps["wall_s"] * args.probe_steps / args.steps_per_job
-    log(f"probe: {ps['jobs']} jobs x {args.probe_steps} steps in {ps['wall_s']:.2f}s -> saturated "
+    # probe jobs as long as the stream's: admission costs (pool repack, graph
+    # capture) then weigh as much per step as in the stream.  The saturated
+    # job rate is the probe's particle-step rate over the stream's mean work
+    # per job, so that the probe's own job sizes do not set it.
+    probe_steps = args.probe_steps or args.steps_per_job
+    ps = serve.serve(probe, steps_per_job=probe_steps, rate_hz=None, budget_bytes=budget, precision=prec)
+    n_side = [max(3, int(round(math.sqrt(d["n"])))) for d in descs]
+    work_per_job = float(np.mean([k * k for k in n_side])) * args.steps_per_job
+    rate_sat = ps["particle_steps_per_s"] / work_per_job
+    log(f"probe: {ps['jobs']} jobs x {probe_steps} steps in {ps['wall_s']:.2f}s -> saturated "
         f"{rate_sat:.3f} jobs/s at {args.steps_per_job} steps per job")
     rate = 0.8 * rate_sat
     out = serve.serve(descs, steps_per_job=args.steps_per_job, rate_hz=rate, budget_bytes=budget,
@@ -356,7 +364,8 @@ def main():
     ap.add_argument("--steps-per-job", type=int, default=200, help="served: advection steps per job")
     ap.add_argument("--budget-gb", type=float, default=0.5, help="served: pool HBM budget")
     ap.add_argument("--probe-jobs", type=int, default=24, help="served: jobs of the saturation probe")
-    ap.add_argument("--probe-steps", type=int, default=20, help="served: steps per probe job")
+    ap.add_argument("--probe-steps", type=int, default=None,
+                    help="served: steps per probe job (default: the stream's steps per job)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
