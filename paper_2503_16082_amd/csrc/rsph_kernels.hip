@@ -839,18 +839,22 @@ template <int D>
 __device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi, int64_t j, double kx,
                                            double ky, double kz)
 {
+    // plain operators with contraction off: one rounding per operation (the
+    // rounding-mode intrinsics alone do not keep the compiler from fusing a
+    // product into the following sum)
+#pragma clang fp contract(off)
     double xj[3];
     load_pos<D>(A, j, xj);
-    double d = __dsub_rn(xi[0], xj[0]);
-    if (kx != 0.0) d = __dsub_rn(d, kx);
-    double r2 = __dmul_rn(d, d);
-    d = __dsub_rn(xi[1], xj[1]);
-    if (ky != 0.0) d = __dsub_rn(d, ky);
-    r2 = __dadd_rn(r2, __dmul_rn(d, d));
+    double d = xi[0] - xj[0];
+    if (kx != 0.0) d = d - kx;
+    double r2 = d * d;
+    d = xi[1] - xj[1];
+    if (ky != 0.0) d = d - ky;
+    r2 = r2 + d * d;
     if (D == 3) {
-        d = __dsub_rn(xi[2], xj[2]);
-        if (kz != 0.0) d = __dsub_rn(d, kz);
-        r2 = __dadd_rn(r2, __dmul_rn(d, d));
+        d = xi[2] - xj[2];
+        if (kz != 0.0) d = d - kz;
+        r2 = r2 + d * d;
     }
     return r2;
 }

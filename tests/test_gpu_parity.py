@@ -125,6 +125,29 @@ def test_neighbour_sets_equal_brute_force(dim):
     s.close()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("with_lattice", [False, True])
+def test_neighbour_predicate_at_oblique_cut_off_pairs(dim, with_lattice):
+    """Pairs at (2h)^2 where a fused multiply-add would decide otherwise than
+    the plain sum, alone (blocks over many cell rows: the exact test of every
+    candidate) and inside a lattice (the FP32 test with the exact test of the
+    near-cut-off band): the GPU lists equal the oracle's brute force."""
+    import cutoff_pairs as CP
+    dp, pos, pp = CP.state(dim, 16, with_lattice, 3)
+    p = WL.base_params(dim, (1.0,) * dim, dp, (1.0, 1.0), (0.0, 0.0), 0.0, 1.0)
+    rng = np.random.default_rng(4)
+    phase = (rng.uniform(size=len(pos)) < 0.3).astype(np.int32)
+    say(f"cut-off pairs dim={dim} lattice={with_lattice} n={len(pos)}")
+    s = rsph.System(p)
+    s.set_particles(pos, np.zeros_like(pos), phase)
+    start, idx = s.neighbours()
+    bs, bi = O.neighbours_brute(p, pos, cap_per=400)
+    assert np.array_equal(start, bs)
+    for i in range(len(pos)):
+        assert np.array_equal(np.sort(idx[start[i]:start[i + 1]]), bi[bs[i]:bs[i + 1]])
+    s.close()
+
+
 # ---------------------------------------------------------------------------
 # single evaluations
 # ---------------------------------------------------------------------------

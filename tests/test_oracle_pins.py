@@ -137,6 +137,27 @@ def test_strict_cutoff_at_2h():
         assert (s[1] - s[0]) == (1 if d * d < (2 * h) ** 2 else 0)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_oblique_cut_off_pairs_follow_the_plain_sum(dim):
+    """Pairs whose squared distance, summed with one rounding per operation,
+    lies on the other side of (2h)^2 than a fused multiply-add evaluation: the
+    oracle's predicate follows the plain sum for every one of them."""
+    import cutoff_pairs as CP
+    dp = 1.0 / 16
+    pp = CP.pairs(dim, dp, 12, 0)
+    assert len(pp) == 12
+    p = WL.base_params(dim, (1.0,) * dim, dp, (1.0, 1.0), (0.0, 0.0), 0.0, 1.0)
+    cut2 = CP.cut2_of(dp)
+    inside = 0
+    for a, b in pp:
+        plain = CP.r2_plain(a - b) < cut2
+        assert any((f < cut2) != plain for f in CP.r2_fused(a - b))
+        s, _ = O.neighbours_brute(p, np.array([a, b]))
+        assert s[1] - s[0] == int(plain)
+        inside += plain
+    assert 0 < inside < 12  # both sides of the cut-off occur
+
+
 def test_binning_is_stable_counting_sort():
     p, pos = _hard_positions(2, 3)
     key = O.cell_keys(p, pos)
