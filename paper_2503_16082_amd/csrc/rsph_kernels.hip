@@ -62,12 +62,6 @@ __device__ __forceinline__ Slot slot_of(const DevArrays& A)
     return c;
 }
 
-__device__ __forceinline__ uint32_t nbr_at(const DevArrays& A, int64_t i, int k)
-{
-    const int64_t w = i >> 6;
-    return A.nbr[(w * A.kmax + k) * kWave + (i & 63)];
-}
-
 // Iterates lane g of particle i's group over list entries g, g + G, ... in
 // order.  Entries are taken CH at a time: the CH indices are loaded together,
 // then the neighbour records of all CH (load(j)), then body(j, record) runs
