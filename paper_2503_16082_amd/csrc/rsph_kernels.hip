@@ -411,8 +411,9 @@ __device__ __forceinline__ int cycle_state(const SysDyn& D)
 }
 
 // Cell key of every particle of a stepping system, its rank among the
-// particles of its cell in atomic order, and a snapshot of the state into the
-// second buffer, from which the rank pass then moves it into sorted order.
+// particles of its cell in atomic order (one atomic per run of equal cells in
+// a wave), and a snapshot of the state into the second buffer, from which the
+// rank pass then moves it into sorted order.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
 {
@@ -427,12 +428,14 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
     const double rho = A.rho[i], drho = A.drho[i], mass = A.mass[i];
     const int32_t id = A.id[i], phase = A.phase[i];
     const Slot c = lookup_slot(A, i);
-    if (!c.lane) return;
+    if (c.s < 0) return;  // wave-uniform: a wave lies in one system or in none
     SysDyn& Dy = A.sd[c.s];
     const SysConst& S = A.sc[c.s];
+    // the system's state is the same for the whole wave, so these returns are
+    // too; the wave's padding slots stay to the end (the shuffles below)
     if (A.mode == 0) {
         const int st = cycle_state(Dy);
-        if (c.i == S.p_off) {
+        if (c.lane && c.i == S.p_off) {
             Dy.state = st;
             Dy.stepping = st == kBoundary;
             if (st == kBoundary && A.work) atomicOr(A.work + group, 1);
@@ -441,23 +444,46 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
     } else if (!Dy.stepping) {
         return;
     }
-    int ck[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) {
-        double xa = x[a];
-        if (xa < 0.0) xa = __dadd_rn(xa, S.box[a]);
-        if (xa >= S.box[a]) xa = __dsub_rn(xa, S.box[a]);
-        A.pos2[a][i] = xa;
-        A.vel2[a][i] = v[a];
-        ck[a] = cell_of(xa, S, a);
+    const bool on = c.lane;
+    uint32_t gkey = 0xffffffffu;  // global cell of the particle; none for padding
+    if (on) {
+        int ck[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+            double xa = x[a];
+            if (xa < 0.0) xa = __dadd_rn(xa, S.box[a]);
+            if (xa >= S.box[a]) xa = __dsub_rn(xa, S.box[a]);
+            A.pos2[a][i] = xa;
+            A.vel2[a][i] = v[a];
+            ck[a] = cell_of(xa, S, a);
+        }
+        A.rho2[i] = rho;
+        A.drho2[i] = drho;
+        A.mass2[i] = mass;
+        A.id2[i] = id;
+        A.phase2[i] = phase;
+        const uint32_t key = (uint32_t)(ck[0] + S.ncell[0] * (ck[1] + S.ncell[1] * ck[2]));
+        A.key[i] = key;
+        gkey = (uint32_t)S.c_off + key;
     }
-    A.rho2[i] = rho;
-    A.drho2[i] = drho;
-    A.mass2[i] = mass;
-    A.id2[i] = id;
-    A.phase2[i] = phase;
-    uint32_t key = (uint32_t)(ck[0] + S.ncell[0] * (ck[1] + S.ncell[1] * ck[2]));
-    A.key[i] = key;
-    A.rank[i] = atomicAdd(&A.cell_cnt[S.c_off + key], 1);
+    // Ranks by runs: the slots are sorted by cell from the last binning, so
+    // neighbouring lanes mostly share a cell.  The first lane of each run of
+    // equal cells reserves the run's ranks with one atomic; every rank of a
+    // cell is still taken exactly once.
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(gkey, 1, 64);
+    const bool lead = on && (lane == 0 || prev != gkey);
+    const unsigned long long lm = __ballot(lead);
+    const unsigned long long bm = __ballot(lead || !on);  // run boundaries
+    int base = 0;
+    if (lead) {
+        const unsigned long long above = lane == 63 ? 0ull : bm & (~0ull << (lane + 1));
+        const int next = above ? __ffsll((long long)above) - 1 : 64;
+        base = atomicAdd(&A.cell_cnt[gkey], next - lane);
+    }
+    const unsigned long long upto = lm & (lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull));
+    const int ld = upto ? 63 - __clzll((long long)upto) : lane;
+    const int b = __shfl(base, ld, 64);
+    if (on) A.rank[i] = b + (lane - ld);
 }
 
 // exclusive scan of cell_cnt[0..n) into cell_start[0..n], three phases
