@@ -598,11 +598,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter_small(DevArrays A, int64_t n
     const int64_t base = (int64_t)threadIdx.x * kScanSmallItems;
     int v[kScanSmallItems];
     int sum = 0;
-    for (int k = 0; k < kScanSmallItems; ++k) {
+    // 16-byte loads where the thread's items lie below n (the counts are
+    // 256-byte aligned and base is a multiple of 32)
+    static_assert(kScanSmallItems % 4 == 0, "16-byte loads");
+    for (int k = 0; k < kScanSmallItems; k += 4) {
         const int64_t idx = base + k;
-        v[k] = idx < n ? A.cell_cnt[idx] : 0;
-        sum += v[k];
+        if (idx + 4 <= n) {
+            const int4 q = *(const int4*)(A.cell_cnt + idx);
+            v[k] = q.x;
+            v[k + 1] = q.y;
+            v[k + 2] = q.z;
+            v[k + 3] = q.w;
+        } else {
+            for (int u = 0; u < 4; ++u) v[k + u] = idx + u < n ? A.cell_cnt[idx + u] : 0;
+        }
     }
+    for (int k = 0; k < kScanSmallItems; ++k) sum += v[k];
     int total;
     int ex = block_exclusive_scan(sum, lds, total);
     for (int k = 0; k < kScanSmallItems; ++k) {
@@ -653,7 +664,13 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
         const int64_t base = S.p_off - A.cell_start[S.c_off];
         const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
         int r = 0;
-        for (int64_t k = b; k < e; ++k) r += A.id2[A.tmp[k]] < me;
+        // four members at a time, their loads in flight together
+        int64_t k = b;
+        for (; k + 4 <= e; k += 4) {
+            const int32_t t0 = A.tmp[k], t1 = A.tmp[k + 1], t2 = A.tmp[k + 2], t3 = A.tmp[k + 3];
+            r += (A.id2[t0] < me) + (A.id2[t1] < me) + (A.id2[t2] < me) + (A.id2[t3] < me);
+        }
+        for (; k < e; ++k) r += A.id2[A.tmp[k]] < me;
         const int64_t d = b + r;
         A.perm[d] = (int32_t)i;
         double v2 = 0.0;
