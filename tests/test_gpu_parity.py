@@ -256,6 +256,33 @@ def test_fp64_trajectory_matches_oracle(n_side):
     s.close()
 
 
+def test_fp64_trajectory_matches_oracle_3d_large():
+    """2 advection steps (80 substeps) of a 3D static droplet of 74,088
+    particles: past the fused-size limit, so a pass of its own ends each
+    substep, in 3D."""
+    w = WL.static_droplet_3d(n_side=42, R=0.25, seed=0)
+    p = w["params"]
+    say(f"trajectory static droplet 3D n={len(w['pos'])}, 2 advection steps")
+    st = O.State(p, w["pos"], w["vel"], w["phase"])
+    st.step(2)
+    s = rsph.System(p, precision=0)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(2)
+    o = s.observables()
+    ref = st.observables()
+    assert o["n_outer"] == 2 and o["n_sub"] == ref["n_sub"]
+    assert o["t"] == pytest.approx(ref["t"], rel=1e-12)
+    ev = normwise(s.read("vel"), st.vel)
+    er = normwise(s.read("rho") - np.asarray(p["rho0"])[w["phase"]],
+                  st.rho - np.asarray(p["rho0"])[w["phase"]])
+    pos = s.read("pos")
+    dpos = pos - O.wrap(p, st.pos)
+    dpos -= np.round(dpos)
+    say(f"trajectory 3D vel {ev:.2e} rho {er:.2e} pos {np.abs(dpos).max():.2e}")
+    assert ev < 1e-9 and er < 1e-9 and np.abs(dpos).max() < 1e-12
+    s.close()
+
+
 def test_bitwise_determinism_and_resume():
     w = WL.static_droplet_2d(n_side=40, R=0.2, seed=6)
     p = w["params"]
