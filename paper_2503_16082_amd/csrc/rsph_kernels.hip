@@ -96,6 +96,7 @@ struct Recs {
 };
 struct Pos3 {
     double x[3];
+    int ph;
 };
 
 // ---------------------------------------------------------------------------
@@ -679,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
             A.vel[a][d] = v[a];
             v2 += v[a] * v[a];
         }
-        ((double4*)A.xd)[d] = double4{x[0], x[1], x[2], 0.0};
+        ((double4*)A.xd)[d] = double4{x[0], x[1], x[2], (double)ph};
         A.rho[d] = rho;
         A.drho[d] = drho;
         A.mass[d] = mass;
@@ -915,7 +916,7 @@ __device__ __forceinline__ void append_hits(bool hit, uint32_t entry, int gshift
 template <int D, int G>
 __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, const double* xi, const int* ci,
                             int ph, bool live, int g, int gshift, uint32_t below, int64_t base, uint32_t* out,
-                            int& cnt, int& cross)
+                            int& cnt)
 {
     const int zr = D == 3 ? 1 : 0;
     for (int dz = -zr; dz <= zr; ++dz) {
@@ -946,7 +947,6 @@ __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, co
                     bool hit = false;
                     if (j < je && j != i) {
                         hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
-                        if (hit) cross |= A.phase[j] != ph;
                     }
                     append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
                 }
@@ -957,8 +957,9 @@ __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, co
 
 // Kernel sum sigma_i = W(0) + sum_j W_ij over particle i's list, the
 // normalised density summation rho_i = rho0_i sigma_i / sigma0, and the
-// {rho, V, p} record of the advection-step passes; flags pairs closer than
-// 1e-9 h.  FP64 in both forms: the density decides the pressure
+// {rho, V, p} record of the advection-step passes, and whether a neighbour is
+// of the other phase (the interface flag, stored with the frozen geometry
+// record); flags pairs closer than 1e-9 h.  FP64 in both forms: the density decides the pressure
 // c0^2 (rho - rho0), which amplifies a density error by rho / (rho - rho0).
 // Every lane of the group takes part; the lane that stores (lane 0 of a live
 // slot) gets true and the volume V.
@@ -966,17 +967,19 @@ template <typename R, int D, int G>
 __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysConst& S, SysDyn& Dy, int64_t i,
                                                   int g, bool live, int cnt, const double* xi, double& V)
 {
+    const int ph = live ? A.phase[i] : 0;
     double wsum = 0.0;
-    int coincident = 0, close = 0;
+    int coincident = 0, close = 0, cross = 0;
     // in 2D every lane's few entries are gathered at once
     constexpr int CH = D == 2 ? 4 : Chunk<R, D>::N;
     for_neighbours<G, CH>(
         A, i, g, live ? cnt : 0,
         [&](uint32_t j) {
             const double4 q = ((const double4*)A.xd)[j];  // one 32-byte record per neighbour
-            return Pos3{{q.x, q.y, q.z}};
+            return Pos3{{q.x, q.y, q.z}, (int)q.w};
         },
         [&](uint32_t j, const Pos3& rj) {
+            cross |= rj.ph != ph;
             double r2 = 0.0;
             for (int a = 0; a < D; ++a) {
                 double d = xi[a] - rj.x[a];
@@ -992,12 +995,16 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
     for (int o = 1; o < G; o <<= 1) {
         coincident |= __shfl_xor(coincident, o, 64);
         close |= __shfl_xor(close, o, 64);
+        cross |= __shfl_xor(cross, o, 64);
     }
     if (!live || g != 0) return false;
     if (coincident) flag_health(Dy, kHealthCoincident);
     if (close) flag_health(Dy, kHealthClose);
+    int ci[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) ci[a] = cell_of(xi[a], S, a);
+    A.flags[i] = cross ? kFlagInterface : 0;
+    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
     const double sigma = S.w0 + wsum;
-    const int ph = A.phase[i];
     double rho = A.rho[i];
     const double mass = A.mass[i];
     if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
@@ -1050,7 +1057,6 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     }
     const int box = stage_union<D>(A, S, L, base, live, ci, g);
     int cnt = 0;
-    int cross = 0;
     uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
     if (L.ok) {  // block-uniform
         float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
@@ -1103,16 +1109,14 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                         bool hit = valid && j != i32 && r2f < cut_hi;
                         if (hit && r2f >= cut_lo)  // within the FP32 error of the cut-off
                             hit = exact_r2<D>(A, xi, j, image_offset(S, ci[0] + dx, 0), ky, kz) < S.cut2;
-                        cross |= hit && (w & 1) != ph;
                         append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
                     }
                 }
             }
         }
     } else {
-        scan_global<D, G>(A, S, i, xi, ci, ph, live, g, gshift, below, base, out, cnt, cross);
+        scan_global<D, G>(A, S, i, xi, ci, ph, live, g, gshift, below, base, out, cnt);
     }
-    for (int o = 1; o < G; o <<= 1) cross |= __shfl_xor(cross, o, 64);
     if (cnt > A.kmax) {  // group-uniform
         if (live && g == 0) flag_health(Dy, kHealthNeighbours);
         cnt = A.kmax;
@@ -1125,13 +1129,11 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     }
     if (!store) return;
     A.ncount[i] = cnt;
-    A.flags[i] = cross ? kFlagInterface : 0;
     if (A.mode == 1)
         for (int a = 0; a < 3; ++a) A.r_gradc[3 * i + a] = 0.0;  // interface particles overwrite
     // the volume rides in the spare component of the velocity record read by
     // the advection pass (in 3D stored by the density pass)
     ((Q4<R>*)A.vbuf[0])[i] = Q4<R>{(R)vel_i[0], (R)vel_i[1], (R)vel_i[2], (R)V};
-    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
     ((Q4<R>*)A.col)[i] = Q4<R>{(R)0, (R)0, (R)0, (R)0};
 }
 
