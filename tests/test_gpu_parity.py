@@ -174,15 +174,20 @@ def test_eval_rates_parity(case, precision):
 
 @pytest.mark.parametrize("flags", [rsph.NO_PENALTY, rsph.GBAR_OWN_PHASE_AVERAGE, rsph.PENALTY_R3,
                                    rsph.NO_SURFACE])
-def test_eval_rates_parity_method_switches(flags):
-    w = WL.static_droplet_2d(n_side=40, R=0.2, seed=1)
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eval_rates_parity_method_switches(flags, dim, precision):
+    if dim == 2:
+        w = WL.static_droplet_2d(n_side=40, R=0.2, seed=1)
+    else:
+        w = WL.static_droplet_3d(n_side=16, R=0.3, seed=1)
     p, pos, vel, rho, mass, phase = perturbed_state(w)
     p["flags"] = flags
     p["oracle_flags"] = flags
-    say(f"eval switches flags={flags}")
-    g = gpu_rates(p, pos, vel, rho, mass, phase, 0)
+    say(f"eval switches flags={flags} dim={dim} precision={precision}")
+    g = gpu_rates(p, pos, vel, rho, mass, phase, precision)
     ref = O.eval_rates(p, pos, vel, rho, mass, phase)
-    compare_rates(g, ref, 0, f"flags{flags}")
+    compare_rates(g, ref, precision, f"flags{flags}/d{dim}/p{precision}")
 
 
 @pytest.mark.parametrize("precision", [0, 1])
