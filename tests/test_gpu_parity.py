@@ -261,6 +261,38 @@ def test_fp64_trajectory_matches_oracle(n_side):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["no_shift", "no_density_summation", "no_penalty", "gravity"])
+def test_fp64_trajectory_method_switches(case):
+    """3 advection steps of the 2D static droplet under each switch that acts
+    on the stepping (position shift, density summation, penalty) and with
+    gravity, against the oracle."""
+    w = WL.static_droplet_2d(n_side=40, R=0.2, seed=2)
+    p = dict(w["params"])
+    flags = {"no_shift": rsph.NO_SHIFT, "no_density_summation": rsph.NO_DENSITY_SUMMATION,
+             "no_penalty": rsph.NO_PENALTY, "gravity": 0}[case]
+    p["flags"] = flags
+    p["oracle_flags"] = flags
+    if case == "gravity":
+        p["gravity"] = [0.0, -0.5, 0.0]
+    say(f"trajectory switch {case}")
+    st = O.State(p, w["pos"], w["vel"], w["phase"])
+    st.step(3)
+    s = rsph.System(p, precision=0)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(3)
+    o = s.observables()
+    ref = st.observables()
+    assert o["n_outer"] == 3 and o["n_sub"] == ref["n_sub"]
+    ev = normwise(s.read("vel"), st.vel)
+    er = normwise(s.read("rho") - np.asarray(p["rho0"])[w["phase"]],
+                  st.rho - np.asarray(p["rho0"])[w["phase"]])
+    dpos = s.read("pos") - O.wrap(p, st.pos)
+    dpos -= np.round(dpos)
+    say(f"switch {case}: vel {ev:.2e} rho {er:.2e} pos {np.abs(dpos).max():.2e}")
+    assert ev < 1e-9 and er < 1e-9 and np.abs(dpos).max() < 1e-12
+    s.close()
+
+
 def test_fp64_trajectory_matches_oracle_3d_large():
     """2 advection steps (80 substeps) of a 3D static droplet of 74,088
     particles: past the fused-size limit, so a pass of its own ends each
