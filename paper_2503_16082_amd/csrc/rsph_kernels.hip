@@ -7,8 +7,9 @@
 // particles are cell-sorted, so neighbour gathers of a block mostly hit the L2
 // of its own XCD.  Pair loops gather-only: every particle sums its own
 // neighbours in a fixed order, so results are deterministic and no floating
-// point atomics are used (the only atomics are integer cell counters, an
-// integer max over |v| bit patterns and health bits).
+// point atomics are used (the only atomics are integer ones: the counting
+// sort's cell counters, whose arrival order the rank pass makes canonical,
+// health and work flags, and the LDS cell bounds of the neighbour staging).
 //
 // Precision forms: R = double (FP64 form) or R = float (mixed form: FP32 pair
 // arithmetic on split positions, FP64 state updates).  D = 2 or 3.
@@ -583,9 +584,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevArrays A)
 // starts for the passes that follow, and the rank pass clears the counts.
 constexpr int kScanSmall = 8192;
 constexpr int kScanSmallItems = kScanSmall / kBlock;
+// LDS index of cell start k: one word of padding per 32, so that the threads'
+// runs of 32 consecutive starts fall on different banks
+__device__ __forceinline__ int64_t st_pad(int64_t k) { return k + (k >> 5); }
+
 __global__ __launch_bounds__(kBlock) void k_scatter_small(DevArrays A, int64_t n)
 {
-    __shared__ int32_t st[kScanSmall + 1];
+    __shared__ int32_t st[kScanSmall + 1 + (kScanSmall + 1) / 32 + 1];
     __shared__ int lds[kBlock / kWave];
     // the slot's own loads first, so that their latency overlaps the scan
     const Slot c = slot_of(A);
@@ -619,16 +624,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter_small(DevArrays A, int64_t n
     int ex = block_exclusive_scan(sum, lds, total);
     for (int k = 0; k < kScanSmallItems; ++k) {
         const int64_t idx = base + k;
-        if (idx < n) st[idx] = ex;
+        if (idx < n) st[st_pad(idx)] = ex;
         ex += v[k];
     }
-    if (threadIdx.x == 0) st[n] = total;
+    if (threadIdx.x == 0) st[st_pad(n)] = total;
     __syncthreads();
     if (blockIdx.x == 0)
-        for (int64_t k = threadIdx.x; k <= n; k += kBlock) A.cell_start[k] = st[k];
+        for (int64_t k = threadIdx.x; k <= n; k += kBlock) A.cell_start[k] = st[st_pad(k)];
     if (!on) return;
     const SysConst& S = A.sc[c.s];
-    const int64_t dest = S.p_off + (st[S.c_off + key] - st[S.c_off]) + rk;
+    const int64_t dest = S.p_off + (st[st_pad(S.c_off + key)] - st[st_pad(S.c_off)]) + rk;
     A.tmp[dest] = (int32_t)c.i;
 }
 
