@@ -284,15 +284,21 @@ def accel_error(w, precision):
     return float(np.abs(acc - ref).max() / np.abs(ref).max())
 
 
-def cpu_baseline(w, outer_steps):
+def cpu_baseline(w, min_seconds, max_steps=5000):
     """The FP64 oracle, untuned, on the host cores: a bounded sample of the same
-    workload (its first advection steps)."""
+    workload, its first advection steps, taken until at least min_seconds of
+    host time have passed (at most max_steps)."""
     from oracle import oracle as O
     p = w["params"]
     st = O.State(p, w["pos"], w["vel"], w["phase"])
+    outer_steps = 0
     t0 = time.perf_counter()
-    st.step(outer_steps)
-    dt = time.perf_counter() - t0
+    while True:
+        st.step(5)
+        outer_steps += 5
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or outer_steps >= max_steps:
+            break
     n = w["pos"].shape[0]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
@@ -369,7 +375,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="host time of the oracle sample (whole advection steps, at least this long)")
     ap.add_argument("--no-accel-check", action="store_true",
                     help="skip the single-evaluation acceleration check against the oracle")
     ap.add_argument("--copy-probe", action="store_true", help="1 GiB device copy (counter reference)")
@@ -452,7 +459,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_steps)
+        cpu = cpu_baseline(w, args.cpu_seconds)
         log(f"cpu baseline {cpu}")
 
     line = {
