@@ -130,6 +130,7 @@ struct rsph_system {
     bool has_particles = false;
     bool faulted = false;
     bool rates_valid = false;
+    long long seen_outer = 0;  // advection steps done when the host last read the system's state
     std::string err;
 };
 
@@ -613,6 +614,32 @@ constexpr uint32_t kFaultBits =
     kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident | kHealthDtCollapse;
 constexpr int64_t kMaxSubsteps = 1000000;  // per advection step
 
+// m acoustic substeps for the systems inside an advection step (the others
+// exit at once)
+void launch_substeps_eager(rsph_pool* P, int64_t m)
+{
+    const Launch L = launch_of(P);
+    if (P->timing && P->next_group + m > P->A.work_cap) collect_timing(P);
+    DevArrays A = kernel_view(P);
+    A.mode = 0;
+    for (int64_t q = 0; q < m; ++q) {
+        const int64_t g = P->next_group++;
+        {
+            TimeScope t(P, RSPH_KERNEL_COLOUR, g);
+            launch_colour(L, A, t.ev);
+        }
+        {
+            TimeScope t(P, RSPH_KERNEL_FORCE, g);
+            launch_force(L, A, t.ev);
+        }
+        if (A.dt_pass) launch_dt_substep(L, A, g);
+        {
+            TimeScope t(P, RSPH_KERNEL_CONTINUITY, g);
+            launch_continuity(L, A, t.ev, g);
+        }
+    }
+}
+
 // One launch cycle: the advection-step prologue for systems at a boundary,
 // then m acoustic substeps for systems inside an advection step.  Every kernel
 // checks its system's state on the device, so no host synchronisation is
@@ -633,22 +660,7 @@ void launch_cycle_eager(rsph_pool* P, int64_t m)
         TimeScope t(P, RSPH_KERNEL_SHIFT, g0);
         launch_shift(L, A, t.ev);
     }
-    for (int64_t q = 0; q < m; ++q) {
-        const int64_t g = P->next_group++;
-        {
-            TimeScope t(P, RSPH_KERNEL_COLOUR, g);
-            launch_colour(L, A, t.ev);
-        }
-        {
-            TimeScope t(P, RSPH_KERNEL_FORCE, g);
-            launch_force(L, A, t.ev);
-        }
-        if (A.dt_pass) launch_dt_substep(L, A, g);
-        {
-            TimeScope t(P, RSPH_KERNEL_CONTINUITY, g);
-            launch_continuity(L, A, t.ev, g);
-        }
-    }
+    launch_substeps_eager(P, m);
 }
 
 // A launch cycle, replayed from a captured graph unless kernel timing is on
@@ -695,35 +707,56 @@ void launch_cycle(rsph_pool* P, int64_t m)
 // OR of the health bits.  Cycles are launched in batches with one stream
 // synchronisation after each: the substeps launched per cycle follow the most
 // substeps any system needed in one advection step during the last batch (a
-// step that needs more simply continues in the next cycle).
+// step that needs more simply continues in the next cycle).  A system's first
+// advection step does not count there: started from rest, it is bounded by
+// the viscous criterion alone and can need many times the substeps of the
+// steps after it.  When every system that still has work is only finishing
+// its last advection step, the rest of that step is launched as substeps
+// alone, as many as the longest of them still needs at its current acoustic
+// step (a later batch adds more if the acoustic step shrinks).
 uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
 {
     int64_t cycles = std::max<int64_t>(outer_hint, 1);
     int64_t batch = 4;
+    int64_t finish = 0;  // substeps alone, instead of cycles
     for (;;) {
-        const int64_t c = std::min(cycles, batch);
-        for (int64_t k = 0; k < c; ++k) launch_cycle(P, P->m_pred);
+        if (finish > 0) {
+            launch_substeps_eager(P, finish);
+        } else {
+            const int64_t c = std::min(cycles, batch);
+            for (int64_t k = 0; k < c; ++k) launch_cycle(P, P->m_pred);
+        }
         std::vector<SysDyn> d = read_dyn(P);
         uint32_t health = 0;
         int64_t remaining = 0;
-        bool pending = false;
-        int64_t m_seen = 0;
+        bool pending = false, new_steps = false;
+        int64_t m_seen = 0, rest = 0;
+        int32_t ksub_max = 0;
         for (size_t s = 0; s < d.size(); ++s) {
+            rsph_system* sys = P->systems[s];
             health |= d[s].health;
+            ksub_max = std::max(ksub_max, d[s].ksub_max);
             const long long left = d[s].target - d[s].n_outer;
             const bool inside = d[s].state == kSubstepping;
+            const bool settled = sys->seen_outer >= 1;
+            sys->seen_outer = d[s].n_outer;
             if (d[s].health & kFaultBits) continue;
             if (left > 0 || inside) pending = true;
+            if (left > 1 || (left == 1 && !inside)) new_steps = true;
             remaining = std::max<int64_t>(remaining, left);
-            m_seen = std::max<int64_t>(m_seen, d[s].ksub_max);
+            if (settled) m_seen = std::max<int64_t>(m_seen, d[s].ksub_max);
             if (d[s].ksub > kMaxSubsteps) fail(RSPH_ENUMERIC, "more than 1e6 acoustic substeps in one advection step");
+            if (inside && left == 1) {
+                const double dt = d[s].dt[d[s].ksub & 1];
+                const double r = dt > 0.0 ? std::ceil((d[s].dt_ad - d[s].tau) / dt) : (double)P->m_pred;
+                rest = std::max<int64_t>(rest, (int64_t)std::min(std::max(r, 1.0), 4096.0));
+            }
         }
-        if (m_seen > 0) {
-            P->m_pred = std::min<int64_t>(4096, m_seen);
-            launch_reset_ksub_max(launch_of(P), P->A);
-        }
+        if (m_seen > 0) P->m_pred = std::min<int64_t>(4096, m_seen);
+        if (ksub_max > 0) launch_reset_ksub_max(launch_of(P), P->A);
         // faulted systems stay idle on the device; the others run to their targets
         if (!pending) return health;
+        finish = new_steps ? 0 : rest;
         cycles = std::max<int64_t>(remaining, 1);
         batch = std::min<int64_t>(batch * 2, 64);
     }
@@ -838,6 +871,7 @@ void reset_dyn(rsph_system* s, bool keep_clock)
         d.vmax[0] = d.vmax[1] = 0.0;
     }
     d.target = d.n_outer;
+    s->seen_outer = d.n_outer;
     HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
 }
 
