@@ -130,7 +130,10 @@ struct rsph_system {
     bool has_particles = false;
     bool faulted = false;
     bool rates_valid = false;
-    long long seen_outer = 0;  // advection steps done when the host last read the system's state
+    // as of the host's last read of the system's device state
+    long long seen_outer = 0;  // advection steps done
+    long long seen_sub = 0;    // acoustic substeps done
+    long long sps = 0;         // most substeps of one advection step lately (0: none seen yet)
     std::string err;
 };
 
@@ -703,28 +706,49 @@ void launch_cycle(rsph_pool* P, int64_t m)
     HIPCHECK(hipGraphLaunch(hit->exec, P->stream));
 }
 
-// Advances every system of the pool to its device-side target.  Returns the
-// OR of the health bits.  Cycles are launched in batches with one stream
-// synchronisation after each: the substeps launched per cycle follow the most
-// substeps any system needed in one advection step during the last batch (a
-// step that needs more simply continues in the next cycle).  A system's first
-// advection step does not count there: started from rest, it is bounded by
-// the viscous criterion alone and can need many times the substeps of the
+// Substeps per launch cycle for the advection steps still to go (left[row]):
+// the system with the most substeps to go is spread over as many cycles as
+// the system with the most advection steps to go needs (a system takes at most
+// one advection step per cycle).  A system's substeps per step are those of
+// its recent steps; a system without any yet counts as the most of the others.
+int64_t plan_substeps(const rsph_pool* P, const std::vector<long long>& left)
+{
+    double work = 0.0;
+    long long steps = 0;
+    for (size_t r = 0; r < left.size(); ++r) {
+        if (left[r] <= 0 || P->systems[r]->faulted) continue;
+        const long long sps = P->systems[r]->sps > 0 ? P->systems[r]->sps : P->m_pred;
+        work = std::max(work, (double)left[r] * (double)sps);
+        steps = std::max(steps, left[r]);
+    }
+    if (steps == 0) return P->m_pred;
+    return std::min<int64_t>(4096, std::max<int64_t>(1, (int64_t)std::ceil(work / (double)steps)));
+}
+
+// Advances every system of the pool to its device-side target (left[row]
+// advection steps to go).  Returns the OR of the health bits.  Cycles are
+// launched in batches with one stream synchronisation after each; the
+// substeps per cycle follow the systems' recent substeps per advection step
+// (a step that needs more simply continues in the next cycle).  A system's
+// first advection step does not count there: started from rest, it is bounded
+// by the viscous criterion alone and can need many times the substeps of the
 // steps after it.  When every system that still has work is only finishing
 // its last advection step, the rest of that step is launched as substeps
 // alone, as many as the longest of them still needs at its current acoustic
 // step (a later batch adds more if the acoustic step shrinks).
-uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
+uint32_t run_to_targets(rsph_pool* P, std::vector<long long> left)
 {
-    int64_t cycles = std::max<int64_t>(outer_hint, 1);
+    int64_t cycles = 1;
+    for (long long l : left) cycles = std::max<int64_t>(cycles, l);
     int64_t batch = 4;
+    int64_t m = plan_substeps(P, left);
     int64_t finish = 0;  // substeps alone, instead of cycles
     for (;;) {
         if (finish > 0) {
             launch_substeps_eager(P, finish);
         } else {
             const int64_t c = std::min(cycles, batch);
-            for (int64_t k = 0; k < c; ++k) launch_cycle(P, P->m_pred);
+            for (int64_t k = 0; k < c; ++k) launch_cycle(P, m);
         }
         std::vector<SysDyn> d = read_dyn(P);
         uint32_t health = 0;
@@ -736,19 +760,25 @@ uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
             rsph_system* sys = P->systems[s];
             health |= d[s].health;
             ksub_max = std::max(ksub_max, d[s].ksub_max);
-            const long long left = d[s].target - d[s].n_outer;
+            const long long l = d[s].target - d[s].n_outer;
             const bool inside = d[s].state == kSubstepping;
             const bool settled = sys->seen_outer >= 1;
             sys->seen_outer = d[s].n_outer;
-            if (d[s].health & kFaultBits) continue;
-            if (left > 0 || inside) pending = true;
-            if (left > 1 || (left == 1 && !inside)) new_steps = true;
-            remaining = std::max<int64_t>(remaining, left);
+            sys->seen_sub = d[s].n_sub;
+            if (settled && d[s].ksub_max > 0) sys->sps = d[s].ksub_max;
+            left[s] = std::max(l, 0LL);
+            if (d[s].health & kFaultBits) {
+                left[s] = 0;
+                continue;
+            }
+            if (l > 0 || inside) pending = true;
+            if (l > 1 || (l == 1 && !inside)) new_steps = true;
+            remaining = std::max<int64_t>(remaining, l);
             if (settled) m_seen = std::max<int64_t>(m_seen, d[s].ksub_max);
             if (d[s].ksub > kMaxSubsteps) fail(RSPH_ENUMERIC, "more than 1e6 acoustic substeps in one advection step");
-            if (inside && left == 1) {
+            if (inside && l == 1) {
                 const double dt = d[s].dt[d[s].ksub & 1];
-                const double r = dt > 0.0 ? std::ceil((d[s].dt_ad - d[s].tau) / dt) : (double)P->m_pred;
+                const double r = dt > 0.0 ? std::ceil((d[s].dt_ad - d[s].tau) / dt) : (double)m;
                 rest = std::max<int64_t>(rest, (int64_t)std::min(std::max(r, 1.0), 4096.0));
             }
         }
@@ -757,6 +787,7 @@ uint32_t run_to_targets(rsph_pool* P, int64_t outer_hint)
         // faulted systems stay idle on the device; the others run to their targets
         if (!pending) return health;
         finish = new_steps ? 0 : rest;
+        m = plan_substeps(P, left);
         cycles = std::max<int64_t>(remaining, 1);
         batch = std::min<int64_t>(batch * 2, 64);
     }
@@ -872,6 +903,8 @@ void reset_dyn(rsph_system* s, bool keep_clock)
     }
     d.target = d.n_outer;
     s->seen_outer = d.n_outer;
+    s->seen_sub = d.n_sub;
+    if (!keep_clock) s->sps = 0;
     HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
 }
 
@@ -1098,7 +1131,9 @@ rsph_status rsph_step(rsph_system* s, int64_t n_outer)
         std::vector<long long> targets(P->systems.size(), -1);
         targets[s->row] = d[s->row].n_outer + n_outer;
         set_targets(P, targets);
-        const uint32_t h = run_to_targets(P, n_outer);
+        std::vector<long long> left(P->systems.size(), 0);
+        left[s->row] = n_outer;
+        const uint32_t h = run_to_targets(P, left);
         if (h & kFaultBits) {
             s->faulted = true;
             char buf[128];
@@ -1446,7 +1481,10 @@ rsph_status rsph_pool_step(rsph_pool* P, rsph_system* const* systems, const int6
         }
         if (most == 0) return;
         set_targets(P, targets);
-        const uint32_t h = run_to_targets(P, most);
+        std::vector<long long> left(P->systems.size(), 0);
+        for (size_t r = 0; r < left.size(); ++r)
+            if (targets[r] >= 0) left[r] = targets[r] - d[r].n_outer;
+        const uint32_t h = run_to_targets(P, left);
         if (h & kFaultBits) {
             std::vector<SysDyn> dd = read_dyn(P);
             std::string names;
@@ -1463,6 +1501,15 @@ rsph_status rsph_pool_step(rsph_pool* P, rsph_system* const* systems, const int6
 }
 
 size_t rsph_pool_bytes(const rsph_pool* P) { return P ? P->bytes : 0; }
+
+rsph_status rsph_step_counts(const rsph_system* s, int64_t* n_outer, int64_t* n_sub, int64_t* substeps_per_step)
+{
+    if (!s || !n_outer || !n_sub || !substeps_per_step) return RSPH_EINVAL;
+    *n_outer = s->seen_outer;
+    *n_sub = s->seen_sub;
+    *substeps_per_step = s->sps;
+    return RSPH_OK;
+}
 
 rsph_status rsph_pool_release(rsph_pool* P, rsph_system* s)
 {

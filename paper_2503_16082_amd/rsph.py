@@ -95,7 +95,7 @@ SYMBOLS = [
     "rsph_step", "rsph_eval_rates", "rsph_read_observables", "rsph_read_particles",
     "rsph_read_binning", "rsph_read_neighbours", "rsph_set_kernel_timing", "rsph_set_launch_mode",
     "rsph_read_kernel_timing", "rsph_destroy_system", "rsph_status_string", "rsph_last_error",
-    "rsph_pool_create", "rsph_pool_admit", "rsph_pool_step", "rsph_pool_bytes",
+    "rsph_pool_create", "rsph_pool_admit", "rsph_pool_step", "rsph_pool_bytes", "rsph_step_counts",
     "rsph_pool_release", "rsph_pool_destroy",
 ]
 
@@ -136,6 +136,7 @@ def lib():
     L.rsph_pool_step.argtypes = [vp, vp, vp, i32]
     L.rsph_pool_bytes.argtypes = [vp]
     L.rsph_pool_bytes.restype = C.c_size_t
+    L.rsph_step_counts.argtypes = [vp, vp, vp, vp]
     L.rsph_pool_release.argtypes = [vp, vp]
     L.rsph_pool_destroy.argtypes = [vp]
     L.rsph_pool_destroy.restype = None
@@ -253,6 +254,14 @@ class System:
         idx = np.zeros(self.n * cap_per, np.int64)
         _check(lib().rsph_read_neighbours(self.h, self.n, idx.shape[0], _p(start), _p(idx)), self.h)
         return start, idx[: start[-1]].copy()
+
+    def step_counts(self):
+        """Advection steps, acoustic substeps, and the most substeps one of the
+        recent advection steps needed (0 until known), as of the end of the
+        last stepping call (host-side; no device access)."""
+        out = [C.c_int64() for _ in range(3)]
+        _check(lib().rsph_step_counts(self.h, *[C.byref(o) for o in out]), self.h)
+        return {"n_outer": out[0].value, "n_sub": out[1].value, "substeps_per_step": out[2].value}
 
     def set_launch_mode(self, mode):
         """'graph' (captured launch cycles, the default) or 'eager'; applies to

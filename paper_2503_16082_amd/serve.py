@@ -2,11 +2,18 @@
 
 Jobs (2D oscillating droplets of uneven particle counts and parameters) arrive
 as a Poisson process.  A job is admitted into a device pool as soon as the
-pool's HBM budget holds it; every scheduler tick advances all admitted jobs by
-one advection step in the same launches (each job keeps its own time steps);
-finished jobs are read out and released, freeing room for queued ones.  The
-loop records, per job, the wall time of each advection step it took part in,
-and reports p50/p99 per-step latency beside the aggregate particle-steps/s.
+pool's HBM budget holds it; every scheduler tick advances all admitted jobs in
+the same launches (each job keeps its own time steps); finished jobs are read
+out and released, freeing room for queued ones.
+
+Jobs differ several-fold in acoustic substeps per advection step (Eqs. 16-18),
+and a tick lasts as long as its longest job.  A tick therefore gives a job
+that needs fewer substeps per step proportionally more advection steps (up to
+max_steps_per_tick), so that all jobs fill the tick; max_steps_per_tick=1
+steps every job once per tick.  The loop records each job's advection steps
+with their latency, the tick's wall time shared out over the steps the job
+took in it, and reports p50/p99 per-step latency (and per tick) beside the
+aggregate particle-steps/s.
 
 Host-side scheduling only: all stepping runs in the HIP library through the
 pool entry points of the C-ABI.
@@ -28,8 +35,22 @@ def build_job(desc):
                                      seed=desc["seed"])
 
 
+def steps_this_tick(sps, left, cap):
+    """Advection steps per job for one tick: the job with the most substeps
+    per step takes one; a job needing fewer takes as many as fit in the same
+    number of substeps (at most cap and its steps left).  A job whose count is
+    not known yet takes one."""
+    known = [v for v in sps if v > 0]
+    ref = max(known) if known else 0
+    out = []
+    for v, l in zip(sps, left):
+        n = 1 if (v <= 0 or ref == 0) else max(1, ref // v)
+        out.append(int(max(1, min(n, cap, l))))
+    return out
+
+
 def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, precision=rsph.MIXED,
-          log=None, keep_results=False, max_seconds=None):
+          log=None, keep_results=False, max_seconds=None, max_steps_per_tick=1):
     """Runs the request loop to completion.  rate_hz: Poisson arrival rate
     (None: all jobs arrive at t = 0).  Returns a summary dictionary."""
     rng = np.random.Generator(np.random.PCG64(12345))
@@ -43,6 +64,7 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
     queue = collections.deque()
     active = {}  # job index -> [system, steps done, n particles]
     step_latency = []
+    tick_latency = []
     finished = {}
     next_arrival = 0
     particle_steps = 0
@@ -76,13 +98,19 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
                 time.sleep(max(0.0, arrivals[next_arrival] - (time.perf_counter() - t0)))
             continue
         order = sorted(active)
+        if max_steps_per_tick > 1:
+            sps = [active[k][0].step_counts()["substeps_per_step"] for k in order]
+            n_tick = steps_this_tick(sps, [steps_per_job - active[k][1] for k in order], max_steps_per_tick)
+        else:
+            n_tick = [1] * len(order)
         ta = time.perf_counter()
-        pool.step([active[k][0] for k in order], [1] * len(order))
+        pool.step([active[k][0] for k in order], n_tick)
         dt = time.perf_counter() - ta
-        for k in order:
-            active[k][1] += 1
-            particle_steps += active[k][2]
-            step_latency.append(dt)
+        tick_latency.append(dt)
+        for k, n in zip(order, n_tick):
+            active[k][1] += n
+            particle_steps += active[k][2] * n
+            step_latency.extend([dt / n] * n)
         for k in order:
             s, done, n = active[k]
             if done >= steps_per_job:
@@ -99,6 +127,7 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
                         f"{len(active)} active, {len(queue)} queued")
     wall = time.perf_counter() - t0
     lat = np.array(step_latency) if step_latency else np.zeros(1)
+    tick = np.array(tick_latency) if tick_latency else np.zeros(1)
     summary = {
         "jobs": len(finished),
         "wall_s": wall,
@@ -106,6 +135,9 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
         "particle_steps_per_s": particle_steps / wall if wall > 0 else 0.0,
         "step_latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
         "step_latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "tick_latency_p50_ms": float(np.percentile(tick, 50) * 1e3),
+        "tick_latency_p99_ms": float(np.percentile(tick, 99) * 1e3),
+        "max_steps_per_tick": max_steps_per_tick,
         "max_queue_depth": int(max(queue_depth) if queue_depth else 0),
         "turnaround_p50_s": float(np.median([f["done_at"] - f["arrived"] for f in finished.values()]))
         if finished else math.nan,

@@ -169,10 +169,12 @@ def test_invalid_particles_rejected():
     s.close()
 
 
-def test_serving_loop_continuous_batching():
+@pytest.mark.parametrize("max_steps_per_tick", [1, 4])
+def test_serving_loop_continuous_batching(max_steps_per_tick):
     """Poisson arrivals into a budget that cannot hold every job at once: all
     jobs finish, the queue was used, and every job's result equals the same
-    job run alone."""
+    job run alone, whether each tick steps every job once or gives jobs with
+    fewer substeps per step more steps."""
     from paper_2503_16082_amd import serve
     descs = WL.served_mix(n_jobs=6, seed=3, n_min=2000, n_max=9000)
     probe = rsph.Pool(2, precision=1)
@@ -180,15 +182,40 @@ def test_serving_loop_continuous_batching():
     probe.admit(w0["params"], w0["pos"], w0["vel"], w0["phase"])
     one = probe.bytes()
     probe.close()
-    out = serve.serve(descs, steps_per_job=4, rate_hz=200.0, budget_bytes=int(one * 4),
-                      precision=1, keep_results=True)
+    steps = 4 if max_steps_per_tick == 1 else 12
+    out = serve.serve(descs, steps_per_job=steps, rate_hz=200.0, budget_bytes=int(one * 4),
+                      precision=1, keep_results=True, max_steps_per_tick=max_steps_per_tick)
     say({k: v for k, v in out.items() if k != "results"})
     assert out["jobs"] == 6 and out["max_queue_depth"] >= 1
     assert out["step_latency_p99_ms"] >= out["step_latency_p50_ms"] > 0
+    assert out["particle_steps"] == steps * sum(serve.build_job(d)["pos"].shape[0] for d in descs)
     for k in [0, 3, 5]:
-        ref = alone(serve.build_job(descs[k]), 4, 1)
+        ref = alone(serve.build_job(descs[k]), steps, 1)
         for f in ["pos", "vel", "rho"]:
             assert np.array_equal(out["results"][k][f], ref[f])
+
+
+def test_step_counts_follow_the_device_counts():
+    """The host-side counts of a pool member equal its observables after each
+    stepping call; substeps per step stay unknown (0) until a step after the
+    first one (from rest) has been seen."""
+    from paper_2503_16082_amd import serve
+    descs = WL.served_mix(n_jobs=2, seed=4, n_min=2000, n_max=6000)
+    pool = rsph.Pool(2, precision=1)
+    ws = [serve.build_job(d) for d in descs]
+    members = [pool.admit(w["params"], w["pos"], w["vel"], w["phase"]) for w in ws]
+    assert [m.step_counts()["n_outer"] for m in members] == [0, 0]
+    pool.step(members, [1, 1])
+    for m in members:
+        c, o = m.step_counts(), m.observables()
+        assert (c["n_outer"], c["n_sub"]) == (o["n_outer"], o["n_sub"]) == (1, c["n_sub"])
+        assert c["substeps_per_step"] == 0
+    pool.step(members, [2, 3])
+    for m, n in zip(members, [3, 4]):
+        c, o = m.step_counts(), m.observables()
+        assert (c["n_outer"], c["n_sub"]) == (o["n_outer"], o["n_sub"]) and c["n_outer"] == n
+        assert 1 <= c["substeps_per_step"] <= c["n_sub"]
+    pool.close()
 
 
 def test_empty_and_overfull_inputs_rejected():

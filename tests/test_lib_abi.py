@@ -57,3 +57,8 @@ def test_create_system_rejects_invalid_parameters(bad):
     with pytest.raises(rsph.RsphError) as e:
         rsph.System(_params(**bad))
     assert e.value.name == "EINVAL"
+
+
+def test_step_counts_rejects_null_arguments():
+    v = [C.c_int64() for _ in range(3)]
+    assert rsph.lib().rsph_step_counts(None, *[C.byref(x) for x in v]) == -1
