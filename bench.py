@@ -354,6 +354,8 @@ def served(args):
         "step_latency_p99_ms": out["step_latency_p99_ms"],
         "tick_latency_p50_ms": out["tick_latency_p50_ms"],
         "tick_latency_p99_ms": out["tick_latency_p99_ms"],
+        "step_interval_p50_ms": out["step_interval_p50_ms"],
+        "step_interval_p99_ms": out["step_interval_p99_ms"],
         "turnaround_p50_s": out["turnaround_p50_s"],
         "max_queue_depth": out["max_queue_depth"],
         "jobs_done": out["jobs"],

@@ -404,6 +404,33 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
         int64_t Pg = P->standalone ? L.P : Pc;
         int64_t Cg = P->standalone ? L.C : Cc;
         int Sg = P->standalone ? S : Sc;
+        if (P->budget && !P->standalone) {
+            // a pool with a budget takes all of it when it first grows: launch
+            // grids follow the slots in use, so unused capacity costs no time,
+            // and later admissions seldom reallocate (which copies every
+            // member).  Cells: one per 4 slots at least; system rows: 64.
+            const int Sb = std::max(Sg, 64);
+            auto cells_for = [&](int64_t p) { return std::max<int64_t>(Cg, p / 4); };
+            auto fits = [&](int64_t p) { return arrays_bytes(P, p, cells_for(p), Sb) <= P->budget; };
+            if (fits(Pg)) {
+                const int64_t top = (int64_t)INT32_MAX / 2 / kBlock * kBlock;
+                int64_t lo = Pg, hi = Pg;
+                while (hi < top && fits(std::min(top, hi * 2))) hi = std::min(top, hi * 2);
+                lo = hi;
+                hi = std::min(top, hi * 2);
+                // largest multiple of kBlock in [lo, hi] that fits
+                while (hi - lo > kBlock) {
+                    const int64_t mid = (lo + hi) / 2 / kBlock * kBlock;
+                    if (mid <= lo) break;
+                    if (fits(mid)) lo = mid;
+                    else hi = mid;
+                }
+                if (hi > lo && fits(hi)) lo = hi;
+                Pg = lo;
+                Cg = cells_for(lo);
+                Sg = Sb;
+            }
+        }
         if (P->budget && arrays_bytes(P, Pg, Cg, Sg) > P->budget) {
             // no head room for growth: exactly what the members need
             Pg = L.P;
@@ -436,6 +463,9 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
         }
     }
     DevArrays& A = P->A;
+    // the kernels cover the slots and cells in use, not the capacity
+    A.P = L.P;
+    A.C = L.C;
     // copy each member's persistent state from its old range into the
     // second buffer (new capacity, new offsets), then make that current
     double** dst_d[] = {&A.pos2[0], &A.pos2[1], &A.pos2[2], &A.vel2[0], &A.vel2[1], &A.vel2[2],

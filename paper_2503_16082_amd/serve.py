@@ -13,7 +13,11 @@ max_steps_per_tick), so that all jobs fill the tick; max_steps_per_tick=1
 steps every job once per tick.  The loop records each job's advection steps
 with their latency, the tick's wall time shared out over the steps the job
 took in it, and reports p50/p99 per-step latency (and per tick) beside the
-aggregate particle-steps/s.
+aggregate particle-steps/s.  It also reports each job's step interval: the
+wall time from its admission or previous tick to the end of its tick, shared
+out over the steps it took, which includes the time the loop spends admitting
+and releasing other jobs.  Job payloads are built before the clock starts, as
+a request carries its particles when it arrives.
 
 Host-side scheduling only: all stepping runs in the HIP library through the
 pool entry points of the C-ABI.
@@ -59,11 +63,12 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
         arrivals = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_jobs))
     else:
         arrivals = np.zeros(n_jobs)
-    built = {}
+    built = {k: build_job(d) for k, d in enumerate(job_descs)}
     pool = rsph.Pool(2, precision=precision, budget_bytes=budget_bytes)
     queue = collections.deque()
-    active = {}  # job index -> [system, steps done, n particles]
+    active = {}  # job index -> [system, steps done, n particles, end of its last tick or admission]
     step_latency = []
+    step_interval = []
     tick_latency = []
     finished = {}
     next_arrival = 0
@@ -80,8 +85,6 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
         # admission, first come first served, as long as the budget allows
         while queue:
             k = queue[0]
-            if k not in built:
-                built[k] = build_job(job_descs[k])
             w = built[k]
             try:
                 s = pool.admit(w["params"], w["pos"], w["vel"], w["phase"])
@@ -90,7 +93,7 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
                     break
                 raise
             queue.popleft()
-            active[k] = [s, 0, w["pos"].shape[0]]
+            active[k] = [s, 0, w["pos"].shape[0], time.perf_counter()]
         queue_depth.append(len(queue))
         if not active:
             # idle until the next arrival
@@ -105,14 +108,17 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
             n_tick = [1] * len(order)
         ta = time.perf_counter()
         pool.step([active[k][0] for k in order], n_tick)
-        dt = time.perf_counter() - ta
+        tb = time.perf_counter()
+        dt = tb - ta
         tick_latency.append(dt)
         for k, n in zip(order, n_tick):
             active[k][1] += n
             particle_steps += active[k][2] * n
             step_latency.extend([dt / n] * n)
+            step_interval.extend([(tb - active[k][3]) / n] * n)
+            active[k][3] = tb
         for k in order:
-            s, done, n = active[k]
+            s, done, n, _ = active[k]
             if done >= steps_per_job:
                 res = None
                 if keep_results:
@@ -128,6 +134,7 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
     wall = time.perf_counter() - t0
     lat = np.array(step_latency) if step_latency else np.zeros(1)
     tick = np.array(tick_latency) if tick_latency else np.zeros(1)
+    gap = np.array(step_interval) if step_interval else np.zeros(1)
     summary = {
         "jobs": len(finished),
         "wall_s": wall,
@@ -137,6 +144,8 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
         "step_latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
         "tick_latency_p50_ms": float(np.percentile(tick, 50) * 1e3),
         "tick_latency_p99_ms": float(np.percentile(tick, 99) * 1e3),
+        "step_interval_p50_ms": float(np.percentile(gap, 50) * 1e3),
+        "step_interval_p99_ms": float(np.percentile(gap, 99) * 1e3),
         "max_steps_per_tick": max_steps_per_tick,
         "max_queue_depth": int(max(queue_depth) if queue_depth else 0),
         "turnaround_p50_s": float(np.median([f["done_at"] - f["arrived"] for f in finished.values()]))
