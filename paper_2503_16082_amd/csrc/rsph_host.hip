@@ -467,32 +467,38 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
     A.P = L.P;
     A.C = L.C;
     // copy each member's persistent state from its old range into the
-    // second buffer (new capacity, new offsets), then make that current
-    double** dst_d[] = {&A.pos2[0], &A.pos2[1], &A.pos2[2], &A.vel2[0], &A.vel2[1], &A.vel2[2],
-                        &A.rho2, &A.drho2, &A.mass2};
-    double* src_d[] = {old.pos[0], old.pos[1], old.pos[2], old.vel[0], old.vel[1], old.vel[2],
-                       old.rho, old.drho, old.mass};
-    int32_t** dst_i[] = {&A.id2, &A.phase2};
-    int32_t* src_i[] = {old.id, old.phase};
-    for (int k = 0; k < S; ++k) {
-        rsph_system* s = members[k];
-        if (!s->has_particles || s->row < 0) continue;
-        for (int q = 0; q < 9; ++q)
-            HIPCHECK(hipMemcpyAsync(*dst_d[q] + L.p_off[k], src_d[q] + s->p_off,
-                                    sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
-        for (int q = 0; q < 2; ++q)
-            HIPCHECK(hipMemcpyAsync(*dst_i[q] + L.p_off[k], src_i[q] + s->p_off,
-                                    sizeof(int32_t) * s->n, hipMemcpyDeviceToDevice, st));
+    // second buffer (new capacity, new offsets), then make that current; not
+    // needed when no member moves (an admission that fits appends its system)
+    bool moved = grow;
+    for (int k = 0; k < S; ++k)
+        if (members[k]->has_particles && members[k]->row >= 0 && L.p_off[k] != members[k]->p_off) moved = true;
+    if (moved) {
+        double** dst_d[] = {&A.pos2[0], &A.pos2[1], &A.pos2[2], &A.vel2[0], &A.vel2[1], &A.vel2[2],
+                            &A.rho2, &A.drho2, &A.mass2};
+        double* src_d[] = {old.pos[0], old.pos[1], old.pos[2], old.vel[0], old.vel[1], old.vel[2],
+                           old.rho, old.drho, old.mass};
+        int32_t** dst_i[] = {&A.id2, &A.phase2};
+        int32_t* src_i[] = {old.id, old.phase};
+        for (int k = 0; k < S; ++k) {
+            rsph_system* s = members[k];
+            if (!s->has_particles || s->row < 0) continue;
+            for (int q = 0; q < 9; ++q)
+                HIPCHECK(hipMemcpyAsync(*dst_d[q] + L.p_off[k], src_d[q] + s->p_off,
+                                        sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
+            for (int q = 0; q < 2; ++q)
+                HIPCHECK(hipMemcpyAsync(*dst_i[q] + L.p_off[k], src_i[q] + s->p_off,
+                                        sizeof(int32_t) * s->n, hipMemcpyDeviceToDevice, st));
+        }
+        for (int a = 0; a < 3; ++a) {
+            std::swap(A.pos[a], A.pos2[a]);
+            std::swap(A.vel[a], A.vel2[a]);
+        }
+        std::swap(A.rho, A.rho2);
+        std::swap(A.drho, A.drho2);
+        std::swap(A.mass, A.mass2);
+        std::swap(A.id, A.id2);
+        std::swap(A.phase, A.phase2);
     }
-    for (int a = 0; a < 3; ++a) {
-        std::swap(A.pos[a], A.pos2[a]);
-        std::swap(A.vel[a], A.vel2[a]);
-    }
-    std::swap(A.rho, A.rho2);
-    std::swap(A.drho, A.drho2);
-    std::swap(A.mass, A.mass2);
-    std::swap(A.id, A.id2);
-    std::swap(A.phase, A.phase2);
     // tables
     std::vector<SysConst> sc(S);
     std::vector<SysDyn> sd(S);
