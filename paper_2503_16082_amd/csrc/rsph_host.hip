@@ -116,6 +116,9 @@ struct rsph_pool {
     // launch cycles captured as HIP graphs, replayed while kernel timing is off
     bool graphs = true;
     std::vector<CycleGraph> cycle_graphs;
+    // pinned host staging of particle uploads (hipHostMalloc), grown on demand
+    char* stage = nullptr;
+    size_t stage_bytes = 0;
 };
 
 struct rsph_system {
@@ -889,34 +892,49 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
     HIPCHECK(hipStreamSynchronize(P->stream));
     const int64_t n = s->n;
     const int d = s->prm.dim;
-    std::vector<double> buf(n);
-    auto put = [&](double* dst) {
-        HIPCHECK(hipMemcpy(dst + s->p_off, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-    };
-    for (int a = 0; a < 3; ++a) {
-        for (int64_t i = 0; i < n; ++i) {
-            double x = a < d ? pos[i * d + a] : 0.0;
-            if (a < d) {
-                const double L = s->prm.box[a];
-                x = x - L * std::floor(x / L);
-                if (x >= L) x -= L;
-            }
-            buf[i] = x;
-        }
-        put(P->A.pos[a]);
-        for (int64_t i = 0; i < n; ++i) buf[i] = a < d ? vel[i * d + a] : 0.0;
-        put(P->A.vel[a]);
+    // the fields are staged in pinned host memory, a bounded chunk of
+    // particles at a time, and each chunk is copied with one stream sync
+    constexpr int64_t kChunk = 1 << 19;
+    const int64_t cn = std::min<int64_t>(n, kChunk);
+    const size_t need = (sizeof(double) * 9 + sizeof(int32_t) * 2) * (size_t)cn;
+    if (need > P->stage_bytes) {
+        if (P->stage) HIPCHECK(hipHostFree(P->stage));
+        P->stage = nullptr;
+        P->stage_bytes = 0;
+        HIPCHECK(hipHostMalloc((void**)&P->stage, need, hipHostMallocDefault));
+        P->stage_bytes = need;
     }
-    for (int64_t i = 0; i < n; ++i) buf[i] = mass ? mass[i] : s->prm.rho0[phase[i]] / s->sc.sigma0;
-    put(P->A.mass);
-    for (int64_t i = 0; i < n; ++i) buf[i] = rho ? rho[i] : s->prm.rho0[phase[i]];
-    put(P->A.rho);
-    for (int64_t i = 0; i < n; ++i) buf[i] = 0.0;
-    put(P->A.drho);
-    std::vector<int32_t> ib(n);
-    for (int64_t i = 0; i < n; ++i) ib[i] = (int32_t)i;
-    HIPCHECK(hipMemcpy(P->A.id + s->p_off, ib.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(P->A.phase + s->p_off, phase, sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    double* f = (double*)P->stage;
+    int32_t* ib = (int32_t*)(f + 9 * cn);
+    double* dst[9] = {P->A.pos[0], P->A.pos[1], P->A.pos[2], P->A.vel[0], P->A.vel[1], P->A.vel[2],
+                      P->A.mass, P->A.rho, P->A.drho};
+    for (int64_t i0 = 0; i0 < n; i0 += cn) {
+        const int64_t m = std::min(cn, n - i0);
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t i = i0 + k;
+            for (int a = 0; a < 3; ++a) {
+                double q = a < d ? pos[i * d + a] : 0.0;
+                if (a < d) {
+                    const double L = s->prm.box[a];
+                    q = q - L * std::floor(q / L);
+                    if (q >= L) q -= L;
+                }
+                f[a * cn + k] = q;
+                f[(3 + a) * cn + k] = a < d ? vel[i * d + a] : 0.0;
+            }
+            f[6 * cn + k] = mass ? mass[i] : s->prm.rho0[phase[i]] / s->sc.sigma0;
+            f[7 * cn + k] = rho ? rho[i] : s->prm.rho0[phase[i]];
+            f[8 * cn + k] = 0.0;
+            ib[k] = (int32_t)i;
+            ib[cn + k] = phase[i];
+        }
+        const int64_t o = s->p_off + i0;
+        for (int q = 0; q < 9; ++q)
+            HIPCHECK(hipMemcpyAsync(dst[q] + o, f + q * cn, sizeof(double) * m, hipMemcpyHostToDevice, P->stream));
+        HIPCHECK(hipMemcpyAsync(P->A.id + o, ib, sizeof(int32_t) * m, hipMemcpyHostToDevice, P->stream));
+        HIPCHECK(hipMemcpyAsync(P->A.phase + o, ib + cn, sizeof(int32_t) * m, hipMemcpyHostToDevice, P->stream));
+        HIPCHECK(hipStreamSynchronize(P->stream));
+    }
 }
 
 void reset_dyn(rsph_system* s, bool keep_clock)
@@ -1001,6 +1019,7 @@ void destroy_pool(rsph_pool* P)
     }
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     free_arrays(P);
+    if (P->stage) (void)hipHostFree(P->stage);
     if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
 }
