@@ -257,11 +257,12 @@ size_t rsph_pool_bytes(const rsph_pool* pool);
 /* Counts of a system (standalone or in a pool) as of the end of its last
  * stepping call, held on the host (no device access): advection steps and
  * acoustic substeps taken, and the most substeps one of its recent advection
- * steps needed (Eqs. 16-18 set that count; 0 until one step after its first
- * has been seen, since a first step from rest is bounded by the viscous
- * criterion alone).  A scheduler can give systems that need few substeps per
- * advection step more advection steps per stepping call.  EINVAL on a NULL
- * argument. */
+ * steps needed (Eqs. 16-18 set that count).  Before the system's first step
+ * the last figure is an estimate for that step from the uploaded velocities;
+ * after it, 0 until a later step has been seen, since a first step from rest
+ * is bounded by the viscous criterion alone.  A scheduler can give systems
+ * that need few substeps per advection step more advection steps per stepping
+ * call.  EINVAL on a NULL argument. */
 rsph_status rsph_step_counts(const rsph_system* sys, int64_t* n_outer, int64_t* n_sub,
                              int64_t* substeps_per_step);
 rsph_status rsph_pool_release(rsph_pool* pool, rsph_system* sys);

@@ -137,6 +137,8 @@ struct rsph_system {
     long long seen_outer = 0;  // advection steps done
     long long seen_sub = 0;    // acoustic substeps done
     long long sps = 0;         // most substeps of one advection step lately (0: none seen yet)
+    long long first_sps = 0;   // estimate for the first advection step, from the uploaded state
+    double v0max[2] = {0.0, 0.0};  // largest uploaded |v| per fluid
     std::string err;
 };
 
@@ -906,6 +908,13 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
     }
     double* f = (double*)P->stage;
     int32_t* ib = (int32_t*)(f + 9 * cn);
+    s->v0max[0] = s->v0max[1] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v2 = 0.0;
+        for (int a = 0; a < d; ++a) v2 += vel[i * d + a] * vel[i * d + a];
+        double& vm = s->v0max[phase[i] & 1];
+        vm = std::max(vm, std::sqrt(v2));
+    }
     double* dst[9] = {P->A.pos[0], P->A.pos[1], P->A.pos[2], P->A.vel[0], P->A.vel[1], P->A.vel[2],
                       P->A.mass, P->A.rho, P->A.drho};
     for (int64_t i0 = 0; i0 < n; i0 += cn) {
@@ -937,6 +946,23 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
     }
 }
 
+// Substeps of an advection step that starts from the per-fluid |v| maxima
+// given: the advection step over the acoustic step of Eqs. 16-18, as the
+// device takes them at the start of the step.  A scheduling estimate only:
+// the device decides every step, and the acoustic step changes as the
+// velocities do.
+long long first_step_estimate(const SysConst& S, const double* vmax)
+{
+    double dt_ad = INFINITY, dt_ac = INFINITY;
+    for (int f = 0; f < 2; ++f) {
+        const double a = vmax[f] > 0.0 ? S.h / vmax[f] : INFINITY;
+        dt_ad = std::min(dt_ad, std::min(S.cfl_ad * a, S.dtad_visc[f]));
+        dt_ac = std::min(dt_ac, std::min(S.cfl_ac * (S.h / (S.c0 + vmax[f])), S.dtac_surf[f]));
+    }
+    if (!std::isfinite(dt_ad) || !(dt_ac > 0.0)) return 1;
+    return (long long)std::min(1e6, std::max(1.0, std::ceil(dt_ad / dt_ac)));
+}
+
 void reset_dyn(rsph_system* s, bool keep_clock)
 {
     rsph_pool* P = s->pool;
@@ -959,6 +985,7 @@ void reset_dyn(rsph_system* s, bool keep_clock)
     s->seen_outer = d.n_outer;
     s->seen_sub = d.n_sub;
     if (!keep_clock) s->sps = 0;
+    s->first_sps = first_step_estimate(s->sc, s->v0max);
     HIPCHECK(hipMemcpy(P->A.sd + s->row, &d, sizeof(SysDyn), hipMemcpyHostToDevice));
 }
 
@@ -1562,7 +1589,7 @@ rsph_status rsph_step_counts(const rsph_system* s, int64_t* n_outer, int64_t* n_
     if (!s || !n_outer || !n_sub || !substeps_per_step) return RSPH_EINVAL;
     *n_outer = s->seen_outer;
     *n_sub = s->seen_sub;
-    *substeps_per_step = s->sps;
+    *substeps_per_step = s->sps > 0 ? s->sps : (s->seen_outer == 0 ? s->first_sps : 0);
     return RSPH_OK;
 }
 

@@ -257,8 +257,9 @@ class System:
 
     def step_counts(self):
         """Advection steps, acoustic substeps, and the most substeps one of the
-        recent advection steps needed (0 until known), as of the end of the
-        last stepping call (host-side; no device access)."""
+        recent advection steps needed (before the first step an estimate for
+        it; after it 0 until a later step is seen), as of the end of the last
+        stepping call (host-side; no device access)."""
         out = [C.c_int64() for _ in range(3)]
         _check(lib().rsph_step_counts(self.h, *[C.byref(o) for o in out]), self.h)
         return {"n_outer": out[0].value, "n_sub": out[1].value, "substeps_per_step": out[2].value}

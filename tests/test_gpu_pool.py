@@ -197,19 +197,23 @@ def test_serving_loop_continuous_batching(max_steps_per_tick):
 
 def test_step_counts_follow_the_device_counts():
     """The host-side counts of a pool member equal its observables after each
-    stepping call; substeps per step stay unknown (0) until a step after the
-    first one (from rest) has been seen."""
+    stepping call.  Before the first step the substeps per step estimate that
+    step (from rest: the viscous criterion over the acoustic one); after it
+    they stay unknown (0) until a later step has been seen."""
     from paper_2503_16082_amd import serve
     descs = WL.served_mix(n_jobs=2, seed=4, n_min=2000, n_max=6000)
     pool = rsph.Pool(2, precision=1)
     ws = [serve.build_job(d) for d in descs]
     members = [pool.admit(w["params"], w["pos"], w["vel"], w["phase"]) for w in ws]
     assert [m.step_counts()["n_outer"] for m in members] == [0, 0]
+    est = [m.step_counts()["substeps_per_step"] for m in members]
     pool.step(members, [1, 1])
-    for m in members:
+    for m, e in zip(members, est):
         c, o = m.step_counts(), m.observables()
         assert (c["n_outer"], c["n_sub"]) == (o["n_outer"], o["n_sub"]) == (1, c["n_sub"])
         assert c["substeps_per_step"] == 0
+        say("first step: estimate", e, "substeps", c["n_sub"])
+        assert 0.8 <= c["n_sub"] / e <= 1.25
     pool.step(members, [2, 3])
     for m, n in zip(members, [3, 4]):
         c, o = m.step_counts(), m.observables()
