@@ -365,6 +365,34 @@ def test_static_droplet_3d_full_size_subset(precision):
     compare_rates(g, ref, precision, f"c3subset/p{precision}", targets=targets)
 
 
+def test_static_droplet_3d_mixed_against_fp64_along_the_run():
+    """262,144 particles, at the states that the FP64 path reaches after 1, 10,
+    100, 1,000 and 2,000 advection steps from the workload's start: one
+    evaluation of every rate in the mixed form against the FP64 form at the
+    same state, all particles, to the mixed form's tolerance.  The reference
+    here is the FP64 GPU path, which the oracle pins at the start; no GPU state
+    is handed to the oracle."""
+    w = WL.static_droplet_3d(n_side=64, R=0.25, seed=0)
+    p = w["params"]
+    s = rsph.System(p, precision=0)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    done = 0
+    for k in (1, 10, 100, 1000, 2000):
+        s.step(k - done)
+        done = k
+        pos, vel, rho, mass = (s.read(f) for f in ("pos", "vel", "rho", "mass"))
+        say(f"3D along the run: step {k}, max |v| {np.abs(vel).max():.3e}")
+        g64 = gpu_rates(p, pos, vel, rho, mass, w["phase"], 0)
+        g32 = gpu_rates(p, pos, vel, rho, mass, w["phase"], 1)
+        errs = {f: normwise(g32[f], g64[f]) for f in FIELDS}
+        say(f"step {k}", " ".join(f"{f}={e:.2e}" for f, e in errs.items()))
+        for f, e in errs.items():
+            assert e <= TOL[1], (k, f, e)
+        assert np.array_equal(g32["nnb"], g64["nnb"])
+    assert s.observables()["health"] == 0
+    s.close()
+
+
 @pytest.mark.parametrize("precision", [1])
 def test_droplet_impact_full_size_sampled(precision):
     """8,388,608 particles; parity on 2,000 sampled particles, half of them
