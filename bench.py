@@ -329,7 +329,7 @@ def served(args):
     probe_steps = args.probe_steps or args.steps_per_job
     cap = args.max_steps_per_tick
     ps = serve.serve(probe, steps_per_job=probe_steps, rate_hz=None, budget_bytes=budget, precision=prec,
-                     max_steps_per_tick=cap)
+                     max_steps_per_tick=cap, max_admits_per_tick=args.max_admits_per_tick)
     n_side = [max(3, int(round(math.sqrt(d["n"])))) for d in descs]
     work_per_job = float(np.mean([k * k for k in n_side])) * args.steps_per_job
     rate_sat = ps["particle_steps_per_s"] / work_per_job
@@ -337,7 +337,8 @@ def served(args):
         f"{rate_sat:.3f} jobs/s at {args.steps_per_job} steps per job")
     rate = 0.8 * rate_sat
     out = serve.serve(descs, steps_per_job=args.steps_per_job, rate_hz=rate, budget_bytes=budget,
-                      precision=prec, log=log, max_steps_per_tick=cap)
+                      precision=prec, log=log, max_steps_per_tick=cap,
+                      max_admits_per_tick=args.max_admits_per_tick)
     line = {
         "metric": "served particle-steps/s with p50/p99 per-step latency",
         "value": out["particle_steps_per_s"],
@@ -349,7 +350,8 @@ def served(args):
         "data": "synthetic",
         "config": {"workload": "served_mix", "jobs": args.jobs, "steps_per_job": args.steps_per_job,
                    "particles_per_job": "log-uniform 2,000-200,000", "arrival_rate_hz": rate,
-                   "hbm_budget_bytes": budget, "form": args.precision, "max_steps_per_tick": cap},
+                   "hbm_budget_bytes": budget, "form": args.precision, "max_steps_per_tick": cap,
+                   "max_admits_per_tick": args.max_admits_per_tick},
         "step_latency_p50_ms": out["step_latency_p50_ms"],
         "step_latency_p99_ms": out["step_latency_p99_ms"],
         "tick_latency_p50_ms": out["tick_latency_p50_ms"],
@@ -380,6 +382,8 @@ def main():
     ap.add_argument("--probe-jobs", type=int, default=24, help="served: jobs of the saturation probe")
     ap.add_argument("--probe-steps", type=int, default=None,
                     help="served: steps per probe job (default: the stream's steps per job)")
+    ap.add_argument("--max-admits-per-tick", type=int, default=0,
+                    help="served: most admissions between two ticks (0: as many as the budget holds)")
     ap.add_argument("--max-steps-per-tick", type=int, default=4,
                     help="served: most advection steps a job takes per scheduler tick (1: lockstep)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])

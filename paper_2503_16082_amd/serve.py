@@ -54,9 +54,11 @@ def steps_this_tick(sps, left, cap):
 
 
 def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, precision=rsph.MIXED,
-          log=None, keep_results=False, max_seconds=None, max_steps_per_tick=1):
+          log=None, keep_results=False, max_seconds=None, max_steps_per_tick=1, max_admits_per_tick=0):
     """Runs the request loop to completion.  rate_hz: Poisson arrival rate
-    (None: all jobs arrive at t = 0).  Returns a summary dictionary."""
+    (None: all jobs arrive at t = 0).  max_admits_per_tick > 0 bounds the
+    admissions between two ticks (each one stalls the running jobs).  Returns a
+    summary dictionary."""
     rng = np.random.Generator(np.random.PCG64(12345))
     n_jobs = len(job_descs)
     if rate_hz:
@@ -83,7 +85,8 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
             queue.append(next_arrival)
             next_arrival += 1
         # admission, first come first served, as long as the budget allows
-        while queue:
+        admitted = 0
+        while queue and (max_admits_per_tick <= 0 or admitted < max_admits_per_tick or not active):
             k = queue[0]
             w = built[k]
             try:
@@ -93,6 +96,7 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
                     break
                 raise
             queue.popleft()
+            admitted += 1
             active[k] = [s, 0, w["pos"].shape[0], time.perf_counter()]
         queue_depth.append(len(queue))
         if not active:
