@@ -119,6 +119,10 @@ struct rsph_pool {
     // pinned host staging of particle uploads (hipHostMalloc), grown on demand
     char* stage = nullptr;
     size_t stage_bytes = 0;
+    // pinned host copies of the per-system state and targets, grown on demand
+    SysDyn* pin_dyn = nullptr;
+    long long* pin_targets = nullptr;
+    size_t pin_rows = 0;
 };
 
 struct rsph_system {
@@ -645,12 +649,31 @@ void rebuild(rsph_pool* P, int mode, int64_t group)
     launch_neighbours(L, A, t.ev);
 }
 
+// pinned host rows for the per-system state and targets (no copy may be in
+// flight from or to them: every stepping call ends with a stream sync)
+void ensure_pinned_rows(rsph_pool* P, size_t rows)
+{
+    if (rows <= P->pin_rows) return;
+    if (P->pin_dyn) HIPCHECK(hipHostFree(P->pin_dyn));
+    if (P->pin_targets) HIPCHECK(hipHostFree(P->pin_targets));
+    P->pin_dyn = nullptr;
+    P->pin_targets = nullptr;
+    P->pin_rows = 0;
+    const size_t n = std::max<size_t>(rows, 64);
+    HIPCHECK(hipHostMalloc((void**)&P->pin_dyn, sizeof(SysDyn) * n, hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void**)&P->pin_targets, sizeof(long long) * n, hipHostMallocDefault));
+    P->pin_rows = n;
+}
+
 std::vector<SysDyn> read_dyn(rsph_pool* P)
 {
     std::vector<SysDyn> d(P->systems.size());
+    if (!d.empty()) {
+        ensure_pinned_rows(P, d.size());
+        HIPCHECK(hipMemcpyAsync(P->pin_dyn, P->A.sd, sizeof(SysDyn) * d.size(), hipMemcpyDeviceToHost, P->stream));
+    }
     HIPCHECK(hipStreamSynchronize(P->stream));
-    if (!d.empty())
-        HIPCHECK(hipMemcpy(d.data(), P->A.sd, sizeof(SysDyn) * d.size(), hipMemcpyDeviceToHost));
+    if (!d.empty()) std::memcpy(d.data(), P->pin_dyn, sizeof(SysDyn) * d.size());
     return d;
 }
 
@@ -834,10 +857,15 @@ uint32_t run_to_targets(rsph_pool* P, std::vector<long long> left)
     }
 }
 
+// new targets, copied in stream order (the pinned rows are free: the last
+// stepping call ended with a stream sync)
 void set_targets(rsph_pool* P, const std::vector<long long>& targets)
 {
-    HIPCHECK(hipStreamSynchronize(P->stream));
-    HIPCHECK(hipMemcpy(P->d_targets, targets.data(), sizeof(long long) * targets.size(), hipMemcpyHostToDevice));
+    if (targets.empty()) return;
+    ensure_pinned_rows(P, targets.size());
+    std::memcpy(P->pin_targets, targets.data(), sizeof(long long) * targets.size());
+    HIPCHECK(hipMemcpyAsync(P->d_targets, P->pin_targets, sizeof(long long) * targets.size(),
+                            hipMemcpyHostToDevice, P->stream));
     launch_set_targets(launch_of(P), P->A, P->d_targets);
 }
 
@@ -1047,6 +1075,8 @@ void destroy_pool(rsph_pool* P)
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     free_arrays(P);
     if (P->stage) (void)hipHostFree(P->stage);
+    if (P->pin_dyn) (void)hipHostFree(P->pin_dyn);
+    if (P->pin_targets) (void)hipHostFree(P->pin_targets);
     if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
 }
@@ -1548,7 +1578,10 @@ rsph_status rsph_pool_step(rsph_pool* P, rsph_system* const* systems, const int6
     if (!P) return RSPH_EINVAL;
     return guarded(&P->err, [&] {
         if (count < 0 || (count > 0 && (!systems || !n_outer))) fail(RSPH_EINVAL, "bad arguments");
-        std::vector<SysDyn> d = read_dyn(P);
+        // advection steps done, as the host last read them: every stepping
+        // call ends with a read, and a reset sets them
+        std::vector<long long> done(P->systems.size());
+        for (size_t r = 0; r < done.size(); ++r) done[r] = P->systems[r]->seen_outer;
         std::vector<long long> targets(P->systems.size(), -1);
         int64_t most = 0;
         for (int k = 0; k < count; ++k) {
@@ -1556,16 +1589,16 @@ rsph_status rsph_pool_step(rsph_pool* P, rsph_system* const* systems, const int6
             if (!s || s->pool != P || s->row < 0) fail(RSPH_EINVAL, "system is not in this pool");
             if (s->faulted) fail(RSPH_ESTATE, "a system of the batch is faulted");
             if (n_outer[k] < 0) fail(RSPH_EINVAL, "n_outer must be >= 0");
-            const long long base = targets[s->row] >= 0 ? targets[s->row] : d[s->row].n_outer;
+            const long long base = targets[s->row] >= 0 ? targets[s->row] : done[s->row];
             targets[s->row] = base + n_outer[k];
-            most = std::max<int64_t>(most, targets[s->row] - d[s->row].n_outer);
+            most = std::max<int64_t>(most, targets[s->row] - done[s->row]);
             s->rates_valid = false;
         }
         if (most == 0) return;
         set_targets(P, targets);
         std::vector<long long> left(P->systems.size(), 0);
         for (size_t r = 0; r < left.size(); ++r)
-            if (targets[r] >= 0) left[r] = targets[r] - d[r].n_outer;
+            if (targets[r] >= 0) left[r] = targets[r] - done[r];
         const uint32_t h = run_to_targets(P, left);
         if (h & kFaultBits) {
             std::vector<SysDyn> dd = read_dyn(P);
