@@ -258,6 +258,7 @@ def run_gpu(w, precision, steps, warmup, timed_kernels, launch="graph"):
         "near_pairs": float(nnb[(flags & 2) != 0].sum()),
         "near": float(((flags & 2) != 0).sum()),
         "obs": o1,
+        "momentum": (np.asarray(o0["momentum"], dtype=np.float64), np.asarray(o1["momentum"], dtype=np.float64)),
     }
 
 
@@ -502,6 +503,12 @@ def main():
         },
         "particle_substeps_per_s": n * r["substeps"] / secs,
         "substeps_per_step": r["substeps"] / args.steps,
+        # total momentum over the timed steps: |P(end) - P(start)|, and, for the
+        # impact (which carries the drop's momentum), that relative to |P(start)|
+        "momentum_change": float(np.linalg.norm(r["momentum"][1] - r["momentum"][0])),
+        "momentum_drift": (float(np.linalg.norm(r["momentum"][1] - r["momentum"][0])
+                                 / np.linalg.norm(r["momentum"][0]))
+                           if args.workload == "impact3d" else None),
         "roofline": {
             "bound": "hbm",
             "kernel": "force pass (k_force)",
