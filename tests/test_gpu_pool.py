@@ -169,12 +169,12 @@ def test_invalid_particles_rejected():
     s.close()
 
 
-@pytest.mark.parametrize("max_steps_per_tick", [1, 4])
-def test_serving_loop_continuous_batching(max_steps_per_tick):
+@pytest.mark.parametrize("max_steps_per_tick,max_admits", [(1, 0), (4, 0), (4, 1)])
+def test_serving_loop_continuous_batching(max_steps_per_tick, max_admits):
     """Poisson arrivals into a budget that cannot hold every job at once: all
     jobs finish, the queue was used, and every job's result equals the same
     job run alone, whether each tick steps every job once or gives jobs with
-    fewer substeps per step more steps."""
+    fewer substeps per step more steps, and with admissions one per tick."""
     from paper_2503_16082_amd import serve
     descs = WL.served_mix(n_jobs=6, seed=3, n_min=2000, n_max=9000)
     probe = rsph.Pool(2, precision=1)
@@ -184,7 +184,8 @@ def test_serving_loop_continuous_batching(max_steps_per_tick):
     probe.close()
     steps = 4 if max_steps_per_tick == 1 else 12
     out = serve.serve(descs, steps_per_job=steps, rate_hz=200.0, budget_bytes=int(one * 4),
-                      precision=1, keep_results=True, max_steps_per_tick=max_steps_per_tick)
+                      precision=1, keep_results=True, max_steps_per_tick=max_steps_per_tick,
+                      max_admits_per_tick=max_admits)
     say({k: v for k, v in out.items() if k != "results"})
     assert out["jobs"] == 6 and out["max_queue_depth"] >= 1
     assert out["step_latency_p99_ms"] >= out["step_latency_p50_ms"] > 0
