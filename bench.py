@@ -459,16 +459,21 @@ def main():
 
     extra = {}
     if prec == rsph.MIXED and not args.no_fp64_compare:
-        s64, r64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, [])
-        s64.close()
-        v64 = n * args.steps / r64["seconds"]
-        s64, rt64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, ["force"])
-        s64.close()
-        l64, m64 = rt64["timing"]["force"]
-        extra["fp64_gpu_value"] = v64
-        extra["mixed_over_fp64"] = value / v64
-        extra["fp64_force_avg_us"] = m64 / max(l64, 1) * 1e3
-        log(f"fp64 gpu {r64['seconds']:.3f}s -> {v64:.3e} particle-steps/s, mixed/fp64 = {value / v64:.2f}")
+        try:
+            s64, r64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, [])
+            s64.close()
+            v64 = n * args.steps / r64["seconds"]
+            s64, rt64 = run_gpu(w, rsph.FP64, args.steps, args.warmup, ["force"])
+            s64.close()
+            l64, m64 = rt64["timing"]["force"]
+            extra["fp64_gpu_value"] = v64
+            extra["mixed_over_fp64"] = value / v64
+            extra["fp64_force_avg_us"] = m64 / max(l64, 1) * 1e3
+            log(f"fp64 gpu {r64['seconds']:.3f}s -> {v64:.3e} particle-steps/s, mixed/fp64 = {value / v64:.2f}")
+        except rsph.RsphError as e:  # a health check of the FP64 run: reported, not timed
+            extra["fp64_gpu_value"] = None
+            extra["fp64_fault"] = str(e)
+            log(f"fp64 gpu run stopped: {e}")
     if not args.no_accel_check:
         try:
             extra["accel_err_vs_fp64_oracle"] = accel_error(w, prec)
