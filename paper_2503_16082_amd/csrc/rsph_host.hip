@@ -536,6 +536,7 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
         for (int64_t c = s->c_off; c < s->c_off + s->ncells; ++c) csys[c] = k;
     }
     A.nsys = S;
+    A.one_sys_waves = S == 1 ? (int32_t)(L.p_cap[0] / kWave) : 0;
     if (S) {
         HIPCHECK(hipMemcpyAsync((void*)A.sc, sc.data(), sizeof(SysConst) * S, hipMemcpyHostToDevice, st));
         HIPCHECK(hipMemcpyAsync(A.sd, sd.data(), sizeof(SysDyn) * S, hipMemcpyHostToDevice, st));

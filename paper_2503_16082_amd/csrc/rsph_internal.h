@@ -127,12 +127,12 @@ struct SysDyn {
 };
 
 struct DevArrays {
-    int64_t P;       // slot capacity (multiple of 256)
-    int64_t C;       // global cell capacity
+    int64_t P;       // slots the kernels cover (multiple of 256; the arrays may hold more)
+    int64_t C;       // global cells the kernels cover
     int32_t kmax;
     int32_t mode;    // 0 = step, 1 = evaluate rates only (no state update)
     int32_t dt_pass; // 1: some system's substeps are ended by the separate substep pass
-    int32_t pad1;
+    int32_t one_sys_waves;  // pool of one system: its 64-slot blocks (0 otherwise)
     // FP64 state, structure of arrays
     double* pos[3];
     double* vel[3];
@@ -169,7 +169,7 @@ struct DevArrays {
     uint8_t* flags;
     uint32_t* nbr;
     int32_t* ncount;
-    double* xd;      // frozen FP64 position {x, y, z, 0} per slot, read by the density summation
+    double* xd;      // frozen FP64 position {x, y, z, phase} per slot, read by the density summation
     // rates written by an evaluation (FP64, slot order)
     double* r_acc;    // 3 * P
     double* r_accp;

@@ -41,6 +41,14 @@ __device__ __forceinline__ int64_t logical_block()
     return (b & 7) * per + (b >> 3);
 }
 
+// system of the 64-slot block w (-1: none): from the per-wave table, or
+// without a load when the pool holds a single system
+__device__ __forceinline__ int system_of_wave(const DevArrays& A, int64_t w)
+{
+    if (A.one_sys_waves > 0) return w < A.one_sys_waves ? 0 : -1;
+    return A.wave_sys[w];
+}
+
 struct Slot {
     int64_t i;   // slot index
     int s;       // system (wave-uniform), -1 if none
@@ -54,7 +62,7 @@ __device__ __forceinline__ Slot slot_of(const DevArrays& A)
     c.s = -1;
     c.lane = false;
     if (c.i >= A.P) return c;
-    int s = A.wave_sys[c.i >> 6];
+    int s = system_of_wave(A, c.i >> 6);
     s = __builtin_amdgcn_readfirstlane(s);
     c.s = s;
     if (s < 0) return c;
@@ -315,7 +323,7 @@ __device__ __forceinline__ Slot lookup_slot(const DevArrays& A, int64_t i)
     Slot c;
     c.i = i;
     c.lane = false;
-    const int s = A.wave_sys[__builtin_amdgcn_readfirstlane((int)(i >> 6))];
+    const int s = system_of_wave(A, __builtin_amdgcn_readfirstlane((int)(i >> 6)));
     c.s = s;
     if (s < 0) return c;
     const SysConst& S = A.sc[s];
@@ -2047,7 +2055,7 @@ __global__ __launch_bounds__(kWave) void k_obs_partial(DevArrays A, int pass)
     const int64_t w = blockIdx.x;
     const int64_t i = w * kWave + threadIdx.x;
     if (i >= A.P) return;
-    int s = A.wave_sys[w];
+    int s = system_of_wave(A, w);
     s = __builtin_amdgcn_readfirstlane(s);
     if (s < 0) return;
     const SysConst& S = A.sc[s];
