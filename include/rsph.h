@@ -237,8 +237,10 @@ const char* rsph_last_error(const rsph_system* sys);
 
 /* A pool packs the particles of many systems of one dimension and one
  * precision into shared device arrays and steps them together in the same
- * launches, each system with its own parameters and time steps.  hbm_budget
- * bounds the device memory the pool may hold. */
+ * launches, each system with its own parameters and time steps.
+ * hbm_budget_bytes bounds the device memory the pool may hold (0: no bound); a
+ * pool with a bound takes all of it at its first admission, so that later
+ * admissions seldom reallocate. */
 rsph_status rsph_pool_create(int32_t dim, int32_t precision, size_t hbm_budget_bytes,
                              void* hip_stream, rsph_pool** out);
 /* Admits a system with its particles (as rsph_set_particles).  EBUSY if the
@@ -252,7 +254,8 @@ rsph_status rsph_pool_admit(rsph_pool* pool, const rsph_params* params, int64_t 
  * progress in the same launches until each has done its own count. */
 rsph_status rsph_pool_step(rsph_pool* pool, rsph_system* const* systems, const int64_t* n_outer,
                            int32_t count);
-/* Bytes of device memory the pool holds now. */
+/* Bytes of device memory the pool holds now (with a budget: the budget's worth
+ * once the first system is admitted). */
 size_t rsph_pool_bytes(const rsph_pool* pool);
 /* Counts of a system (standalone or in a pool) as of the end of its last
  * stepping call, held on the host (no device access): advection steps and
@@ -265,7 +268,10 @@ size_t rsph_pool_bytes(const rsph_pool* pool);
  * call.  EINVAL on a NULL argument. */
 rsph_status rsph_step_counts(const rsph_system* sys, int64_t* n_outer, int64_t* n_sub,
                              int64_t* substeps_per_step);
+/* Removes a system from its pool and frees its slots; the systems packed after
+ * it move down.  sys is invalid afterwards. */
 rsph_status rsph_pool_release(rsph_pool* pool, rsph_system* sys);
+/* Frees the pool and every system still in it. */
 void rsph_pool_destroy(rsph_pool* pool);
 
 #ifdef __cplusplus
