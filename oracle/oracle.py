@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# RSPH_ORACLE_LIB points the binding at another build of the same source
+LIB_PATH = os.environ.get("RSPH_ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 
 NO_PENALTY = 1
 NO_SHIFT = 2

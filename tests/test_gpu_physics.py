@@ -18,6 +18,8 @@ import pytest
 from oracle import oracle as O
 from paper_2503_16082_amd import workloads as WL
 
+from physics_util import measured_period, theory_period, trace
+
 pytestmark = pytest.mark.gpu
 
 rsph = pytest.importorskip("paper_2503_16082_amd.rsph")
@@ -26,38 +28,6 @@ rsph = pytest.importorskip("paper_2503_16082_amd.rsph")
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def deformation(o):
-    m = o["moment2"]
-    return (m[0, 0] - m[1, 1]) / (m[0, 0] + m[1, 1])
-
-
-def theory_period(R, rho_k, gamma):
-    return 2.0 * math.pi * math.sqrt(R ** 3 * rho_k / (6.0 * gamma))
-
-
-def measured_period(ts, ds, tau):
-    cross = []
-    for k in range(1, len(ts)):
-        if ts[k] < 0.2 * tau:
-            continue
-        if (ds[k - 1] > 0) != (ds[k] > 0):
-            f = ds[k - 1] / (ds[k - 1] - ds[k])
-            cross.append(ts[k - 1] + f * (ts[k] - ts[k - 1]))
-    assert len(cross) >= 2, cross
-    return 2.0 * (cross[-1] - cross[0]) / (len(cross) - 1)
-
-
-def trace(stepper, observe, t_end, every=5):
-    ts, ds = [0.0], [deformation(observe())]
-    while ts[-1] < t_end:
-        stepper(every)
-        o = observe()
-        assert o.get("health", 0) == 0
-        ts.append(o["t"])
-        ds.append(deformation(o))
-    return ts, ds
 
 
 def gpu_period(w, precision, tau):
