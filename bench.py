@@ -4,11 +4,19 @@ A step is one advection step of the dual-criteria scheme: rebinning, neighbour
 lists, density summation, viscous acceleration, correction matrix and position
 shift, then every acoustic substep (colour gradient, Riemann pressure with the
 surface stress and penalty force, kick, continuity) until the advection step is
-covered.  The default workload is the 2D square droplet relaxing to a circle:
-periodic unit square, dp = 1/200 (40,000 particles), a square of side 0.4 of
-fluid k, density ratio 1000 and viscosity ratio 100, gamma = 1, in the mixed
-precision form (FP32 pair loops, FP64 state).  Inputs are synthetic and already
-resident in device memory when the timed region starts.
+covered.  The default workload is the largest single-GPU one: the 3D droplet
+impact onto a liquid pool, 8,388,608 particles (drop D = 1 at 32 particles per
+unit length, pool depth 2 in an 8 x 8 x 4 air-filled periodic box, density
+ratio 1000, viscosity ratio 100, Re = 1e4, We = 2.5e4), in the mixed precision
+form (FP32 pair loops, FP64 state), with the penalty force on.  Inputs are
+synthetic and already resident in device memory when the timed region starts.
+
+The same run also measures the FP64 form on the same steps, the single-step
+acceleration error of the mixed and FP64 forms against the FP64 oracle on a
+sample chosen from the inputs, the FP64 oracle itself on the host cores (one
+advection step of the same workload), and the served form: a stream of 256 2D
+droplet jobs admitted by HBM budget into one pool, with p50/p99 per-step
+latency.
 
 Prints ONE JSON line.  Everything else goes to stderr.
 """
@@ -29,8 +37,14 @@ sys.path.insert(0, ROOT)
 from paper_2503_16082_amd import rsph  # noqa: E402
 from paper_2503_16082_amd import workloads as WL  # noqa: E402
 
-# Published MI355X peaks used for the roofline (dense vector arithmetic).
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# MI355X vector peaks for the ALU fraction.  The published FP32 figure
+# (157.3 TFLOP/s) needs packed FP32 instructions, which this build does not
+# generate (-packed-fp32-ops), so FP32 is priced at the non-packed rate:
+# 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s, the FP64 rate.
+PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+# working sets below this are served from the 256 MB Infinity Cache, where an
+# HBM fraction is no evidence of HBM use
+MALL_BYTES = 256 << 20
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic operations per neighbour pair of the force pass (Riemann pressure,
@@ -262,9 +276,40 @@ def run_gpu(w, precision, steps, warmup, timed_kernels, launch="graph"):
     }
 
 
-def accel_error(w, precision):
-    """Normwise single-evaluation acceleration error of a GPU form against the
-    FP64 oracle at the workload's initial state."""
+def rate_errors(a, ref):
+    """Single-evaluation error of an acceleration field against the oracle's:
+    the normwise max_i |a_i - a_i^ref| / max_i |a_i^ref|, and the per-particle
+    |a_i - a_i^ref| / |a_i^ref| over the particles with |a_i^ref| >= 1e-3 of the
+    largest (its maximum and 99th percentile)."""
+    d = np.linalg.norm(a - ref, axis=1)
+    r = np.linalg.norm(ref, axis=1)
+    big = r >= 1e-3 * r.max()
+    rel = d[big] / r[big]
+    return {"normwise": float(d.max() / r.max()), "per_particle_max": float(rel.max()),
+            "per_particle_p99": float(np.percentile(rel, 99))}
+
+
+def input_sample(w, n, seed=0):
+    """Particles chosen from the inputs alone: every lattice particle whose
+    unjittered site lies within 3h of the drop's or the pool's surface, or a
+    random half of them if there are more than n / 2, plus n / 2 drawn at
+    random from all particles."""
+    rng = np.random.default_rng(seed)
+    p = w["params"]
+    h = p["dp"] * p.get("h_over_dp", 1.3)
+    pos = w["pos"]
+    near = np.abs(np.linalg.norm(pos - w["centre"], axis=1) - w["R"]) < 3 * h
+    near |= np.abs(pos[:, 2] - w["pool_depth"]) < 3 * h
+    near = np.where(near)[0]
+    if len(near) > n // 2:
+        near = rng.choice(near, n // 2, replace=False)
+    return np.unique(np.concatenate([near, rng.choice(pos.shape[0], n // 2, replace=False)]))
+
+
+def accel_error(w, precision, sample=4096):
+    """Acceleration error of a GPU form against the FP64 oracle at the
+    workload's initial state; above 300,000 particles the oracle evaluates a
+    sample chosen from the inputs (input_sample)."""
     from oracle import oracle as O
     p = w["params"]
     s = rsph.System(p, precision=precision)
@@ -275,49 +320,88 @@ def accel_error(w, precision):
     s.close()
     n = pos.shape[0]
     targets = None
-    if n > 300000:  # the oracle evaluates a sample, half of it near the interface
-        rng = np.random.default_rng(0)
-        gc = np.linalg.norm(acc, axis=1)
-        top = np.argsort(gc)[-2048:]
-        targets = np.unique(np.concatenate([rng.choice(n, 2048, replace=False), top]))
+    if n > 300000:
+        targets = input_sample(w, sample)
         acc = acc[targets]
     ref = O.eval_rates(p, O.wrap(p, pos), vel, rho, mass, w["phase"], targets=targets)["acc"]
-    return float(np.abs(acc - ref).max() / np.abs(ref).max())
+    out = rate_errors(acc, ref)
+    out["particles"] = int(n if targets is None else len(targets))
+    return out
+
+
+def host_cpu():
+    """CPU model and the OpenMP threads the oracle runs with."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return model, threads
+
+
+def mem_available_bytes():
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemAvailable:"):
+                return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return 0
+
+
+# host bytes the oracle holds per particle while it steps: its frozen pair
+# geometry (index, r_ij, |r_ij|, W, W' = 56 B per pair) and per-particle arrays
+ORACLE_BYTES = {2: 56 * 30 + 600, 3: 56 * 100 + 800}
 
 
 def cpu_baseline(w, min_seconds, max_steps=5000):
     """The FP64 oracle, untuned, on the host cores: a bounded sample of the same
-    workload, its first advection steps, taken until at least min_seconds of
-    host time have passed (at most max_steps)."""
+    workload, its first advection steps.  Below a million particles whole
+    advection steps are taken (five at a time) until at least min_seconds of
+    host time have passed; above, exactly one advection step of the full
+    workload, after checking that the host has the memory for it."""
     from oracle import oracle as O
     p = w["params"]
-    st = O.State(p, w["pos"], w["vel"], w["phase"])
+    n = w["pos"].shape[0]
+    dim = p["dim"]
+    model, threads = host_cpu()
+    need = ORACLE_BYTES[dim] * n
+    avail = mem_available_bytes()
+    if avail and need > 0.8 * avail:
+        return {"value": None, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+                "cpu_model": model,
+                "sample": f"not run: the oracle needs ~{need / 2**30:.0f} GiB, {avail / 2**30:.0f} GiB available"}
+    st = O.State(p, O.wrap(p, w["pos"]), w["vel"], w["phase"])
+    chunk = 5 if n < 1_000_000 else 1
     outer_steps = 0
     t0 = time.perf_counter()
     while True:
-        st.step(5)
-        outer_steps += 5
+        st.step(chunk)
+        outer_steps += chunk
         dt = time.perf_counter() - t0
-        if dt >= min_seconds or outer_steps >= max_steps:
+        if chunk == 1 or dt >= min_seconds or outer_steps >= max_steps:
             break
-    n = w["pos"].shape[0]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": n * outer_steps / dt,
         "unit": "particle-steps/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"first {outer_steps} advection steps ({int(st.clock.n_sub)} substeps) of the "
-                  f"same workload, {n} particles, {dt:.1f} s",
+        "cpu_model": model,
+        "sample": f"first {outer_steps} advection step(s) ({int(st.clock.n_sub)} substeps) of the "
+                  f"same workload, all {n} particles, {dt:.1f} s on {threads} OpenMP threads",
         "particle_substeps_per_s": n * st.clock.n_sub / dt,
     }
 
 
-def served(args):
+def served_leg(args, log_jobs=False):
     """Served form on the mixed droplet stream: the saturated job rate is taken
     from a probe batch that arrives all at once; the full stream then arrives
     as a Poisson process at 0.8 of that rate into a pool with a fixed HBM
-    budget.  Prints one JSON line."""
+    budget.  Returns the summary."""
     from paper_2503_16082_amd import serve
     prec = rsph.MIXED if args.precision == "mixed" else rsph.FP64
     descs = WL.served_mix(n_jobs=args.jobs, seed=0)
@@ -338,8 +422,18 @@ def served(args):
         f"{rate_sat:.3f} jobs/s at {args.steps_per_job} steps per job")
     rate = 0.8 * rate_sat
     out = serve.serve(descs, steps_per_job=args.steps_per_job, rate_hz=rate, budget_bytes=budget,
-                      precision=prec, log=log, max_steps_per_tick=cap,
+                      precision=prec, log=log if log_jobs else None, max_steps_per_tick=cap,
                       max_admits_per_tick=args.max_admits_per_tick)
+    out.update({"arrival_rate_hz": rate, "saturated_job_rate_hz": rate_sat, "hbm_budget_bytes": budget,
+                "jobs_in_stream": args.jobs, "steps_per_job": args.steps_per_job,
+                "particles_per_job": "log-uniform 2,000-200,000", "form": args.precision})
+    return out
+
+
+def served(args):
+    """--workload served: the served leg alone, as its own JSON line."""
+    out = served_leg(args, log_jobs=True)
+    prec = rsph.MIXED if args.precision == "mixed" else rsph.FP64
     line = {
         "metric": "served particle-steps/s with p50/p99 per-step latency",
         "value": out["particle_steps_per_s"],
@@ -350,21 +444,16 @@ def served(args):
         "dtype": "f32" if prec == rsph.MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": "served_mix", "jobs": args.jobs, "steps_per_job": args.steps_per_job,
-                   "particles_per_job": "log-uniform 2,000-200,000", "arrival_rate_hz": rate,
-                   "hbm_budget_bytes": budget, "form": args.precision, "max_steps_per_tick": cap,
+                   "particles_per_job": "log-uniform 2,000-200,000", "arrival_rate_hz": out["arrival_rate_hz"],
+                   "hbm_budget_bytes": out["hbm_budget_bytes"], "form": args.precision,
+                   "max_steps_per_tick": args.max_steps_per_tick,
                    "max_admits_per_tick": args.max_admits_per_tick},
-        "step_latency_p50_ms": out["step_latency_p50_ms"],
-        "step_latency_p99_ms": out["step_latency_p99_ms"],
-        "tick_latency_p50_ms": out["tick_latency_p50_ms"],
-        "tick_latency_p99_ms": out["tick_latency_p99_ms"],
-        "step_interval_p50_ms": out["step_interval_p50_ms"],
-        "step_interval_p99_ms": out["step_interval_p99_ms"],
-        "turnaround_p50_s": out["turnaround_p50_s"],
-        "max_queue_depth": out["max_queue_depth"],
-        "jobs_done": out["jobs"],
-        "wall_s": out["wall_s"],
-        "saturated_job_rate_hz": rate_sat,
     }
+    for k in ("step_latency_p50_ms", "step_latency_p99_ms", "tick_latency_p50_ms", "tick_latency_p99_ms",
+              "step_interval_p50_ms", "step_interval_p99_ms", "turnaround_p50_s", "max_queue_depth",
+              "wall_s", "saturated_job_rate_hz"):
+        line[k] = out[k]
+    line["jobs_done"] = out["jobs"]
     print(json.dumps(line), flush=True)
 
 
@@ -372,11 +461,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed advection steps (default: 500 for the 2D workloads, 40 for the 3D "
-                         "static droplet, 6 for the 8.4M-particle impact)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed advection steps first (default: 10, 2, 1)")
-    ap.add_argument("--workload", default="square2d",
-                    choices=["square2d", "droplet2d", "droplet3d", "impact3d", "served"])
+                    help="timed advection steps (default: 20 for the 8.4M-particle impact, 40 for the 3D "
+                         "static droplet, 500 for the 2D workloads)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed advection steps first (default: 3, 2, 10)")
+    ap.add_argument("--workload", default="impact3d",
+                    choices=["impact3d", "square2d", "droplet2d", "droplet3d", "served"])
     ap.add_argument("--jobs", type=int, default=256, help="served: jobs in the stream")
     ap.add_argument("--steps-per-job", type=int, default=200, help="served: advection steps per job")
     ap.add_argument("--budget-gb", type=float, default=0.5, help="served: pool HBM budget")
@@ -390,8 +479,10 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true", help="leave the served leg out of the bench line")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="host time of the oracle sample (whole advection steps, at least this long)")
+                    help="host time of the oracle sample below a million particles (whole advection steps, "
+                         "at least this long)")
     ap.add_argument("--no-accel-check", action="store_true",
                     help="skip the single-evaluation acceleration check against the oracle")
     ap.add_argument("--copy-probe", action="store_true", help="1 GiB device copy (counter reference)")
@@ -422,7 +513,7 @@ def main():
     if args.workload == "served":
         served(args)
         return
-    steps0, warm0 = {"droplet3d": (40, 2), "impact3d": (6, 1)}.get(args.workload, (500, 10))
+    steps0, warm0 = {"droplet3d": (40, 2), "impact3d": (20, 3)}.get(args.workload, (500, 10))
     args.steps = steps0 if args.steps is None else args.steps
     args.warmup = warm0 if args.warmup is None else args.warmup
     w = workload(args.workload)
@@ -436,6 +527,7 @@ def main():
     s.close()
     secs = r["seconds"]
     value = n * args.steps / secs
+    log(f"gpu {secs:.3f}s -> {value:.3e} particle-steps/s, {r['substeps'] / args.steps:.2f} substeps/step")
     # the force-pass duration: the same steps again, every force launch
     # bracketed by HIP events on the system's stream (the events lengthen the
     # step, so they stay out of the timed region)
@@ -454,8 +546,8 @@ def main():
     per_p, per_pair, per_near = FORCE_BYTES[(dim, args.precision)]
     algo_bytes = n * per_p + rt["pairs"] * per_pair + rt["near"] * per_near
     gbs = algo_bytes / (f_avg_ms * 1e-3) / 1e9
-    log(f"gpu {secs:.3f}s substeps={r['substeps']} force launches={f_launch} avg={f_avg_ms * 1e3:.1f}us "
-        f"bytes/launch={algo_bytes:.3e} -> {gbs:.1f} GB/s; ops/launch={ops:.3e} -> {tflops:.2f} TFLOP/s")
+    log(f"force launches={f_launch} avg={f_avg_ms * 1e3:.1f}us bytes/launch={algo_bytes:.3e} -> {gbs:.1f} GB/s; "
+        f"ops/launch={ops:.3e} -> {tflops:.2f} TFLOP/s")
 
     extra = {}
     if prec == rsph.MIXED and not args.no_fp64_compare:
@@ -468,6 +560,7 @@ def main():
             l64, m64 = rt64["timing"]["force"]
             extra["fp64_gpu_value"] = v64
             extra["mixed_over_fp64"] = value / v64
+            extra["fp64_substeps_per_step"] = r64["substeps"] / args.steps
             extra["fp64_force_avg_us"] = m64 / max(l64, 1) * 1e3
             log(f"fp64 gpu {r64['seconds']:.3f}s -> {v64:.3e} particle-steps/s, mixed/fp64 = {value / v64:.2f}")
         except rsph.RsphError as e:  # a health check of the FP64 run: reported, not timed
@@ -476,15 +569,32 @@ def main():
             log(f"fp64 gpu run stopped: {e}")
     if not args.no_accel_check:
         try:
-            extra["accel_err_vs_fp64_oracle"] = accel_error(w, prec)
+            err = accel_error(w, prec)
+            extra["accel_err_vs_fp64_oracle"] = err["normwise"]
+            extra["accel_err_per_particle_p99"] = err["per_particle_p99"]
+            extra["accel_err_per_particle_max"] = err["per_particle_max"]
+            extra["accel_err_particles"] = err["particles"]
+            if prec == rsph.MIXED:
+                e64 = accel_error(w, rsph.FP64)
+                extra["fp64_gpu_accel_err_vs_oracle"] = e64["normwise"]
+            log(f"accel error vs oracle: {err}")
         except Exception as e:  # the oracle is a checker, not the product
             log(f"accel error check skipped: {e}")
+
+    srv = None
+    if not args.no_served:
+        srv = served_leg(args)
+        log(f"served: {srv['particle_steps_per_s']:.3e} particle-steps/s, p50 {srv['step_latency_p50_ms']:.2f} ms, "
+            f"p99 {srv['step_latency_p99_ms']:.2f} ms per step")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
         log(f"cpu baseline {cpu}")
 
+    # the force pass streams from HBM only when the workload's working set
+    # exceeds the Infinity Cache
+    working_set = n * (1300 if dim == 3 else 800)
     line = {
         "metric": "particle-steps/s",
         "value": value,
@@ -526,6 +636,7 @@ def main():
             "avg_launch_us": f_avg_ms * 1e3,
             "launches": f_launch,
             "empty_kernel_event_us": floor_ms * 1e3,
+            "working_set_exceeds_mall": working_set > MALL_BYTES,
             "alu_achieved_tflops": tflops,
             "alu_peak_tflops": peak_tf,
             "alu_frac": tflops / peak_tf,
@@ -533,6 +644,14 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if srv is not None:
+        line["served_particle_steps_per_s"] = srv["particle_steps_per_s"]
+        line["served_step_latency_p50_ms"] = srv["step_latency_p50_ms"]
+        line["served_step_latency_p99_ms"] = srv["step_latency_p99_ms"]
+        line["served"] = {k: srv[k] for k in (
+            "jobs", "jobs_in_stream", "steps_per_job", "particles_per_job", "form", "arrival_rate_hz",
+            "saturated_job_rate_hz", "hbm_budget_bytes", "wall_s", "tick_latency_p50_ms", "tick_latency_p99_ms",
+            "step_interval_p50_ms", "step_interval_p99_ms", "turnaround_p50_s", "max_queue_depth")}
     line.update(extra)
     print(json.dumps(line), flush=True)
 

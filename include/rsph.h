@@ -76,7 +76,9 @@ typedef struct {
     double h_over_dp;   /* smoothing length over dp [1.3] */
     double rho0[2];     /* reference densities of fluids k and l */
     double eta[2];      /* dynamic viscosities of fluids k and l (>= 0) */
-    double c0;          /* common artificial sound speed (> 0) */
+    double c0;          /* common artificial sound speed (section 2: one c0 for both fluids); 0 selects
+                           the section 2 rule c0 = 10 U_max with U_max = max(u_ref, largest initial |v|),
+                           taken when the particles are set */
     double gamma;       /* surface-tension coefficient (>= 0) */
     double xi;          /* penalty coefficient; < 0: 1.3 n + 0.6 for a density ratio 10^n */
     double alpha_shift; /* position-correction coefficient alpha of Eq. 14 [0.2] */
@@ -85,6 +87,7 @@ typedef struct {
     double gravity[3];  /* body force g of Eq. 2 [0] */
     uint32_t flags;     /* RSPH_NO_* switches [0] */
     uint32_t reserved;
+    double u_ref;       /* anticipated largest flow speed of the c0 = 0 rule (>= 0) [0] */
 } rsph_params;
 
 /* Observables of one system, all FP64, reduced on the device in a fixed order. */
@@ -114,6 +117,8 @@ typedef struct {
 #define RSPH_HEALTH_NEIGHBOURS 4u /* more neighbours than the list holds */
 #define RSPH_HEALTH_COINCIDENT 8u /* two neighbours closer than 1e-9 h */
 #define RSPH_HEALTH_DT 32u        /* acoustic step collapsed below 1e-12 of its no-flow value */
+#define RSPH_HEALTH_DISPLACEMENT 64u /* a particle moved more than one cell (edge >= 2h) between two
+                                        binnings: the advection step of Eq. 16 no longer bounds the motion */
 
 /* particle fields readable with rsph_read_particles, and their width per particle */
 enum {
@@ -139,57 +144,93 @@ enum {
     RSPH_FIELD_COUNT = 18
 };
 
-/* Fills *p with the documented defaults (2D, FP64, unit box, dp = 0.02, ...). */
+/* Fills *p with the documented defaults: 2D, FP64, unit box, dp = 0.02, h = 1.3 dp
+ * (section 5), alpha = 0.2 (Eq. 14), CFL factors 0.1 and 0.6 (Eqs. 16-17), xi by
+ * the rule of section 4.2, c0 = 1. */
 void rsph_params_default(rsph_params* p);
 
-/* Creates an empty system (no particles yet). Validates params: dim in {2,3};
- * dp, rho0, c0 > 0; eta, gamma >= 0; at least 3 cells of edge >= 2h per axis and
- * at most 1024; all values finite. EINVAL otherwise. */
+/* Creates an empty system (no particles yet) for the problem of section 2:
+ * two immiscible weakly compressible fluids k and l (rho0, eta per fluid), one
+ * sound speed c0 for both (Eq. 3) and one surface-tension coefficient gamma,
+ * discretised with the Wendland kernel of section 5 (h = 1.3 dp, cut-off 2h) in
+ * a periodic box.  Validates params: dim in {2,3}; dp, rho0 > 0; c0 > 0, or
+ * c0 = 0 with u_ref >= 0 (the section 2 rule, applied by rsph_set_particles);
+ * eta, gamma >= 0; at least 3 cells of edge >= 2h per axis and at most 1024;
+ * all values finite.  hip_stream: a hipStream_t owned by the caller, or NULL
+ * for a stream of the library's own.  *out is owned by the caller and freed with
+ * rsph_destroy_system.  EINVAL (nothing created) otherwise. */
 rsph_status rsph_create_system(const rsph_params* params, void* hip_stream, rsph_system** out);
 
-/* Sets (or resets) all particles: pos, vel (n x dim), phase (n, in {0,1}),
- * mass (n, NULL -> rho0[phase] / sigma0 with sigma0 the lattice kernel sum, so a
- * perfect lattice has rho = rho0), rho (n, NULL -> rho0[phase]).  Positions are
- * wrapped into the box.  Resets t, counters, density rates and the fault state
- * unless opts has RSPH_KEEP_CLOCK (then t and counters are kept: resume).
- * EINVAL (nothing changed) on n < 1, NaN/Inf, a phase outside {0,1}, mass or
- * rho <= 0, or two particles closer than 1e-3 dp. */
+/* Sets (or resets) all particles of the two-fluid system of section 2, each a
+ * Lagrangian particle with position, velocity, fluid and mass (section 3.1):
+ * pos, vel (n x dim), phase (n, in {0,1}), mass (n, NULL -> rho0[phase] / sigma0
+ * with sigma0 the lattice kernel sum, so a perfect lattice has rho = rho0), rho
+ * (n, NULL -> rho0[phase]; it sets the initial pressure by Eq. 3).  Positions are
+ * wrapped into the box.  With c0 = 0 in the system's params, c0 becomes
+ * 10 max(u_ref, largest |vel|) here (section 2).  Resets t, counters, density
+ * rates and the fault state unless opts has RSPH_KEEP_CLOCK (then t and
+ * counters are kept: resume).  The arrays are host memory owned by the caller
+ * and copied before the call returns.  EINVAL (nothing changed) on n < 1,
+ * NaN/Inf, a phase outside {0,1}, mass or rho <= 0, two particles closer than
+ * 1e-3 dp, or c0 = 0 with u_ref = 0 and every velocity zero.
+ * The extra rho argument (beyond particles, velocities, fluids and masses) lets
+ * a caller restore a state for a bitwise resume. */
 #define RSPH_KEEP_CLOCK 1u
 rsph_status rsph_set_particles(rsph_system* sys, int64_t n, const double* pos, const double* vel,
                                const int32_t* phase, const double* mass, const double* rho,
                                uint32_t opts);
 
-/* Restores the continuity rates (n doubles, caller order) after
- * rsph_set_particles(..., RSPH_KEEP_CLOCK), for a bitwise resume. */
+/* Restores the continuity rates D rho / Dt of Eq. 6 (n doubles, caller order,
+ * host memory copied before return) after rsph_set_particles(...,
+ * RSPH_KEEP_CLOCK), for a bitwise resume: the dual-criteria scheme of section
+ * 3.3 carries the rate from one acoustic substep to the next.  EINVAL if n
+ * differs from the particle count, ESTATE without particles. */
 rsph_status rsph_set_drho(rsph_system* sys, int64_t n, const double* drho);
 
-/* Advances n_outer advection steps of the dual-criteria scheme (section 3.3),
- * each with its own data-dependent number of acoustic substeps; returns when
- * they are done (synchronises the stream). ENUMERIC if a health check trips
- * (the system is then faulted and later steps return ESTATE). */
+/* Advances n_outer advection steps of the dual-criteria scheme (section 3.3,
+ * Eqs. 16-18), each with its own data-dependent number of acoustic substeps
+ * that integrate Eqs. 1-2 as discretised by Eqs. 6-15 and 21-33; returns when
+ * they are done (synchronises the stream).  EINVAL on n_outer < 0; ESTATE
+ * without particles or when faulted; ENUMERIC if a health check trips (the
+ * system is then faulted and later steps return ESTATE until
+ * rsph_set_particles resets it). */
 rsph_status rsph_step(rsph_system* sys, int64_t n_outer);
 
 /* One evaluation, at the current state and with no update, of the neighbour
- * geometry, kernel sum, viscous acceleration, correction matrix, position
- * correction, colour gradient, accelerations and continuity rate (density as
- * set, pressure c0^2 (rho - rho0)); read them with rsph_read_particles. */
+ * geometry, kernel sum, viscous acceleration (Eq. 13), correction matrix
+ * (Eq. 15), position correction (Eq. 14), colour gradient (Eq. 22),
+ * accelerations (Eqs. 7-12 and 33) and continuity rate (Eqs. 6, 9), with the
+ * density as set and the pressure of Eq. 3; read them with
+ * rsph_read_particles.  ESTATE without particles. */
 rsph_status rsph_eval_rates(rsph_system* sys);
 
-/* Reduces the observables on the device and copies them to *out. */
+/* Reduces the observables on the device and copies them to *out (caller
+ * owned): clock and step counts (section 3.3), total momentum (conserved by
+ * the antisymmetric pair terms of sections 3.1 and 4), kinetic energy, fluid
+ * masses and volumes, and the fluid-k centroid, second moment and mean inner
+ * and outer pressures from which the oscillation period (Eq. 35) and the
+ * Young-Laplace jump (Eq. 37) are measured.  ESTATE without particles. */
 rsph_status rsph_read_observables(rsph_system* sys, rsph_observables* out);
 
 /* Copies one field (RSPH_FIELD_*) of all n particles, caller order, into out
- * (n * width doubles).  EINVAL if n differs from the system's particle count. */
+ * (host memory, n * width doubles, caller owned): the state of section 3.1
+ * (position, velocity, density, Eq. 3 pressure, mass, fluid) or a rate of the
+ * last rsph_eval_rates.  EINVAL if n differs from the system's particle count
+ * or the field is unknown; ESTATE for a rate field before an evaluation. */
 rsph_status rsph_read_particles(rsph_system* sys, int32_t field, int64_t n, double* out);
 
-/* Binning of the last rebuild: per particle (caller order) its cell key
- * cx + nx (cy + ny cz) and its rank in cell order (cells ascending, then caller
- * index ascending). */
+/* Binning of the last rebuild (the cell-linked list behind the kernel's
+ * compact support of section 5, cells of edge >= 2h): per particle (caller
+ * order) its cell key cx + nx (cy + ny cz) and its rank in cell order (cells
+ * ascending, then caller index ascending), into caller-owned host arrays of n
+ * entries.  EINVAL if n differs from the particle count. */
 rsph_status rsph_read_binning(rsph_system* sys, int64_t n, uint32_t* key, int64_t* rank);
 
-/* Neighbour lists of the last rebuild in caller indices: start has n + 1
- * entries, idx up to cap entries, each list in the library's stencil order.
- * EINVAL if cap is too small. */
+/* Neighbour lists of the last rebuild in caller indices: every j != i with
+ * |r_ij| < 2h, the support of the kernel of section 5, frozen for the
+ * advection step (section 3.3).  start has n + 1 entries, idx up to cap
+ * entries (caller-owned host arrays), each list in the library's stencil order.
+ * EINVAL if cap is too small or n differs from the particle count. */
 rsph_status rsph_read_neighbours(rsph_system* sys, int64_t n, int64_t cap, int64_t* start,
                                  int64_t* idx);
 
@@ -235,23 +276,32 @@ const char* rsph_last_error(const rsph_system* sys);
 
 /* ---- serving: many systems packed in one device array ------------------- */
 
-/* A pool packs the particles of many systems of one dimension and one
+/* Serving many independent simulations of the section 2 problem at once.
+ * A pool packs the particles of many systems of one dimension and one
  * precision into shared device arrays and steps them together in the same
- * launches, each system with its own parameters and time steps.
- * hbm_budget_bytes bounds the device memory the pool may hold (0: no bound); a
- * pool with a bound takes all of it at its first admission, so that later
- * admissions seldom reallocate. */
+ * launches, each system with its own parameters and its own dual-criteria time
+ * steps (section 3.3).  dim and precision are fixed per pool because every
+ * member shares the pool's kernels and record layout.  hbm_budget_bytes bounds
+ * the device memory the pool may hold (0: no bound); a pool with a bound takes
+ * all of it at its first admission, so that later admissions seldom
+ * reallocate.  *out is freed with rsph_pool_destroy.  EINVAL on a bad dim or
+ * precision. */
 rsph_status rsph_pool_create(int32_t dim, int32_t precision, size_t hbm_budget_bytes,
                              void* hip_stream, rsph_pool** out);
-/* Admits a system with its particles (as rsph_set_particles).  EBUSY if the
- * budget cannot hold it now; EINVAL on bad input.  The returned system is
- * owned by the pool: read it with the rsph_read_* calls, release it with
- * rsph_pool_release. */
+/* Admits a system of the section 2 problem with its particles (as
+ * rsph_create_system followed by rsph_set_particles, with params->dim and
+ * params->precision equal to the pool's).  EBUSY if the budget cannot hold it
+ * now; EINVAL on bad input.  The returned system is owned by the pool: read it
+ * with the rsph_read_* calls, release it with rsph_pool_release. */
 rsph_status rsph_pool_admit(rsph_pool* pool, const rsph_params* params, int64_t n,
                             const double* pos, const double* vel, const int32_t* phase,
                             const double* mass, rsph_system** out);
-/* Advances each of the count systems by n_outer[k] advection steps; all of them
- * progress in the same launches until each has done its own count. */
+/* Advances each of the count systems by n_outer[k] advection steps of the
+ * dual-criteria scheme (section 3.3), each with its own substeps; all of them
+ * progress in the same launches until each has done its own count.  ENUMERIC
+ * if a member's health check trips: that member is faulted (its later steps
+ * return ESTATE), the others keep the steps they took and may be stepped
+ * again; release the faulted one with rsph_pool_release. */
 rsph_status rsph_pool_step(rsph_pool* pool, rsph_system* const* systems, const int64_t* n_outer,
                            int32_t count);
 /* Bytes of device memory the pool holds now (with a budget: the budget's worth
@@ -268,8 +318,9 @@ size_t rsph_pool_bytes(const rsph_pool* pool);
  * call.  EINVAL on a NULL argument. */
 rsph_status rsph_step_counts(const rsph_system* sys, int64_t* n_outer, int64_t* n_sub,
                              int64_t* substeps_per_step);
-/* Removes a system from its pool and frees its slots; the systems packed after
- * it move down.  sys is invalid afterwards. */
+/* Removes a system (section 2 problem) from its pool and frees its slots; the
+ * systems packed after it move down.  sys is invalid afterwards.  EINVAL if
+ * sys is not a member of pool. */
 rsph_status rsph_pool_release(rsph_pool* pool, rsph_system* sys);
 /* Frees the pool and every system still in it. */
 void rsph_pool_destroy(rsph_pool* pool);

@@ -163,13 +163,14 @@ void validate_params(const rsph_params* p)
         fail(RSPH_EINVAL, "precision must be RSPH_FP64 or RSPH_MIXED");
     const double vals[] = {p->dp, p->h_over_dp, p->rho0[0], p->rho0[1], p->eta[0], p->eta[1],
                            p->c0, p->gamma, p->xi, p->alpha_shift, p->cfl_ad, p->cfl_ac,
-                           p->gravity[0], p->gravity[1], p->gravity[2]};
+                           p->gravity[0], p->gravity[1], p->gravity[2], p->u_ref};
     for (double v : vals)
         if (!std::isfinite(v)) fail(RSPH_EINVAL, "parameters must be finite");
     if (!(p->dp > 0) || !(p->h_over_dp > 0)) fail(RSPH_EINVAL, "dp and h_over_dp must be > 0");
     if (!(p->rho0[0] > 0) || !(p->rho0[1] > 0)) fail(RSPH_EINVAL, "rho0 must be > 0");
     if (p->eta[0] < 0 || p->eta[1] < 0) fail(RSPH_EINVAL, "eta must be >= 0");
-    if (!(p->c0 > 0)) fail(RSPH_EINVAL, "c0 must be > 0");
+    if (p->c0 < 0) fail(RSPH_EINVAL, "c0 must be > 0, or 0 for the rule c0 = 10 U_max");
+    if (p->u_ref < 0) fail(RSPH_EINVAL, "u_ref must be >= 0");
     if (p->gamma < 0) fail(RSPH_EINVAL, "gamma must be >= 0");
     if (!(p->cfl_ad > 0) || !(p->cfl_ac > 0)) fail(RSPH_EINVAL, "CFL factors must be > 0");
     const double h = p->h_over_dp * p->dp;
@@ -216,9 +217,12 @@ SysConst make_const(const rsph_params& p)
                              ? p.cfl_ac * std::sqrt(p.rho0[f] * h * h * h / (2.0 * M_PI * p.gamma))
                              : INFINITY;
     }
-    S.c0 = p.c0;
-    S.inv_c0 = 1.0 / p.c0;
-    S.c0sq = p.c0 * p.c0;
+    // c0 = 0 (the rule of section 2) is resolved by effective_c0 once the
+    // particles are known; until then the anticipated speed alone sets it
+    const double c0 = p.c0 > 0 ? p.c0 : 10.0 * p.u_ref;
+    S.c0 = c0;
+    S.inv_c0 = c0 > 0 ? 1.0 / c0 : 0.0;
+    S.c0sq = c0 * c0;
     S.gamma = p.gamma;
     S.xi = p.xi >= 0 ? p.xi : 1.3 * std::fabs(std::log10(p.rho0[0] / p.rho0[1])) + 0.6;
     S.alpha_h2 = p.alpha_shift * h * h;
@@ -227,6 +231,32 @@ SysConst make_const(const rsph_params& p)
     S.coincident2 = (1e-9 * h) * (1e-9 * h);
     S.close2 = (1e-3 * p.dp) * (1e-3 * p.dp);
     return S;
+}
+
+// Section 2 sets the artificial sound speed to ten times the largest
+// anticipated flow speed.  With c0 = 0 in the parameters that speed is the
+// larger of u_ref and the largest initial particle speed.
+double effective_c0(const rsph_params& p, int64_t n, const double* vel)
+{
+    if (p.c0 > 0) return p.c0;
+    double vmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v2 = 0.0;
+        for (int a = 0; a < p.dim; ++a) v2 += vel[i * p.dim + a] * vel[i * p.dim + a];
+        vmax = std::max(vmax, std::sqrt(v2));
+    }
+    const double c0 = 10.0 * std::max(p.u_ref, vmax);
+    if (!(c0 > 0) || !std::isfinite(c0))
+        fail(RSPH_EINVAL, "c0 = 0 needs u_ref > 0 or a moving particle (c0 = 10 U_max)");
+    return c0;
+}
+
+// Constants of a system whose particles are set now: the c0 = 0 rule resolved.
+SysConst const_for_particles(const rsph_params& p, int64_t n, const double* vel)
+{
+    rsph_params q = p;
+    q.c0 = effective_c0(p, n, vel);
+    return make_const(q);
 }
 
 // Allocation plan of a pool: the same walk either allocates (P given) or only
@@ -519,6 +549,9 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
         rsph_system* s = members[k];
         SysDyn d{};
         if (s->row >= 0 && s->row < (int)dyn_old.size()) d = dyn_old[s->row];
+        // the frozen positions of the last binning stay in the old slots:
+        // the displacement check restarts at the system's next binning
+        if (moved || L.p_off[k] != s->p_off) d.binned = 0;
         s->p_off = L.p_off[k];
         s->p_cap = L.p_cap[k];
         s->c_off = L.c_off[k];
@@ -678,8 +711,8 @@ std::vector<SysDyn> read_dyn(rsph_pool* P)
     return d;
 }
 
-constexpr uint32_t kFaultBits =
-    kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident | kHealthDtCollapse;
+constexpr uint32_t kFaultBits = kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident |
+                                kHealthDtCollapse | kHealthDisplacement;
 constexpr int64_t kMaxSubsteps = 1000000;  // per advection step
 
 // m acoustic substeps for the systems inside an advection step (the others
@@ -1000,6 +1033,8 @@ void reset_dyn(rsph_system* s, bool keep_clock)
     if (keep_clock) HIPCHECK(hipMemcpy(&d, P->A.sd + s->row, sizeof(SysDyn), hipMemcpyDeviceToHost));
     d.health = 0;
     d.stepping = 0;
+    d.binned = 0;
+    d.displaced = 0;
     d.ksub_max = 0;
     d.state = kBoundary;
     d.sub_state = kIdle;
@@ -1183,6 +1218,7 @@ rsph_status rsph_set_particles(rsph_system* s, int64_t n, const double* pos, con
     return guarded(&s->err, [&] {
         if (!s->owns_pool) fail(RSPH_ESTATE, "systems of a served pool take particles at admission");
         validate_particles(s->prm, n, pos, vel, phase, mass, rho);
+        const SysConst sc_new = const_for_particles(s->prm, n, vel);
         rsph_pool* P = s->pool;
         const bool keep = (opts & RSPH_KEEP_CLOCK) && s->has_particles && s->row >= 0;
         s->has_particles = false;
@@ -1201,6 +1237,13 @@ rsph_status rsph_set_particles(rsph_system* s, int64_t n, const double* pos, con
             repack(P, {s});
         }
         s->has_particles = true;
+        // the slot and cell placement of the packing stays; the constants
+        // may change with c0 (a reset with new velocities under c0 = 0)
+        const SysConst placed = s->sc;
+        s->sc = sc_new;
+        s->sc.p_off = placed.p_off;
+        s->sc.c_off = placed.c_off;
+        s->sc.fuse_dt = placed.fuse_dt;
         s->sc.p_n = n;
         HIPCHECK(hipMemcpy((void*)(P->A.sc + s->row), &s->sc, sizeof(SysConst), hipMemcpyHostToDevice));
         upload_particles(s, pos, vel, phase, mass, rho);
@@ -1542,10 +1585,11 @@ rsph_status rsph_pool_admit(rsph_pool* P, const rsph_params* params, int64_t n, 
         if (params->dim != P->dim || params->precision != P->precision)
             fail(RSPH_EINVAL, "system dim and precision must match the pool's");
         validate_particles(*params, n, pos, vel, phase, mass, nullptr);
+        const SysConst sc = const_for_particles(*params, n, vel);
         rsph_system* s = new rsph_system();
         s->pool = P;
         s->prm = *params;
-        s->sc = make_const(*params);
+        s->sc = sc;
         s->ncells = s->sc.ncells;
         s->n = n;
         std::vector<rsph_system*> members = P->systems;

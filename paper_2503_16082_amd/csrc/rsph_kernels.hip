@@ -437,6 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
     }
     const double rho = A.rho[i], drho = A.drho[i], mass = A.mass[i];
     const int32_t id = A.id[i], phase = A.phase[i];
+    const double4 xold = ((const double4*)A.xd)[i];  // position at the last binning
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;  // wave-uniform: a wave lies in one system or in none
     SysDyn& Dy = A.sd[c.s];
@@ -474,6 +475,19 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
         const uint32_t key = (uint32_t)(ck[0] + S.ncell[0] * (ck[1] + S.ncell[1] * ck[2]));
         A.key[i] = key;
         gkey = (uint32_t)S.c_off + key;
+        // the same slot held the same particle at the last binning: more than
+        // one cell of motion since then (periodic distance) is a fault.  It is
+        // noted apart from the health bits, which decide the state of this
+        // pass, and folded into them when the advection step begins.
+        if (A.mode == 0 && Dy.binned) {
+            const double xo[3] = {xold.x, xold.y, xold.z};
+            bool far = false;
+            for (int a = 0; a < D; ++a) {
+                const int dc = abs(ck[a] - cell_of(xo[a], S, a));
+                far |= dc > 1 && dc < S.ncell[a] - 1;
+            }
+            if (far) Dy.displaced = 1;
+        }
     }
     // Ranks by runs: the slots are sorted by cell from the last binning, so
     // neighbouring lanes mostly share a cell.  The first lane of each run of
@@ -699,6 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
         A.mass[d] = mass;
         A.id[d] = me;
         A.phase[d] = ph;
+        if (i == S.p_off) A.sd[c.s].binned = 1;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
         if (ph == 0) m0 = bits;
         else m1 = bits;
@@ -1542,6 +1557,10 @@ __device__ void begin_advection_step(const DevArrays& A, const SysConst& S, SysD
     D.ksub = 0;
     D.dt[0] = fmin(dt_ac, dt_ad);
     D.state = kSubstepping;
+    if (D.displaced) {
+        atomicOr(&D.health, kHealthDisplacement);
+        D.displaced = 0;
+    }
     if (dt_collapsed(S, dt_ac) || !(dt_ad > 0.0)) {
         atomicOr(&D.health, kHealthDtCollapse);
         D.state = kIdle;

@@ -34,6 +34,8 @@ FIELDS = {
 KERNELS = ["bin", "neighbours", "advection", "shift", "colour", "force", "continuity",
            "event_floor"]
 
+HEALTH = {"nonfinite": 1, "density": 2, "neighbours": 4, "coincident": 8, "dt": 32, "displacement": 64}
+
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENUMERIC",
           -6: "EBUSY"}
 
@@ -63,6 +65,7 @@ class Params(C.Structure):
         ("gravity", C.c_double * 3),
         ("flags", C.c_uint32),
         ("reserved", C.c_uint32),
+        ("u_ref", C.c_double),
     ]
 
 
@@ -172,6 +175,7 @@ def make_params(p: dict, precision=None) -> Params:
     g = list(p.get("gravity", [0.0, 0.0, 0.0])) + [0.0] * 3
     q.gravity = (C.c_double * 3)(*g[:3])
     q.flags = int(p.get("flags", 0))
+    q.u_ref = float(p.get("u_ref", 0.0))
     return q
 
 

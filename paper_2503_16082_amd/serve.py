@@ -34,6 +34,10 @@ from . import rsph
 from . import workloads as WL
 
 
+# health bits that fault a system (RSPH_HEALTH_*; 16 is an input check only)
+FAULT_BITS = 1 | 2 | 4 | 8 | 32 | 64
+
+
 def build_job(desc):
     return WL.oscillating_ellipse_2d(desc["n"], desc["aspect"], desc["ratio"], desc["gamma"],
                                      seed=desc["seed"])
@@ -54,18 +58,21 @@ def steps_this_tick(sps, left, cap):
 
 
 def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, precision=rsph.MIXED,
-          log=None, keep_results=False, max_seconds=None, max_steps_per_tick=1, max_admits_per_tick=0):
+          log=None, keep_results=False, max_seconds=None, max_steps_per_tick=1, max_admits_per_tick=0,
+          builder=build_job):
     """Runs the request loop to completion.  rate_hz: Poisson arrival rate
     (None: all jobs arrive at t = 0).  max_admits_per_tick > 0 bounds the
     admissions between two ticks (each one stalls the running jobs).  Returns a
-    summary dictionary."""
+    summary dictionary.  A job whose health check trips is released and reported
+    (jobs_failed, failed_health) while the others go on.  builder(desc) makes a
+    job's parameters and particles."""
     rng = np.random.Generator(np.random.PCG64(12345))
     n_jobs = len(job_descs)
     if rate_hz:
         arrivals = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_jobs))
     else:
         arrivals = np.zeros(n_jobs)
-    built = {k: build_job(d) for k, d in enumerate(job_descs)}
+    built = {k: builder(d) for k, d in enumerate(job_descs)}
     pool = rsph.Pool(2, precision=precision, budget_bytes=budget_bytes)
     queue = collections.deque()
     active = {}  # job index -> [system, steps done, n particles, end of its last tick or admission]
@@ -111,10 +118,36 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
         else:
             n_tick = [1] * len(order)
         ta = time.perf_counter()
-        pool.step([active[k][0] for k in order], n_tick)
+        failed_now = {}
+        try:
+            pool.step([active[k][0] for k in order], n_tick)
+        except rsph.RsphError as e:
+            # one job's health check tripped: the others took their steps;
+            # the faulted ones are released and reported, the loop goes on
+            if e.name != "ENUMERIC":
+                raise
+            for k in order:
+                h = active[k][0].observables()["health"]
+                if h & FAULT_BITS:
+                    failed_now[k] = h
+            if not failed_now:
+                raise
         tb = time.perf_counter()
         dt = tb - ta
         tick_latency.append(dt)
+        for k, h in failed_now.items():
+            s = active[k][0]
+            finished[k] = {"n": active[k][2], "done_at": time.perf_counter() - t0,
+                           "arrived": float(arrivals[k]), "result": None, "failed": int(h),
+                           "steps": active[k][1]}
+            pool.release(s)
+            built.pop(k, None)
+            del active[k]
+            if log:
+                log(f"job {k} failed (health bits 0x{h:x}) after {finished[k]['steps']} steps; released")
+        steps_of = dict(zip(order, n_tick))
+        order = [k for k in order if k not in failed_now]
+        n_tick = [steps_of[k] for k in order]
         for k, n in zip(order, n_tick):
             active[k][1] += n
             particle_steps += active[k][2] * n
@@ -136,11 +169,14 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
                     log(f"job {k} done ({n} particles) at {finished[k]['done_at']:.2f}s, "
                         f"{len(active)} active, {len(queue)} queued")
     wall = time.perf_counter() - t0
+    failed = {k: f["failed"] for k, f in finished.items() if f.get("failed")}
     lat = np.array(step_latency) if step_latency else np.zeros(1)
     tick = np.array(tick_latency) if tick_latency else np.zeros(1)
     gap = np.array(step_interval) if step_interval else np.zeros(1)
     summary = {
-        "jobs": len(finished),
+        "jobs": len(finished) - len(failed),
+        "jobs_failed": len(failed),
+        "failed_health": failed,
         "wall_s": wall,
         "particle_steps": particle_steps,
         "particle_steps_per_s": particle_steps / wall if wall > 0 else 0.0,
@@ -152,10 +188,11 @@ def serve(job_descs, steps_per_job=200, rate_hz=None, budget_bytes=4 << 30, prec
         "step_interval_p99_ms": float(np.percentile(gap, 99) * 1e3),
         "max_steps_per_tick": max_steps_per_tick,
         "max_queue_depth": int(max(queue_depth) if queue_depth else 0),
-        "turnaround_p50_s": float(np.median([f["done_at"] - f["arrived"] for f in finished.values()]))
-        if finished else math.nan,
+        "turnaround_p50_s": float(np.median([f["done_at"] - f["arrived"] for f in finished.values()
+                                             if not f.get("failed")]))
+        if len(finished) > len(failed) else math.nan,
     }
     if keep_results:
-        summary["results"] = {k: f["result"] for k, f in finished.items()}
+        summary["results"] = {k: f["result"] for k, f in finished.items() if not f.get("failed")}
     pool.close()
     return summary

@@ -200,7 +200,7 @@ def droplet_impact_3d(n_per_unit=32, seed=0, U0=50.0, amp=0.05, box=(8.0, 8.0, 4
     vel[in_drop, 2] = -U0
     p = base_params(3, box, dp, (1.0, 1e-3), (5e-3, 5e-5), 0.1, 10.0 * U0)
     return {"name": "droplet_impact_3d", "params": p, "pos": pos, "vel": vel, "phase": phase,
-            "R": D / 2}
+            "R": D / 2, "centre": centre, "pool_depth": pool_depth}
 
 
 def acoustic_wave_2d(n_side=24, amp_v=1e-3, seed=0):

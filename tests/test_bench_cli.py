@@ -12,6 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
+import numpy as np  # noqa: E402
+import pytest  # noqa: E402
 
 
 def test_more_than_one_gpu_is_refused():
@@ -90,3 +92,37 @@ def test_bench_line_keys_documented():
     for key in ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
                 "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"]:
         assert f'"{key}"' in src, key
+
+
+def test_served_and_error_keys_in_the_default_line():
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    for key in ["served_step_latency_p50_ms", "served_step_latency_p99_ms", "served_particle_steps_per_s",
+                "particle_substeps_per_s", "accel_err_per_particle_p99", "fp64_gpu_value", "cpu_model"]:
+        assert f'"{key}"' in src, key
+    assert 'default="impact3d"' in src
+
+
+def test_rate_errors_normwise_and_per_particle():
+    import bench
+    ref = np.array([[1.0, 0.0], [0.0, 2.0], [1e-6, 0.0], [3.0, 4.0]])
+    a = ref.copy()
+    a[0, 0] += 1e-3        # 1e-3 relative to its own |a| = 1
+    a[2, 0] += 1e-7        # a tiny acceleration: below 1e-3 of the max, not counted per particle
+    e = bench.rate_errors(a, ref)
+    assert e["normwise"] == pytest.approx(1e-3 / 5.0)
+    assert e["per_particle_max"] == pytest.approx(1e-3)
+    assert 0 < e["per_particle_p99"] <= 1e-3
+
+
+def test_impact_sample_is_chosen_from_the_inputs():
+    import bench
+    from paper_2503_16082_amd import workloads as WL
+    w = WL.droplet_impact_3d(n_per_unit=8)
+    t = bench.input_sample(w, 1000)
+    assert 900 <= len(t) <= 1000 and len(np.unique(t)) == len(t)
+    h = 1.3 / 8
+    pos = w["pos"][t]
+    near = (np.abs(np.linalg.norm(pos - w["centre"], axis=1) - w["R"]) < 3 * h) | (
+        np.abs(pos[:, 2] - w["pool_depth"]) < 3 * h)
+    assert near.sum() >= 500
+    assert np.array_equal(t, bench.input_sample(w, 1000))

@@ -184,8 +184,12 @@ def interface_roughness(s, dp):
 
 
 def test_penalty_ablation_interface_roughness():
+    """The oscillating drop at ratio 1000 to t = 0.5 in the FP64 form, without
+    the penalty and with it under readings R1 (default) and R3 of Eq. 30: both
+    readings keep the interface sharper and smoother, and R1 raises the
+    kinetic energy of the spurious currents less than R3 (as on the oracle)."""
     res = {}
-    for name, flags in (("penalty", 0), ("no penalty", rsph.NO_PENALTY)):
+    for name, flags in (("penalty", 0), ("no penalty", rsph.NO_PENALTY), ("R3", rsph.PENALTY_R3)):
         w = WL.oscillating_drop_2d(n_side=60, ratio=1000.0, V0=1.0, gamma=1.0)
         p = dict(w["params"])
         p["flags"] = flags
@@ -193,10 +197,51 @@ def test_penalty_ablation_interface_roughness():
         s.set_particles(w["pos"], w["vel"], w["phase"])
         while s.observables()["t"] < 0.5:
             s.step(50)
-        res[name] = interface_roughness(s, p["dp"])
+        res[name] = interface_roughness(s, p["dp"]) + (s.observables()["kinetic"],)
         s.close()
         say(f"{name}: cross-phase pairs per dp of interface {res[name][0]:.3f}, "
-            f"interface radius spread {res[name][1]:.3f} dp")
-    # the penalty keeps the interface sharper and smoother
-    assert res["penalty"][0] < 0.97 * res["no penalty"][0]
-    assert res["penalty"][1] < 0.95 * res["no penalty"][1]
+            f"interface radius spread {res[name][1]:.3f} dp, kinetic energy {res[name][2]:.4f}")
+    # the penalty keeps the interface sharper and smoother, in both readings
+    for k in ("penalty", "R3"):
+        assert res[k][0] < 0.97 * res["no penalty"][0], k
+        assert res[k][1] < 0.95 * res["no penalty"][1], k
+    # and drives spurious currents, less so in reading R1
+    assert res["penalty"][2] > res["no penalty"][2]
+    assert res["penalty"][2] < res["R3"][2]
+
+
+# ---------------------------------------------------------------------------
+# oscillating drop at density ratio 1 (section 5.1, first case): V0 = 10,
+# eta = 0.05, R/dp = 12 and 24; the centre of mass of the drop's upper-right
+# quarter, GPU against the oracle
+# ---------------------------------------------------------------------------
+
+def test_ratio1_drop_quarter_centre_matches_oracle():
+    from physics_util import upper_right_quarter_centre
+    t_end = 0.5
+    tq = np.linspace(0.02, t_end, 25)
+    for r_dp in (12, 24):
+        w = WL.oscillating_drop_2d(n_side=int(round(r_dp / 0.2)), ratio=1.0, V0=10.0, gamma=1.0)
+        p = w["params"]
+
+        def track(step, observe, positions):
+            ts, xs = [], []
+            while True:
+                o = observe()
+                ts.append(o["t"])
+                xs.append(upper_right_quarter_centre(positions(), w["phase"], o["centroid"])[0])
+                if o["t"] >= t_end:
+                    return np.interp(tq, ts, xs)
+                step(10)
+
+        st = O.State(p, O.wrap(p, w["pos"]), w["vel"], w["phase"])
+        x_or = track(st.step, st.observables, lambda: O.wrap(p, st.pos))
+        for prec in (rsph.FP64, rsph.MIXED):
+            s = rsph.System(p, precision=prec)
+            s.set_particles(w["pos"], w["vel"], w["phase"])
+            x_g = track(s.step, s.observables, lambda: s.read("pos"))
+            s.close()
+            e = np.abs(x_g - x_or).max() / np.abs(x_or).max()
+            say(f"ratio 1, R/dp={r_dp}, precision {prec}: quarter centre vs oracle {e:.2e} "
+                f"(x from {x_or.min():.4f} to {x_or.max():.4f})")
+            assert e < 0.01

@@ -49,9 +49,9 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    {"dim": 4}, {"dp": 0.0}, {"rho0": [0.0, 1.0]}, {"eta": [-1.0, 0.0]}, {"c0": 0.0},
+    {"dim": 4}, {"dp": 0.0}, {"rho0": [0.0, 1.0]}, {"eta": [-1.0, 0.0]}, {"c0": -1.0},
     {"gamma": -1.0}, {"box": [0.1, 1.0]}, {"c0": float("nan")}, {"precision": 7},
-    {"box": [100.0, 1.0]},
+    {"box": [100.0, 1.0]}, {"c0": 0.0, "u_ref": -1.0}, {"c0": 0.0, "u_ref": float("inf")},
 ])
 def test_create_system_rejects_invalid_parameters(bad):
     with pytest.raises(rsph.RsphError) as e:
@@ -62,3 +62,10 @@ def test_create_system_rejects_invalid_parameters(bad):
 def test_step_counts_rejects_null_arguments():
     v = [C.c_int64() for _ in range(3)]
     assert rsph.lib().rsph_step_counts(None, *[C.byref(x) for x in v]) == -1
+
+
+def test_params_struct_matches_the_header():
+    """The binding's record has the header's size (u_ref is the last field)."""
+    text = open(os.path.join(ROOT, "include", "rsph.h")).read()
+    assert "double u_ref;" in text
+    assert C.sizeof(rsph.Params) == 4 + 4 + 24 + 8 + 8 + 16 + 16 + 8 * 6 + 24 + 4 + 4 + 8
