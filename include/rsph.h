@@ -109,7 +109,11 @@ typedef struct {
     double p_out;         /* mean pressure of fluid l with |r - centroid| > r_eq + 3h */
     double n_in, n_out;   /* particle counts of the two means */
     uint32_t health;      /* RSPH_HEALTH_* bits */
-    uint32_t reserved;
+    uint32_t displaced_steps; /* advection steps whose binning found a particle more than one cell
+                                 (edge >= 2h, periodic distance) from where the previous binning put
+                                 it.  A diagnostic, not a fault: the first advection step from rest is
+                                 bounded by the viscous criterion of Eq. 16 alone and may carry
+                                 particles that far with the geometry frozen (section 3.3). */
 } rsph_observables;
 
 #define RSPH_HEALTH_NONFINITE 1u  /* NaN or Inf in velocity, density or acceleration */
@@ -117,8 +121,6 @@ typedef struct {
 #define RSPH_HEALTH_NEIGHBOURS 4u /* more neighbours than the list holds */
 #define RSPH_HEALTH_COINCIDENT 8u /* two neighbours closer than 1e-9 h */
 #define RSPH_HEALTH_DT 32u        /* acoustic step collapsed below 1e-12 of its no-flow value */
-#define RSPH_HEALTH_DISPLACEMENT 64u /* a particle moved more than one cell (edge >= 2h) between two
-                                        binnings: the advection step of Eq. 16 no longer bounds the motion */
 
 /* particle fields readable with rsph_read_particles, and their width per particle */
 enum {

@@ -711,8 +711,8 @@ std::vector<SysDyn> read_dyn(rsph_pool* P)
     return d;
 }
 
-constexpr uint32_t kFaultBits = kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident |
-                                kHealthDtCollapse | kHealthDisplacement;
+constexpr uint32_t kFaultBits =
+    kHealthNonFinite | kHealthDensity | kHealthNeighbours | kHealthCoincident | kHealthDtCollapse;
 constexpr int64_t kMaxSubsteps = 1000000;  // per advection step
 
 // m acoustic substeps for the systems inside an advection step (the others
@@ -1035,6 +1035,7 @@ void reset_dyn(rsph_system* s, bool keep_clock)
     d.stepping = 0;
     d.binned = 0;
     d.displaced = 0;
+    if (!keep_clock) d.n_displaced = 0;
     d.ksub_max = 0;
     d.state = kBoundary;
     d.sub_state = kIdle;
@@ -1361,6 +1362,7 @@ rsph_status rsph_read_observables(rsph_system* s, rsph_observables* out)
         out->p_in = o[23] > 0 ? o[22] / o[23] : 0.0;
         out->p_out = o[25] > 0 ? o[24] / o[25] : 0.0;
         out->health = d.health;
+        out->displaced_steps = (uint32_t)std::min<long long>(d.n_displaced, UINT32_MAX);
     });
 }
 

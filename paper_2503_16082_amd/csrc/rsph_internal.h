@@ -45,7 +45,6 @@ constexpr uint32_t kHealthNeighbours = 4u;
 constexpr uint32_t kHealthCoincident = 8u;
 constexpr uint32_t kHealthClose = 16u;  // two particles closer than 1e-3 dp (input check only)
 constexpr uint32_t kHealthDtCollapse = 32u;  // acoustic step below 1e-12 of its no-flow value
-constexpr uint32_t kHealthDisplacement = 64u;  // moved more than one cell between two binnings
 constexpr int64_t kMaxCells = 2048LL * 2048LL;  // capacity of the three-phase scan
 
 // per-particle flag bits, rebuilt every advection step
@@ -114,6 +113,7 @@ struct SysDyn {
     int32_t stepping;                // 1 while the advection-step prologue runs for this system
     int32_t binned;                  // 1: xd holds the positions of the last binning, slot by slot
     int32_t displaced;               // 1: the key pass found a particle more than one cell from it
+    long long n_displaced;           // advection steps whose binning found such a particle
     uint32_t health;
     int32_t ksub_max;                // most substeps in one advection step since the host last looked
     long long ksub;                  // substeps started in the current advection step

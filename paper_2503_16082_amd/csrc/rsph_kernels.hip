@@ -476,9 +476,8 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
         A.key[i] = key;
         gkey = (uint32_t)S.c_off + key;
         // the same slot held the same particle at the last binning: more than
-        // one cell of motion since then (periodic distance) is a fault.  It is
-        // noted apart from the health bits, which decide the state of this
-        // pass, and folded into them when the advection step begins.
+        // one cell of motion since then (periodic distance) is counted, once
+        // per advection step, when the step begins
         if (A.mode == 0 && Dy.binned) {
             const double xo[3] = {xold.x, xold.y, xold.z};
             bool far = false;
@@ -1558,7 +1557,7 @@ __device__ void begin_advection_step(const DevArrays& A, const SysConst& S, SysD
     D.dt[0] = fmin(dt_ac, dt_ad);
     D.state = kSubstepping;
     if (D.displaced) {
-        atomicOr(&D.health, kHealthDisplacement);
+        D.n_displaced += 1;
         D.displaced = 0;
     }
     if (dt_collapsed(S, dt_ac) || !(dt_ad > 0.0)) {

@@ -34,7 +34,7 @@ FIELDS = {
 KERNELS = ["bin", "neighbours", "advection", "shift", "colour", "force", "continuity",
            "event_floor"]
 
-HEALTH = {"nonfinite": 1, "density": 2, "neighbours": 4, "coincident": 8, "dt": 32, "displacement": 64}
+HEALTH = {"nonfinite": 1, "density": 2, "neighbours": 4, "coincident": 8, "dt": 32}
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENUMERIC",
           -6: "EBUSY"}
@@ -89,7 +89,7 @@ class Observables(C.Structure):
         ("n_in", C.c_double),
         ("n_out", C.c_double),
         ("health", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("displaced_steps", C.c_uint32),
     ]
 
 
@@ -244,7 +244,7 @@ class System:
             "vmax": np.array(o.vmax[:]), "centroid": np.array(o.centroid[:d]),
             "moment2": np.array(o.moment2[:]).reshape(3, 3)[:d, :d], "r_eq": o.r_eq,
             "p_in": o.p_in, "p_out": o.p_out, "n_in": o.n_in, "n_out": o.n_out,
-            "health": o.health,
+            "health": o.health, "displaced_steps": o.displaced_steps,
         }
 
     def binning(self):
@@ -359,3 +359,4 @@ class Pool:
             self.close()
         except Exception:
             pass
+

@@ -35,7 +35,7 @@ from . import workloads as WL
 
 
 # health bits that fault a system (RSPH_HEALTH_*; 16 is an input check only)
-FAULT_BITS = 1 | 2 | 4 | 8 | 32 | 64
+FAULT_BITS = 1 | 2 | 4 | 8 | 32
 
 
 def build_job(desc):

@@ -1,5 +1,6 @@
 """Boundary rules that need a device: the sound-speed rule of section 2
-(c0 = 0 in the parameters), and the displacement health check."""
+(c0 = 0 in the parameters), and the count of advection steps that moved a
+particle more than one cell."""
 import sys
 
 import numpy as np
@@ -58,12 +59,12 @@ def test_sound_speed_rule_needs_a_speed():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_displacement_beyond_one_cell_faults(precision):
+def test_displacement_beyond_one_cell_is_counted(precision):
     """A perfect lattice under a strong uniform gravity: the viscous limit of
     Eq. 16 (0.1 rho0 h^2 / eta = 0.1) lets every particle fall g dt^2 / 2 = 0.5,
     three cells of edge 1/6, within one advection step; the next binning finds
-    it and the system faults with the displacement bit.  The first step is
-    clean (no pair force acts on a uniformly moving lattice)."""
+    it and counts the step.  No pair force acts on a uniformly moving lattice,
+    so the system stays healthy and keeps stepping."""
     n_side = 16
     dp = 1.0 / n_side
     h = 1.3 * dp
@@ -74,10 +75,17 @@ def test_displacement_beyond_one_cell_faults(precision):
     s.set_particles(pts, np.zeros_like(pts), np.zeros(len(pts), np.int32))
     s.step(1)
     o = s.observables()
-    say(f"after one step: t={o['t']:.4f} dt_ad={o['dt_ad']:.4f} health={o['health']}")
+    say(f"after one step: t={o['t']:.4f} dt_ad={o['dt_ad']:.4f} displaced={o['displaced_steps']}")
     assert o["health"] == 0 and o["dt_ad"] == pytest.approx(0.1, rel=1e-12)
-    with pytest.raises(rsph.RsphError) as e:
-        s.step(1)
-    assert e.value.name == "ENUMERIC"
-    assert s.observables()["health"] & 64
+    assert o["displaced_steps"] == 0
+    s.step(1)
+    o = s.observables()
+    assert o["health"] == 0 and o["displaced_steps"] == 1
+    # a slow lattice (no gravity) is never counted
+    p["gravity"] = [0.0, 0.0, 0.0]
+    q = rsph.System(p, precision=precision)
+    q.set_particles(pts, np.full_like(pts, 1e-3), np.zeros(len(pts), np.int32))
+    q.step(3)
+    assert q.observables()["displaced_steps"] == 0
     s.close()
+    q.close()

@@ -39,10 +39,11 @@ def jobs():
     ]
 
 
-# trajectory tolerance after a few advection steps: FP64 against FP64 differs
-# by summation order only; the mixed form's pair sums carry FP32 rounding
-# (1e-5 per evaluation) into the state
-TRAJ = {0: (1e-9, 1e-12), 1: (1e-4, 1e-7)}
+# trajectory tolerance after a few advection steps (normwise velocity and
+# density deviation, position in units of dp): FP64 against FP64 differs by
+# summation order only; the mixed form's pair sums carry FP32 rounding (1e-5
+# per evaluation) into the state
+TRAJ = {0: (1e-9, 1e-10), 1: (1e-4, 1e-4)}
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -69,9 +70,9 @@ def test_pooled_jobs_match_the_oracle(precision):
         er = normwise(m.read("rho") - rho0, st.rho - rho0)
         dpos = m.read("pos") - O.wrap(p, st.pos)
         dpos -= np.round(dpos)
-        ex = np.abs(dpos).max()
+        ex = np.abs(dpos).max() / p["dp"]
         say(f"pooled job {k} (n={len(w['pos'])}, {n} steps, precision {precision}): "
-            f"vel {ev:.2e} rho {er:.2e} pos {ex:.2e}")
+            f"vel {ev:.2e} rho {er:.2e} pos {ex:.2e} dp")
         assert ev < tol_v and er < tol_v and ex < tol_x
     # one evaluation of every rate of a pool member at its current state,
     # against the oracle at the same state
