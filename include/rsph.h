@@ -206,6 +206,25 @@ rsph_status rsph_step(rsph_system* sys, int64_t n_outer);
  * rsph_read_particles.  ESTATE without particles. */
 rsph_status rsph_eval_rates(rsph_system* sys);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * single evaluation as rsph_create_system + rsph_set_particles +
+ * rsph_eval_rates + rsph_read_particles(ACC, RATE_DRHO), with every particle
+ * array in DEVICE memory owned by the caller and no device allocation by the
+ * library.  pos, vel (n x dim), phase (n), mass and rho (n, or NULL for the
+ * defaults of rsph_set_particles) are read; acc (n x dim) and drho_rate (n)
+ * are written, in the caller's particle order, on hip_stream (NULL: the null
+ * stream); the call returns when they are written.  Everything else lives in
+ * one fixed 64 MiB array per device that the library holds until the process
+ * ends (about 65,000 particles in 2D and 40,000 in 3D): larger inputs are
+ * rejected with EINVAL.  Calls on one device share that array, so calls that
+ * overlap on one device (two host threads, or two streams) race.  params must
+ * have c0 > 0.  EINVAL also for a fluid outside {0,1}, a non-finite value, a
+ * mass or density <= 0, or two particles closer than 1e-3 dp. */
+rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_t n, const double* pos,
+                                    const double* vel, const int32_t* phase, const double* mass,
+                                    const double* rho, double* acc, double* drho_rate, void* hip_stream);
+
 /* Reduces the observables on the device and copies them to *out (caller
  * owned): clock and step counts (section 3.3), total momentum (conserved by
  * the antisymmetric pair terms of sections 3.1 and 4), kinetic energy, fluid

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "rsph.h"
@@ -300,8 +301,10 @@ void free_arrays(rsph_pool* P)
     P->S_cap = 0;
 }
 
-// Walks every device array of a pool with the capacities given.
-size_t plan_arrays(Alloc& M, int dim, int precision, DevArrays& A, int32_t*& mask, long long*& targets,
+// Walks every device array of a pool with the capacities given (M: the pool's
+// allocator, or a carver of the fixed scratch array).
+template <typename Mem>
+size_t plan_arrays(Mem& M, int dim, int precision, DevArrays& A, int32_t*& mask, long long*& targets,
                    int32_t*& work, int64_t Pc, int64_t Cc, int Sc)
 {
     A = DevArrays{};
@@ -310,61 +313,61 @@ size_t plan_arrays(Alloc& M, int dim, int precision, DevArrays& A, int32_t*& mas
     A.C = Cc;
     A.kmax = kmax_of(dim);
     for (int a = 0; a < 3; ++a) {
-        A.pos[a] = M.take<double>(Pc);
-        A.vel[a] = M.take<double>(Pc);
-        A.pos2[a] = M.take<double>(Pc);
-        A.vel2[a] = M.take<double>(Pc);
+        A.pos[a] = M.template take<double>(Pc);
+        A.vel[a] = M.template take<double>(Pc);
+        A.pos2[a] = M.template take<double>(Pc);
+        A.vel2[a] = M.template take<double>(Pc);
     }
-    A.rho = M.take<double>(Pc);
-    A.drho = M.take<double>(Pc);
-    A.mass = M.take<double>(Pc);
-    A.id = M.take<int32_t>(Pc);
-    A.phase = M.take<int32_t>(Pc);
-    A.rho2 = M.take<double>(Pc);
-    A.drho2 = M.take<double>(Pc);
-    A.mass2 = M.take<double>(Pc);
-    A.id2 = M.take<int32_t>(Pc);
-    A.phase2 = M.take<int32_t>(Pc);
-    A.key = M.take<uint32_t>(Pc);
-    A.rank = M.take<int32_t>(Pc);
-    A.perm = M.take<int32_t>(Pc);
-    A.tmp = M.take<int32_t>(Pc);
-    A.cell_cnt = M.take<int32_t>(Cc);
-    A.cell_start = M.take<int32_t>(Cc + 1);
-    A.cell_sys = M.take<int32_t>(Cc);
-    A.scan_part = M.take<int32_t>(2048);
-    A.wave_sys = M.take<int32_t>(Pc / kWave);
-    A.geo = M.take<char>(Pc * r4);
+    A.rho = M.template take<double>(Pc);
+    A.drho = M.template take<double>(Pc);
+    A.mass = M.template take<double>(Pc);
+    A.id = M.template take<int32_t>(Pc);
+    A.phase = M.template take<int32_t>(Pc);
+    A.rho2 = M.template take<double>(Pc);
+    A.drho2 = M.template take<double>(Pc);
+    A.mass2 = M.template take<double>(Pc);
+    A.id2 = M.template take<int32_t>(Pc);
+    A.phase2 = M.template take<int32_t>(Pc);
+    A.key = M.template take<uint32_t>(Pc);
+    A.rank = M.template take<int32_t>(Pc);
+    A.perm = M.template take<int32_t>(Pc);
+    A.tmp = M.template take<int32_t>(Pc);
+    A.cell_cnt = M.template take<int32_t>(Cc);
+    A.cell_start = M.template take<int32_t>(Cc + 1);
+    A.cell_sys = M.template take<int32_t>(Cc);
+    A.scan_part = M.template take<int32_t>(2048);
+    A.wave_sys = M.template take<int32_t>(Pc / kWave);
+    A.geo = M.template take<char>(Pc * r4);
     for (int k = 0; k < 2; ++k) {
-        A.vbuf[k] = M.take<char>(Pc * r4);
-        A.th[k] = M.take<char>(Pc * r4);
-        A.bm[k] = M.take<char>(Pc * r4);
+        A.vbuf[k] = M.template take<char>(Pc * r4);
+        A.th[k] = M.template take<char>(Pc * r4);
+        A.bm[k] = M.template take<char>(Pc * r4);
     }
-    A.col = M.take<char>(Pc * r4);
-    A.av = M.take<char>(Pc * r4);
-    A.flags = M.take<uint8_t>(Pc);
-    A.nbr = M.take<uint32_t>(Pc * (size_t)A.kmax);
-    A.ncount = M.take<int32_t>(Pc);
-    A.xd = M.take<double>(Pc * 4);
-    A.r_acc = M.take<double>(3 * Pc);
-    A.r_accp = M.take<double>(3 * Pc);
-    A.r_accs = M.take<double>(3 * Pc);
-    A.r_accv = M.take<double>(3 * Pc);
-    A.r_gradc = M.take<double>(3 * Pc);
-    A.r_drho = M.take<double>(Pc);
-    A.r_b = M.take<double>(9 * Pc);
-    A.r_dr = M.take<double>(3 * Pc);
-    A.r_sigma = M.take<double>(Pc);
-    A.obs_part = M.take<double>((Pc / kWave) * kObsPart);
-    A.vpart = M.take<unsigned long long>(2 * (Pc * kMaxLanes / kWave));
-    A.obs_out = M.take<double>((size_t)Sc * kObsOut);
-    A.sc = M.take<SysConst>(Sc);
-    A.sd = M.take<SysDyn>(Sc);
-    mask = M.take<int32_t>(Sc);
-    targets = M.take<long long>(Sc);
+    A.col = M.template take<char>(Pc * r4);
+    A.av = M.template take<char>(Pc * r4);
+    A.flags = M.template take<uint8_t>(Pc);
+    A.nbr = M.template take<uint32_t>(Pc * (size_t)A.kmax);
+    A.ncount = M.template take<int32_t>(Pc);
+    A.xd = M.template take<double>(Pc * 4);
+    A.r_acc = M.template take<double>(3 * Pc);
+    A.r_accp = M.template take<double>(3 * Pc);
+    A.r_accs = M.template take<double>(3 * Pc);
+    A.r_accv = M.template take<double>(3 * Pc);
+    A.r_gradc = M.template take<double>(3 * Pc);
+    A.r_drho = M.template take<double>(Pc);
+    A.r_b = M.template take<double>(9 * Pc);
+    A.r_dr = M.template take<double>(3 * Pc);
+    A.r_sigma = M.template take<double>(Pc);
+    A.obs_part = M.template take<double>((Pc / kWave) * kObsPart);
+    A.vpart = M.template take<unsigned long long>(2 * (Pc * kMaxLanes / kWave));
+    A.obs_out = M.template take<double>((size_t)Sc * kObsOut);
+    A.sc = M.template take<SysConst>(Sc);
+    A.sd = M.template take<SysDyn>(Sc);
+    mask = M.template take<int32_t>(Sc);
+    targets = M.template take<long long>(Sc);
     A.work_cap = 1 << 16;
     A.work = nullptr;
-    work = M.take<int32_t>(A.work_cap);
+    work = M.template take<int32_t>(A.work_cap);
     return M.bytes;
 }
 
@@ -1695,3 +1698,140 @@ void rsph_pool_destroy(rsph_pool* P)
 }
 
 }  // extern "C"
+
+// ---- evaluation without allocation ------------------------------------------
+
+namespace {
+
+// The working memory of rsph_eval_rates_noalloc: one fixed array per device,
+// held until the process ends.  Host code must not pass its name to a kernel
+// (that is a host-side stand-in); the device address comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_address()
+{
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(RSPH_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> g(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) fail(RSPH_EDEVICE, "scratch array has no device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Carves the arrays of plan_arrays out of the scratch array, 256-byte aligned.
+struct ScratchCarver {
+    char* base;
+    size_t cap;
+    size_t bytes = 0;
+    template <typename T>
+    T* take(size_t count)
+    {
+        const size_t b = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+        if (bytes + b > cap) fail(RSPH_EINVAL, "input too large for the evaluation scratch");
+        T* p = (T*)(base + bytes);
+        bytes += b;
+        return p;
+    }
+};
+
+// Bytes the carver needs for one system of n particles (arrays 256-byte aligned)
+struct CountCarver {
+    size_t bytes = 0;
+    template <typename T>
+    T* take(size_t count)
+    {
+        bytes += (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+        return nullptr;
+    }
+};
+
+}  // namespace
+
+extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_t n, const double* pos,
+                                               const double* vel, const int32_t* phase, const double* mass,
+                                               const double* rho, double* acc, double* drho_rate,
+                                               void* hip_stream)
+{
+    return guarded(nullptr, [&] {
+        validate_params(params);
+        if (!(params->c0 > 0)) fail(RSPH_EINVAL, "this entry point needs c0 > 0");
+        if (n < 1) fail(RSPH_EINVAL, "n must be >= 1");
+        if (n > (int64_t)INT32_MAX / 2) fail(RSPH_EINVAL, "too many particles");
+        if (!pos || !vel || !phase || !acc || !drho_rate) fail(RSPH_EINVAL, "pos, vel, phase, acc and drho are required");
+        char* base = (char*)scratch_address();
+        // a pool of one system whose arrays live in the scratch array
+        rsph_pool P;
+        P.dim = params->dim;
+        P.precision = params->precision;
+        P.stream = (hipStream_t)hip_stream;
+        P.standalone = true;
+        P.graphs = false;
+        rsph_system s;
+        s.pool = &P;
+        s.prm = *params;
+        s.sc = make_const(*params);
+        s.ncells = s.sc.ncells;
+        s.n = n;
+        Layout L = plan({}, &s);
+        CountCarver count;
+        DevArrays probe;
+        int32_t *m0 = nullptr, *w0 = nullptr;
+        long long* t0 = nullptr;
+        const size_t need = plan_arrays(count, P.dim, P.precision, probe, m0, t0, w0, L.P, L.C, 1) + 256;
+        if (need > kScratchBytes) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "%lld particles need %zu bytes of evaluation scratch; it holds %zu",
+                          (long long)n, need, kScratchBytes);
+            fail(RSPH_EINVAL, buf);
+        }
+        ScratchCarver carve{base, kScratchBytes};
+        plan_arrays(carve, P.dim, P.precision, P.A, P.d_mask, P.d_targets, P.work_dev, L.P, L.C, 1);
+        int32_t* bad = carve.take<int32_t>(1);
+        P.P_cap = L.P;
+        P.C_cap = L.C;
+        P.S_cap = 1;
+        const Launch Lc = launch_of(&P);
+        // the scratch keeps the last call's contents: clear what starts at zero
+        launch_fill_i32(Lc, P.A.cell_cnt, L.C, 0);
+        launch_fill_i32(Lc, P.work_dev, P.A.work_cap, 0);
+        launch_fill_i32(Lc, bad, 1, 0);
+        repack(&P, {&s});
+        s.has_particles = true;
+        s.sc.p_n = n;
+        HIPCHECK(hipMemcpyAsync((void*)(P.A.sc + s.row), &s.sc, sizeof(SysConst), hipMemcpyHostToDevice, P.stream));
+        launch_load_particles(Lc, P.A, s.p_off, n, pos, vel, phase, mass, rho, s.sc.box, s.sc.rho0, s.sc.sigma0,
+                              bad);
+        int32_t bad_h = 0;
+        HIPCHECK(hipMemcpyAsync(&bad_h, bad, sizeof bad_h, hipMemcpyDeviceToHost, P.stream));
+        HIPCHECK(hipStreamSynchronize(P.stream));
+        if (bad_h) fail(RSPH_EINVAL, "a fluid outside {0,1}, a non-finite value, or a mass or density <= 0");
+        reset_dyn(&s, false);
+        check_spacing(&s);
+        // one evaluation, as rsph_eval_rates
+        std::vector<int32_t> mask(1, 1);
+        set_mask(&P, mask);
+        rebuild(&P, 1, -1);
+        DevArrays A = kernel_view(&P);
+        A.work = nullptr;
+        A.mode = 1;
+        launch_advection(Lc, A, Ev{});
+        launch_shift(Lc, A, Ev{});
+        launch_colour(Lc, A, Ev{});
+        launch_force(Lc, A, Ev{});
+        launch_continuity(Lc, A, Ev{}, -1);
+        launch_store_rates(Lc, A, s.p_off, n, acc, drho_rate);
+        HIPCHECK(hipStreamSynchronize(P.stream));
+        P.systems.clear();
+    });
+}

@@ -225,6 +225,10 @@ void launch_force(const Launch& L, const DevArrays& A, Ev ev);
 void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group);
 void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group);
 void launch_observables(const Launch& L, const DevArrays& A);
+void launch_load_particles(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, const double* pos,
+                           const double* vel, const int32_t* phase, const double* mass, const double* rho,
+                           const double* box, const double* rho0, double sigma0, int32_t* bad);
+void launch_store_rates(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, double* acc, double* drho);
 
 constexpr int kObsPart = 16;  // partial sums per wave and pass
 constexpr int kObsOut = 32;   // reduced values per system

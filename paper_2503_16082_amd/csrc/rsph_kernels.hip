@@ -2320,6 +2320,85 @@ void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group
     RSPH_DISPATCH(k_continuity, G2, G3, ev, A, group);
 }
 
+// ---------------------------------------------------------------------------
+// device-resident particle input and rate output of the evaluation that works
+// in the caller's device buffers (no staging through host memory)
+// ---------------------------------------------------------------------------
+
+// Particle i of the caller (row-major n x dim arrays on the device) into slot
+// p_off + i: position wrapped into the box, velocity, mass (NULL: rho0 /
+// sigma0), density (NULL: rho0), a zero continuity rate, caller index and
+// fluid.  Inputs that the host could not check (a fluid outside {0, 1}, a
+// non-finite value, a mass or density <= 0) set *bad; the fluid is then
+// clamped so that every later index stays in bounds.
+__global__ __launch_bounds__(kBlock) void k_load_particles(DevArrays A, int64_t p_off, int64_t n, int dim,
+                                                           const double* pos, const double* vel,
+                                                           const int32_t* phase, const double* mass,
+                                                           const double* rho, double3 box, double2 rho0,
+                                                           double sigma0, int32_t* bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = p_off + i;
+    bool wrong = false;
+    int ph = phase[i];
+    if (ph != 0 && ph != 1) {
+        wrong = true;
+        ph = ph < 0 ? 0 : 1;
+    }
+    const double L[3] = {box.x, box.y, box.z};
+    for (int a = 0; a < 3; ++a) {
+        double q = a < dim ? pos[i * dim + a] : 0.0;
+        const double v = a < dim ? vel[i * dim + a] : 0.0;
+        wrong |= !isfinite(q) || !isfinite(v);
+        if (a < dim) {
+            q = q - L[a] * floor(q / L[a]);
+            if (q >= L[a]) q -= L[a];
+        }
+        A.pos[a][o] = q;
+        A.vel[a][o] = v;
+    }
+    const double r0 = ph ? rho0.y : rho0.x;
+    const double m = mass ? mass[i] : r0 / sigma0;
+    const double r = rho ? rho[i] : r0;
+    wrong |= !isfinite(m) || !(m > 0.0) || !isfinite(r) || !(r > 0.0);
+    A.mass[o] = m;
+    A.rho[o] = r;
+    A.drho[o] = 0.0;
+    A.id[o] = (int32_t)i;
+    A.phase[o] = ph;
+    if (wrong) atomicOr(bad, 1);
+}
+
+// Rates of the last evaluation, from slot order into the caller's order:
+// acc (n x dim) and the continuity rate (n).
+__global__ __launch_bounds__(kBlock) void k_store_rates(DevArrays A, int64_t p_off, int64_t n, int dim,
+                                                        double* acc, double* drho)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = p_off + k;
+    const int64_t id = A.id[o];
+    for (int a = 0; a < dim; ++a) acc[id * dim + a] = A.r_acc[3 * o + a];
+    drho[id] = A.r_drho[o];
+}
+
+void launch_load_particles(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, const double* pos,
+                           const double* vel, const int32_t* phase, const double* mass, const double* rho,
+                           const double* box, const double* rho0, double sigma0, int32_t* bad)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_load_particles, flat_grid(n), dim3(kBlock), 0, L.stream, A, p_off, n, L.dim, pos,
+                           vel, phase, mass, rho, double3{box[0], box[1], box[2]}, double2{rho0[0], rho0[1]},
+                           sigma0, bad);
+}
+
+void launch_store_rates(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, double* acc, double* drho)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_store_rates, flat_grid(n), dim3(kBlock), 0, L.stream, A, p_off, n, L.dim, acc, drho);
+}
+
 void launch_observables(const Launch& L, const DevArrays& A)
 {
     const int64_t nwaves = A.P / kWave;

@@ -99,7 +99,7 @@ SYMBOLS = [
     "rsph_read_binning", "rsph_read_neighbours", "rsph_set_kernel_timing", "rsph_set_launch_mode",
     "rsph_read_kernel_timing", "rsph_destroy_system", "rsph_status_string", "rsph_last_error",
     "rsph_pool_create", "rsph_pool_admit", "rsph_pool_step", "rsph_pool_bytes", "rsph_step_counts",
-    "rsph_pool_release", "rsph_pool_destroy",
+    "rsph_pool_release", "rsph_pool_destroy", "rsph_eval_rates_noalloc",
 ]
 
 _lib = None
@@ -143,6 +143,7 @@ def lib():
     L.rsph_pool_release.argtypes = [vp, vp]
     L.rsph_pool_destroy.argtypes = [vp]
     L.rsph_pool_destroy.restype = None
+    L.rsph_eval_rates_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in SYMBOLS:
         f = getattr(L, name)
         if f.restype is C.c_int:  # ctypes default
@@ -360,3 +361,16 @@ class Pool:
         except Exception:
             pass
 
+
+def eval_rates_noalloc(params, n, pos, vel, phase, acc, drho, mass=None, rho=None, precision=None, stream=None):
+    """rsph_eval_rates_noalloc on caller-owned device buffers, given by their
+    device addresses (integers, e.g. torch's data_ptr()); mass and rho may be
+    None.  Raises RsphError on a non-zero status."""
+    prm = make_params(params, precision)
+    st = lib().rsph_eval_rates_noalloc(C.byref(prm), int(n), C.c_void_p(pos), C.c_void_p(vel),
+                                       C.c_void_p(phase), None if mass is None else C.c_void_p(mass),
+                                       None if rho is None else C.c_void_p(rho), C.c_void_p(acc),
+                                       C.c_void_p(drho), None if stream is None else C.c_void_p(stream))
+    if st != 0:
+        msg = lib().rsph_last_error(None)
+        raise RsphError(st, msg.decode() if msg else "")
