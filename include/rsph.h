@@ -12,7 +12,16 @@
  * Eqs. 14-15); surface stress and its divergence with the projected,
  * momentum-conserving penalty force (section 4, Eqs. 19-33); dual-criteria time
  * stepping (section 3.3, Eqs. 16-18); 5th-order Wendland kernel with h = 1.3 dp
- * and cut-off 2h (section 5).  Domains are fully periodic boxes.
+ * and cut-off 2h (section 5).  Domains are periodic boxes; walls (the shear and
+ * impact cases of section 5 use them; the paper gives no wall scheme) are
+ * layers of wall particles (fluid id 2) inside the box, which never move and
+ * act on the fluid through the one-sided Riemann wall condition of the
+ * Riemann-SPH scheme the paper builds on: a wall neighbour is the mirror of the
+ * fluid particle (its density, volume and pressure, the latter continued
+ * hydrostatically by -rho g . r_ij, and the normal velocity reflected about the
+ * wall's), with the fluid's viscosity against the wall's velocity (no slip) and
+ * no colour.  Three layers of dp (more than the 2.6 dp support) behind a wall
+ * face keep the fluid from seeing through it.
  *
  * Conventions used by every call:
  *  - every pointer argument named in a signature is a HOST pointer; the library
@@ -90,7 +99,8 @@ typedef struct {
     double u_ref;       /* anticipated largest flow speed of the c0 = 0 rule (>= 0) [0] */
 } rsph_params;
 
-/* Observables of one system, all FP64, reduced on the device in a fixed order. */
+/* Observables of one system, all FP64, reduced on the device in a fixed order
+ * over the fluid particles (wall particles are left out). */
 typedef struct {
     double t;             /* simulated time */
     int64_t n_outer;      /* advection steps taken */
@@ -130,7 +140,7 @@ enum {
     RSPH_FIELD_P = 3,      /* 1: c0^2 (rho - rho0) */
     RSPH_FIELD_DRHO = 4,   /* 1: last continuity rate */
     RSPH_FIELD_MASS = 5,   /* 1 */
-    RSPH_FIELD_PHASE = 6,  /* 1 (0.0 or 1.0) */
+    RSPH_FIELD_PHASE = 6,  /* 1 (0.0, 1.0, or 2.0 for a wall particle) */
     /* rates of the last rsph_eval_rates: */
     RSPH_FIELD_ACC = 7,    /* dim: a^p + a^s + a^v + g */
     RSPH_FIELD_ACC_P = 8,  /* dim: Riemann pressure acceleration (Eq. 7) */
@@ -157,7 +167,7 @@ void rsph_params_default(rsph_params* p);
  * discretised with the Wendland kernel of section 5 (h = 1.3 dp, cut-off 2h) in
  * a periodic box.  Validates params: dim in {2,3}; dp, rho0 > 0; c0 > 0, or
  * c0 = 0 with u_ref >= 0 (the section 2 rule, applied by rsph_set_particles);
- * eta, gamma >= 0; at least 3 cells of edge >= 2h per axis and at most 1024;
+ * eta, gamma >= 0; at least 3 cells of edge >= 2h per axis and at most 512;
  * all values finite.  hip_stream: a hipStream_t owned by the caller, or NULL
  * for a stream of the library's own.  *out is owned by the caller and freed with
  * rsph_destroy_system.  EINVAL (nothing created) otherwise. */
@@ -165,15 +175,17 @@ rsph_status rsph_create_system(const rsph_params* params, void* hip_stream, rsph
 
 /* Sets (or resets) all particles of the two-fluid system of section 2, each a
  * Lagrangian particle with position, velocity, fluid and mass (section 3.1):
- * pos, vel (n x dim), phase (n, in {0,1}), mass (n, NULL -> rho0[phase] / sigma0
- * with sigma0 the lattice kernel sum, so a perfect lattice has rho = rho0), rho
- * (n, NULL -> rho0[phase]; it sets the initial pressure by Eq. 3).  Positions are
+ * pos, vel (n x dim), phase (n, in {0,1}, or 2 for a wall particle, whose
+ * velocity is the wall's), mass (n, NULL -> rho0[phase] / sigma0 with sigma0 the
+ * lattice kernel sum, so a perfect lattice has rho = rho0; 1 / sigma0 for a
+ * wall particle), rho (n, NULL -> rho0[phase], 1 for a wall particle; it sets
+ * the initial pressure by Eq. 3).  Positions are
  * wrapped into the box.  With c0 = 0 in the system's params, c0 becomes
- * 10 max(u_ref, largest |vel|) here (section 2).  Resets t, counters, density
+ * 10 max(u_ref, largest |vel|, walls included) here (section 2).  Resets t, counters, density
  * rates and the fault state unless opts has RSPH_KEEP_CLOCK (then t and
  * counters are kept: resume).  The arrays are host memory owned by the caller
  * and copied before the call returns.  EINVAL (nothing changed) on n < 1,
- * NaN/Inf, a phase outside {0,1}, mass or rho <= 0, two particles closer than
+ * NaN/Inf, a phase outside {0,1,2}, mass or rho <= 0, two particles closer than
  * 1e-3 dp, or c0 = 0 with u_ref = 0 and every velocity zero.
  * The extra rho argument (beyond particles, velocities, fluids and masses) lets
  * a caller restore a state for a bitwise resume. */
@@ -219,7 +231,7 @@ rsph_status rsph_eval_rates(rsph_system* sys);
  * ends (about 65,000 particles in 2D and 40,000 in 3D): larger inputs are
  * rejected with EINVAL.  Calls on one device share that array, so calls that
  * overlap on one device (two host threads, or two streams) race.  params must
- * have c0 > 0.  EINVAL also for a fluid outside {0,1}, a non-finite value, a
+ * have c0 > 0.  EINVAL also for a fluid id outside {0,1,2}, a non-finite value, a
  * mass or density <= 0, or two particles closer than 1e-3 dp. */
 rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_t n, const double* pos,
                                     const double* vel, const int32_t* phase, const double* mass,

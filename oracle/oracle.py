@@ -6,8 +6,8 @@ compiled from ``rsph_oracle.c`` by the repository's build step; this module only
 marshals numpy arrays into it.
 
 Every function mirrors one C entry point; the method's arithmetic lives in C.
-Particle arrays are row-major ``(n, dim)`` float64; phases are int32 in {0, 1}
-(0 = fluid k, the droplet; 1 = fluid l).
+Particle arrays are row-major ``(n, dim)`` float64; phases are int32 in {0, 1, 2}
+(0 = fluid k, the droplet; 1 = fluid l; 2 = a wall particle, which never moves).
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ NO_DENSITY_SUMMATION = 4
 GBAR_OWN_PHASE_AVERAGE = 8
 PENALTY_R3 = 16
 NO_SURFACE = 32
+WALL = 2
 
 
 class OrcParams(C.Structure):
@@ -287,7 +288,9 @@ class State:
         n = self.pos.shape[0]
         self.vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(n, d).copy()
         self.phase = np.ascontiguousarray(phase, dtype=np.int32).copy()
-        rho0 = np.asarray(p["rho0"], dtype=np.float64)
+        # fluid ids 0 and 1 are the fluids k and l, 2 marks a wall particle
+        # (reference density 1, so that its volume is the lattice volume)
+        rho0 = np.asarray(list(p["rho0"]) + [1.0], dtype=np.float64)
         if mass is None:
             h = p["dp"] * p.get("h_over_dp", 1.3)
             mass = rho0[self.phase] / sigma0(d, h, p["dp"])

@@ -27,7 +27,19 @@
  *  - kernel values and gradients are frozen over one advection step (section
  *    3.3); volumes V = m / rho always use the current density;
  *  - density is re-initialised by a normalised summation at every advection
- *    step (the paper evolves it by Eq. 6 only; flag ORC_NO_DENSITY_SUMMATION).
+ *    step (the paper evolves it by Eq. 6 only; flag ORC_NO_DENSITY_SUMMATION);
+ *  - walls (the paper gives no wall scheme; its shear and impact cases use
+ *    walls): particles of fluid id 2 that never move, with the one-sided
+ *    Riemann wall condition of the Riemann-SPH scheme the paper builds on
+ *    (Zhang, Hu and Adams 2017): a wall neighbour j of fluid particle i is the
+ *    mirror of i, rho_R = rho_i, U_R = 2 U_w - U_L with U_w = -v_w . e_ij the
+ *    wall's velocity along the pair axis, p_R = p_i - rho_i g . r_ij
+ *    (hydrostatic), and the mirror's volume V_i in the pressure, continuity
+ *    and viscous sums; its viscosity is the fluid's (no slip against v_w);
+ *    walls carry no colour, so no surface stress or penalty acts across them;
+ *    they fill the kernel support, with their own volume, in the density
+ *    summation and in the correction matrix and position shift (with their
+ *    own B).
  *
  * Compiled with -ffp-contract=off so that the neighbour predicate and the cell
  * keys are evaluated with one rounding per operation, as written.
@@ -48,6 +60,9 @@
 #define ORC_GBAR_OWN_PHASE_AVERAGE 8u
 #define ORC_PENALTY_R3 16u
 #define ORC_NO_SURFACE 32u
+
+/* fluid id of wall particles (0 and 1 are the fluids k and l) */
+#define ORC_WALL 2
 
 typedef struct {
     int32_t dim;
@@ -440,9 +455,11 @@ static void viscous_acc(const orc_params* P, const nb_t* nb, int64_t i, const do
     double s[3] = {0, 0, 0};
     for (int64_t k = 0; k < nb->n; ++k) {
         int64_t j = nb->j[k];
-        double eta_j = P->eta[phase[j]];
+        /* a wall neighbour has the fluid's own viscosity: the harmonic mean is
+         * then eta_i, and v_j is the wall's velocity (no slip) */
+        double eta_j = phase[j] == ORC_WALL ? eta_i : P->eta[phase[j]];
         double eta_bar = (eta_i + eta_j) > 0.0 ? 2.0 * eta_i * eta_j / (eta_i + eta_j) : 0.0;
-        double Vj = mass[j] / rho[j];
+        double Vj = phase[j] == ORC_WALL ? mass[i] / rho[i] : mass[j] / rho[j];
         double f = eta_bar * nb->dW[k] / nb->r[k] * Vj;
         for (int a = 0; a < d; ++a) s[a] += f * (vel[i * d + a] - vel[j * d + a]);
     }
@@ -540,6 +557,7 @@ static void colour_gradient(const orc_params* P, const nb_t* nb, int64_t i, cons
     g[0] = g[1] = g[2] = 0.0;
     for (int64_t k = 0; k < nb->n; ++k) {
         int64_t j = nb->j[k];
+        if (phase[j] == ORC_WALL) continue; /* walls carry no colour */
         double Cij = (phase[j] != phase[i]) ? 1.0 : 0.0;
         double phi_i = phi_of(P, phase[i], phase[j]);
         double Vj = mass[j] / rho[j];
@@ -594,7 +612,8 @@ static void momentum_rates(const orc_params* P, const nb_t* nb, int64_t i, const
     stress_of(P, gradC + 3 * i, Ni, Ti, Pii);
     for (int64_t k = 0; k < nb->n; ++k) {
         int64_t j = nb->j[k];
-        double Vj = mass[j] / rho[j];
+        /* a wall neighbour enters with the mirror's volume V_i */
+        double Vj = phase[j] == ORC_WALL ? mass[i] / rho[i] : mass[j] / rho[j];
         double e[3];
         unit(nb, k, e);
         double dW = nb->dW[k];
@@ -606,19 +625,29 @@ static void momentum_rates(const orc_params* P, const nb_t* nb, int64_t i, const
             UL -= vel[i * d + a] * e[a];
             UR -= vel[j * d + a] * e[a];
         }
+        double pR = p[j];
+        if (phase[j] == ORC_WALL) {
+            /* the wall's mirrored state: rho_R = rho_L, U_R = 2 U_w - U_L,
+             * p_R = p_L - rho_L g . r_ij */
+            double grij = 0.0;
+            for (int a = 0; a < d; ++a) grij += P->gravity[a] * nb->rij[3 * k + a];
+            rhoR = rhoL;
+            UR = 2.0 * UR - UL;
+            pR = p[i] - rhoL * grij;
+        }
         double cL = P->c0, cR = P->c0;
         double ZL = rhoL * cL, ZR = rhoR * cR;
         /* Eq. 11, numerator pressures read as densities */
         double lim = (rhoL + rhoR) * (UL - UR) / (ZL + ZR);
         double beta = fmin(3.0 * fmax(lim, 0.0), 1.0);
         /* Eq. 12: density-weighted pressure average */
-        double pbar = (rho[i] * p[j] + rho[j] * p[i]) / (rho[i] + rho[j]);
+        double pbar = (rhoL * pR + rhoR * p[i]) / (rhoL + rhoR);
         /* Eq. 8: star pressure */
         double Pstar = pbar + beta * ZL * ZR * (UL - UR) / (ZL + ZR);
         /* Eq. 7 */
         for (int a = 0; a < d; ++a) sp[a] += Pstar * dW * e[a] * Vj;
 
-        if (no_surf) continue;
+        if (no_surf || phase[j] == ORC_WALL) continue;
         /* Eqs. 33 with Eq. 24 */
         int same = phase[i] == phase[j];
         double Nj[9], Tj[9], Pij[9];
@@ -684,12 +713,12 @@ static double continuity_rate(const orc_params* P, const nb_t* nb, int64_t i, co
                               const double* rho, const double* p, const double* mass,
                               const int32_t* phase)
 {
-    (void)phase;
     int d = P->dim;
     double s = 0.0;
     for (int64_t k = 0; k < nb->n; ++k) {
         int64_t j = nb->j[k];
-        double Vj = mass[j] / rho[j];
+        /* a wall neighbour enters with the mirror's volume V_i */
+        double Vj = phase[j] == ORC_WALL ? mass[i] / rho[i] : mass[j] / rho[j];
         double e[3];
         unit(nb, k, e);
         double UL = 0.0, UR = 0.0, vie = 0.0;
@@ -698,16 +727,25 @@ static double continuity_rate(const orc_params* P, const nb_t* nb, int64_t i, co
             UR -= vel[j * d + a] * e[a];
             vie += vel[i * d + a] * e[a];
         }
-        double ZL = rho[i] * P->c0, ZR = rho[j] * P->c0;
-        double Ustar = (ZL * UL + ZR * UR + p[i] - p[j]) / (ZL + ZR);
+        double ZL = rho[i] * P->c0, ZR = rho[j] * P->c0, pR = p[j];
+        if (phase[j] == ORC_WALL) {
+            /* mirrored wall state, as in the momentum equation */
+            double grij = 0.0;
+            for (int a = 0; a < d; ++a) grij += P->gravity[a] * nb->rij[3 * k + a];
+            ZR = ZL;
+            UR = 2.0 * UR - UL;
+            pR = p[i] - rho[i] * grij;
+        }
+        double Ustar = (ZL * UL + ZR * UR + p[i] - pR) / (ZL + ZR);
         s += (vie + Ustar) * nb->dW[k] * Vj;
     }
     return 2.0 * rho[i] * s;
 }
 
-/* Eq. 3 */
+/* Eq. 3 (walls: no pressure of their own; a wall pair mirrors the fluid's) */
 static double eos(const orc_params* P, double rho, int ph)
 {
+    if (ph == ORC_WALL) return 0.0;
     return P->c0 * P->c0 * (rho - P->rho0[ph]);
 }
 
@@ -743,6 +781,7 @@ static void phase_vmax(const orc_params* P, int64_t n, const double* vel, const 
     int d = P->dim;
     vmax[0] = vmax[1] = 0.0;
     for (int64_t i = 0; i < n; ++i) {
+        if (phase[i] == ORC_WALL) continue;
         double s = 0.0;
         for (int a = 0; a < d; ++a) s += vel[i * d + a] * vel[i * d + a];
         s = sqrt(s);
@@ -805,18 +844,21 @@ int orc_eval_rates(const orc_params* P, int64_t n, const double* pos, const doub
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i) {
         if (!need[i]) continue;
-        colour_gradient(P, &nb[i], i, rho, mass, phase, gradC + 3 * i);
+        if (phase[i] != ORC_WALL) colour_gradient(P, &nb[i], i, rho, mass, phase, gradC + 3 * i);
         correction_matrix(P, &nb[i], rho, mass, B + (size_t)d * d * i);
     }
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < nt; ++t) {
         int64_t i = targets ? targets[t] : t;
-        double ap[3], as[3], av[3], dr[3];
-        momentum_rates(P, &nb[i], i, vel, rho, p, mass, phase, gradC, ap, as);
-        viscous_acc(P, &nb[i], i, vel, rho, mass, phase, av);
-        position_shift(P, &nb[i], i, B, rho, mass, dr);
+        double ap[3] = {0, 0, 0}, as[3] = {0, 0, 0}, av[3] = {0, 0, 0}, dr[3] = {0, 0, 0};
+        const int wall = phase[i] == ORC_WALL; /* a wall particle has no rates */
+        if (!wall) {
+            momentum_rates(P, &nb[i], i, vel, rho, p, mass, phase, gradC, ap, as);
+            viscous_acc(P, &nb[i], i, vel, rho, mass, phase, av);
+            position_shift(P, &nb[i], i, B, rho, mass, dr);
+        }
         for (int a = 0; a < 3; ++a) {
-            double g = a < d ? P->gravity[a] : 0.0;
+            double g = (a < d && !wall) ? P->gravity[a] : 0.0;
             if (out->gradC) out->gradC[3 * t + a] = gradC[3 * i + a];
             if (out->acc) out->acc[3 * t + a] = ap[a] + as[a] + av[a] + g;
             if (out->acc_p) out->acc_p[3 * t + a] = ap[a];
@@ -826,7 +868,7 @@ int orc_eval_rates(const orc_params* P, int64_t n, const double* pos, const doub
         }
         if (out->B)
             for (int q = 0; q < 9; ++q) out->B[9 * t + q] = q < d * d ? B[(size_t)d * d * i + q] : 0.0;
-        if (out->drho) out->drho[t] = continuity_rate(P, &nb[i], i, vel, rho, p, mass, phase);
+        if (out->drho) out->drho[t] = wall ? 0.0 : continuity_rate(P, &nb[i], i, vel, rho, p, mass, phase);
         if (out->sigma) out->sigma[t] = kernel_sum(P, &nb[i]);
         if (out->nnb) out->nnb[t] = nb[i].n;
     }
@@ -887,7 +929,7 @@ int orc_step(const orc_params* P, int64_t n, double* pos, double* vel, double* r
         if (!(P->flags & ORC_NO_DENSITY_SUMMATION)) {
 #pragma omp parallel for
             for (int64_t i = 0; i < n; ++i)
-                rho[i] = P->rho0[phase[i]] * kernel_sum(P, &nb[i]) / sigma0;
+                if (phase[i] != ORC_WALL) rho[i] = P->rho0[phase[i]] * kernel_sum(P, &nb[i]) / sigma0;
         }
         /* Eq. 16, Eq. 18 */
         double vmax[2];
@@ -899,16 +941,18 @@ int orc_step(const orc_params* P, int64_t n, double* pos, double* vel, double* r
         /* Eq. 13, held over the advection step */
 #pragma omp parallel for
         for (int64_t i = 0; i < n; ++i)
-            viscous_acc(P, &nb[i], i, vel, rho, mass, phase, av + 3 * i);
+            if (phase[i] != ORC_WALL) viscous_acc(P, &nb[i], i, vel, rho, mass, phase, av + 3 * i);
         /* Eq. 15 then Eq. 14 */
         if (!(P->flags & ORC_NO_SHIFT)) {
 #pragma omp parallel for
             for (int64_t i = 0; i < n; ++i)
                 correction_matrix(P, &nb[i], rho, mass, B + (size_t)d * d * i);
 #pragma omp parallel for
-            for (int64_t i = 0; i < n; ++i) position_shift(P, &nb[i], i, B, rho, mass, dr + 3 * i);
             for (int64_t i = 0; i < n; ++i)
-                for (int a = 0; a < d; ++a) pos[i * d + a] += dr[3 * i + a];
+                if (phase[i] != ORC_WALL) position_shift(P, &nb[i], i, B, rho, mass, dr + 3 * i);
+            for (int64_t i = 0; i < n; ++i)
+                if (phase[i] != ORC_WALL)
+                    for (int a = 0; a < d; ++a) pos[i * d + a] += dr[3 * i + a];
         }
         /* acoustic substeps */
         double tau = 0.0;
@@ -917,29 +961,37 @@ int orc_step(const orc_params* P, int64_t n, double* pos, double* vel, double* r
             double dt = fmin(orc_dt_acoustic(P, vmax), dt_ad - tau);
             clk->dt_ac = dt;
             for (int64_t i = 0; i < n; ++i) {
+                if (phase[i] == ORC_WALL) { /* walls stay where they are */
+                    p[i] = 0.0;
+                    continue;
+                }
                 rho[i] += 0.5 * dt * drho[i];
                 p[i] = eos(P, rho[i], phase[i]);
                 for (int a = 0; a < d; ++a) pos[i * d + a] += 0.5 * dt * vel[i * d + a];
             }
 #pragma omp parallel for
-            for (int64_t i = 0; i < n; ++i) colour_gradient(P, &nb[i], i, rho, mass, phase, gradC + 3 * i);
+            for (int64_t i = 0; i < n; ++i)
+                if (phase[i] != ORC_WALL) colour_gradient(P, &nb[i], i, rho, mass, phase, gradC + 3 * i);
 #pragma omp parallel for
             for (int64_t i = 0; i < n; ++i) {
                 double ap[3], as[3];
+                if (phase[i] == ORC_WALL) continue;
                 momentum_rates(P, &nb[i], i, vel, rho, p, mass, phase, gradC, ap, as);
                 for (int a = 0; a < d; ++a)
                     acc[3 * i + a] = ap[a] + as[a] + av[3 * i + a] + P->gravity[a];
             }
             for (int64_t i = 0; i < n; ++i)
-                for (int a = 0; a < d; ++a) {
-                    vel[i * d + a] += dt * acc[3 * i + a];
-                    pos[i * d + a] += 0.5 * dt * vel[i * d + a];
-                }
+                if (phase[i] != ORC_WALL)
+                    for (int a = 0; a < d; ++a) {
+                        vel[i * d + a] += dt * acc[3 * i + a];
+                        pos[i * d + a] += 0.5 * dt * vel[i * d + a];
+                    }
 #pragma omp parallel for
             for (int64_t i = 0; i < n; ++i)
-                drho[i] = continuity_rate(P, &nb[i], i, vel, rho, p, mass, phase);
+                drho[i] = phase[i] == ORC_WALL ? 0.0 : continuity_rate(P, &nb[i], i, vel, rho, p, mass, phase);
             int bad = 0;
             for (int64_t i = 0; i < n; ++i) {
+                if (phase[i] == ORC_WALL) continue;
                 rho[i] += 0.5 * dt * drho[i];
                 if (!(rho[i] > 0.0) || !isfinite(rho[i])) bad = 1;
                 for (int a = 0; a < d; ++a)
@@ -992,6 +1044,7 @@ void orc_observables(const orc_params* P, int64_t n, const double* pos, const do
     double h = param_h(P);
     memset(o, 0, sizeof(*o));
     for (int64_t i = 0; i < n; ++i) {
+        if (phase[i] == ORC_WALL) continue; /* observables are of the fluids */
         double v2 = 0.0;
         for (int a = 0; a < d; ++a) {
             o->momentum[a] += mass[i] * vel[i * d + a];

@@ -179,7 +179,7 @@ void validate_params(const rsph_params* p)
         if (!std::isfinite(p->box[a]) || !(p->box[a] > 0)) fail(RSPH_EINVAL, "box must be > 0");
         const double nc = std::floor(p->box[a] / (2.0 * h));
         if (nc < 3) fail(RSPH_EINVAL, "box must hold at least 3 cells of edge 2h per axis");
-        if (nc > kMaxCellsPerAxis) fail(RSPH_EINVAL, "at most 1024 cells per axis");
+        if (nc > kMaxCellsPerAxis) fail(RSPH_EINVAL, "at most 512 cells of edge 2h per axis");
     }
 }
 
@@ -942,7 +942,8 @@ void validate_particles(const rsph_params& p, int64_t n, const double* pos, cons
     for (int64_t i = 0; i < n * d; ++i)
         if (!std::isfinite(pos[i]) || !std::isfinite(vel[i])) fail(RSPH_EINVAL, "non-finite position or velocity");
     for (int64_t i = 0; i < n; ++i)
-        if (phase[i] != 0 && phase[i] != 1) fail(RSPH_EINVAL, "phase must be 0 or 1");
+        if (phase[i] != 0 && phase[i] != 1 && phase[i] != kWall)
+            fail(RSPH_EINVAL, "phase must be 0, 1 (the fluids) or 2 (a wall particle)");
     if (mass)
         for (int64_t i = 0; i < n; ++i)
             if (!std::isfinite(mass[i]) || !(mass[i] > 0)) fail(RSPH_EINVAL, "mass must be finite and > 0");
@@ -975,6 +976,7 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
     int32_t* ib = (int32_t*)(f + 9 * cn);
     s->v0max[0] = s->v0max[1] = 0.0;
     for (int64_t i = 0; i < n; ++i) {
+        if (phase[i] == kWall) continue;  // a wall's speed is not the fluids'
         double v2 = 0.0;
         for (int a = 0; a < d; ++a) v2 += vel[i * d + a] * vel[i * d + a];
         double& vm = s->v0max[phase[i] & 1];
@@ -996,8 +998,10 @@ void upload_particles(rsph_system* s, const double* pos, const double* vel, cons
                 f[a * cn + k] = q;
                 f[(3 + a) * cn + k] = a < d ? vel[i * d + a] : 0.0;
             }
-            f[6 * cn + k] = mass ? mass[i] : s->prm.rho0[phase[i]] / s->sc.sigma0;
-            f[7 * cn + k] = rho ? rho[i] : s->prm.rho0[phase[i]];
+            // a wall particle's reference density is 1: its volume is the lattice one
+            const double r0 = phase[i] == kWall ? 1.0 : s->prm.rho0[phase[i]];
+            f[6 * cn + k] = mass ? mass[i] : r0 / s->sc.sigma0;
+            f[7 * cn + k] = rho ? rho[i] : r0;
             f[8 * cn + k] = 0.0;
             ib[k] = (int32_t)i;
             ib[cn + k] = phase[i];
@@ -1411,7 +1415,8 @@ rsph_status rsph_read_particles(rsph_system* s, int32_t field, int64_t n, double
         case RSPH_FIELD_P: {
             std::vector<double> r = dl(P, A.rho + o, n);
             std::vector<int32_t> ph = dl(P, A.phase + o, n);
-            for (int64_t k = 0; k < n; ++k) tmp[k] = s->sc.c0sq * (r[k] - s->sc.rho0[ph[k]]);
+            for (int64_t k = 0; k < n; ++k)
+                tmp[k] = ph[k] == kWall ? 0.0 : s->sc.c0sq * (r[k] - s->sc.rho0[ph[k]]);
             break;
         }
         case RSPH_FIELD_PHASE: {

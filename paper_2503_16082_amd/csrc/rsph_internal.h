@@ -27,7 +27,7 @@ constexpr int kBlock = 256;
 constexpr int64_t kFuseDtEntries = 1024;
 constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lattice)
 constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
-constexpr int kMaxCellsPerAxis = 1024;
+constexpr int kMaxCellsPerAxis = 512;  // 9 bits per axis in the mixed-form geometry tag
 constexpr int kMaxLanes = 16;  // lanes per particle slot in the pair passes (at most)
 
 // method switches (mirror of the public RSPH_* flags)
@@ -46,6 +46,11 @@ constexpr uint32_t kHealthCoincident = 8u;
 constexpr uint32_t kHealthClose = 16u;  // two particles closer than 1e-3 dp (input check only)
 constexpr uint32_t kHealthDtCollapse = 32u;  // acoustic step below 1e-12 of its no-flow value
 constexpr int64_t kMaxCells = 2048LL * 2048LL;  // capacity of the three-phase scan
+
+// fluid id of a wall particle (0 and 1 are the fluids k and l): it never moves,
+// its velocity is the wall's, and a fluid particle sees it as the mirror of
+// itself (the one-sided Riemann wall condition)
+constexpr int kWall = 2;
 
 // per-particle flag bits, rebuilt every advection step
 constexpr uint8_t kFlagInterface = 1;  // has a neighbour of the other fluid

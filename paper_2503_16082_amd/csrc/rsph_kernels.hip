@@ -126,9 +126,10 @@ __device__ __forceinline__ double wendland_w(double q, double alpha)
 }
 
 // ---------------------------------------------------------------------------
-// frozen geometry records
-//   FP64: {x, y, z, phase}
-//   mixed: {x - cx*cell, y - cy*cell, z - cz*cell, bits(cx | cy<<10 | cz<<20 | phase<<31)}
+// frozen geometry records (phase 0, 1: the fluids; 2: a wall particle)
+//   FP64: {x, y, z, phase + 4 * interface}
+//   mixed: {x - cx*cell, y - cy*cell, z - cz*cell,
+//           bits(cx | cy<<9 | cz<<18 | interface<<27 | phase<<28)}
 // ---------------------------------------------------------------------------
 
 template <typename R>
@@ -136,15 +137,15 @@ struct Geo;
 
 template <>
 struct Geo<double> {
-    // w = phase + 2 * (particle has a neighbour of the other fluid)
+    // w = phase + 4 * (particle has a neighbour of the other fluid)
     __device__ static Q4<double> make(const double* x, int ph, bool iface, const SysConst& S, const int* c)
     {
         (void)S;
         (void)c;
-        return Q4<double>{x[0], x[1], x[2], (double)(ph + (iface ? 2 : 0))};
+        return Q4<double>{x[0], x[1], x[2], (double)(ph + (iface ? 4 : 0))};
     }
-    __device__ static int phase(const Q4<double>& g) { return (int)g.w & 1; }
-    __device__ static bool interface(const Q4<double>& g) { return ((int)g.w >> 1) != 0; }
+    __device__ static int phase(const Q4<double>& g) { return (int)g.w & 3; }
+    __device__ static bool interface(const Q4<double>& g) { return ((int)g.w >> 2) != 0; }
     template <int D>
     __device__ static void rij(const Q4<double>& gi, const Q4<double>& gj, const SysConst& S,
                                const double* cellr, double* r)
@@ -171,33 +172,33 @@ struct Geo<double> {
 
 template <>
 struct Geo<float> {
-    // tag: cell x, y, z in 10 bits each, bit 30 = particle has a neighbour of
-    // the other fluid, bit 31 = phase
+    // tag: cell x, y, z in 9 bits each, bit 27 = particle has a neighbour of
+    // the other fluid, bits 28-29 = phase
     __device__ static Q4<float> make(const double* x, int ph, bool iface, const SysConst& S, const int* c)
     {
         float o[3];
         for (int a = 0; a < 3; ++a) o[a] = (float)(x[a] - (double)c[a] * S.cell[a]);
-        uint32_t tag = (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20) |
-                       ((uint32_t)(iface ? 1 : 0) << 30) | ((uint32_t)ph << 31);
+        uint32_t tag = (uint32_t)c[0] | ((uint32_t)c[1] << 9) | ((uint32_t)c[2] << 18) |
+                       ((uint32_t)(iface ? 1 : 0) << 27) | ((uint32_t)ph << 28);
         return Q4<float>{o[0], o[1], o[2], __uint_as_float(tag)};
     }
-    __device__ static int phase(const Q4<float>& g) { return (int)(__float_as_uint(g.w) >> 31); }
-    __device__ static bool interface(const Q4<float>& g) { return ((__float_as_uint(g.w) >> 30) & 1u) != 0; }
+    __device__ static int phase(const Q4<float>& g) { return (int)((__float_as_uint(g.w) >> 28) & 3u); }
+    __device__ static bool interface(const Q4<float>& g) { return ((__float_as_uint(g.w) >> 27) & 1u) != 0; }
     template <int D>
     __device__ static void rij(const Q4<float>& gi, const Q4<float>& gj, const SysConst& S,
                                const float* cellr, float* r)
     {
         const uint32_t ti = __float_as_uint(gi.w), tj = __float_as_uint(gj.w);
-        int dc = (int)(ti & 1023u) - (int)(tj & 1023u);
+        int dc = (int)(ti & 511u) - (int)(tj & 511u);
         if (dc > 1) dc -= S.ncell[0];
         else if (dc < -1) dc += S.ncell[0];
         r[0] = (gi.x - gj.x) + (float)dc * cellr[0];
-        dc = (int)((ti >> 10) & 1023u) - (int)((tj >> 10) & 1023u);
+        dc = (int)((ti >> 9) & 511u) - (int)((tj >> 9) & 511u);
         if (dc > 1) dc -= S.ncell[1];
         else if (dc < -1) dc += S.ncell[1];
         r[1] = (gi.y - gj.y) + (float)dc * cellr[1];
         if (D == 3) {
-            dc = (int)((ti >> 20) & 1023u) - (int)((tj >> 20) & 1023u);
+            dc = (int)((ti >> 18) & 511u) - (int)((tj >> 18) & 511u);
             if (dc > 1) dc -= S.ncell[2];
             else if (dc < -1) dc += S.ncell[2];
             r[2] = (gi.z - gj.z) + (float)dc * cellr[2];
@@ -715,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
         if (i == S.p_off) A.sd[c.s].binned = 1;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
         if (ph == 0) m0 = bits;
-        else m1 = bits;
+        else if (ph == 1) m1 = bits;  // a wall's speed is not the fluids'
     }
     m0 = wave_max_u64(m0);
     m1 = wave_max_u64(m1);
@@ -890,7 +891,7 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
             const int cz = wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]);
             c4.z = (float)(xj[2] - (double)cz * S.cell[2]);
         }
-        c4.w = __int_as_float((lx << 1) | (A.phase[j] & 1));
+        c4.w = __int_as_float((lx << 2) | (A.phase[j] & 3));
         L.q[k] = c4;
     }
     __syncthreads();
@@ -1006,7 +1007,7 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
             return Pos3{{q.x, q.y, q.z}, (int)q.w};
         },
         [&](uint32_t j, const Pos3& rj) {
-            cross |= rj.ph != ph;
+            cross |= rj.ph != ph && rj.ph != kWall;  // walls carry no colour
             double r2 = 0.0;
             for (int a = 0; a < D; ++a) {
                 double d = xi[a] - rj.x[a];
@@ -1029,18 +1030,21 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
     if (close) flag_health(Dy, kHealthClose);
     int ci[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) ci[a] = cell_of(xi[a], S, a);
-    A.flags[i] = cross ? kFlagInterface : 0;
-    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, cross != 0, S, ci);
+    const bool wall = ph == kWall;
+    const bool iface = cross && !wall;
+    A.flags[i] = iface ? kFlagInterface : 0;
+    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, iface, S, ci);
     const double sigma = S.w0 + wsum;
     double rho = A.rho[i];
     const double mass = A.mass[i];
-    if (A.mode == 0 && !(S.flags & kNoDensitySummation)) {
+    // a wall particle keeps its density; it has no pressure of its own
+    if (A.mode == 0 && !(S.flags & kNoDensitySummation) && !wall) {
         rho = S.rho0[ph] * sigma / S.sigma0;
         A.rho[i] = rho;
     }
     if (A.mode == 1) A.r_sigma[i] = sigma;
     V = mass / rho;
-    const double p = S.c0sq * (rho - S.rho0[ph]);
+    const double p = wall ? 0.0 : S.c0sq * (rho - S.rho0[ph]);
     ((Q4<R>*)A.th[1])[i] = Q4<R>{(R)rho, (R)V, (R)p, (R)0};
     return true;
 }
@@ -1127,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                         const bool valid = k < ke;
                         const float4 q = L.q[valid ? k : kb];
                         const int w = __float_as_int(q.w);
-                        const int dx = (w >> 1) - lx;
+                        const int dx = (w >> 2) - lx;
                         const float ax = (oi[0] - q.x) - (float)dx * cellf[0];
                         const float ay = ry0 - q.y;
                         const float az = D == 3 ? rz0 - q.z : 0.f;
@@ -1231,6 +1235,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
         phi = Geo<R>::phase(gi);
         cnt = cnt_i;
     }
+    const bool wall_i = phi == kWall;  // a wall particle: its B only
     const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
     nl.run(
@@ -1244,10 +1249,14 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
             const Q4<R> vj = rj.q[1];
             const R Vj = vj.w;  // volume, stored beside the velocity
-            const R eta_j = Geo<R>::phase(gj) == phi ? eta_i : eta_o;
+            // a wall neighbour: the fluid's own viscosity against the wall's
+            // velocity, with the mirror's volume V_i
+            const int phj = Geo<R>::phase(gj);
+            const bool wall_j = phj == kWall;
+            const R eta_j = (phj == phi || wall_j) ? eta_i : eta_o;
             const R es = eta_i + eta_j;
             const R eta_bar = es > R(0) ? R(2) * eta_i * eta_j / es : R(0);
-            const R f = eta_bar * dW * inv_r * Vj;
+            const R f = wall_i ? R(0) : eta_bar * dW * inv_r * (wall_j ? vi.w : Vj);
             av[0] += f * (vi.x - vj.x);
             av[1] += f * (vi.y - vj.y);
             if (D == 3) av[2] += f * (vi.z - vj.z);
@@ -1395,11 +1404,14 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
         });
     for (int a = 0; a < D; ++a) s[a] = group_sum<G>(s[a]);
     if (!c.lane || g != 0) return;
+    const int ph = A.phase[i];
+    const bool wall = ph == kWall;
     double dr[3];
-    for (int a = 0; a < 3; ++a) dr[a] = a < D ? -S.alpha_h2 * (double)s[a] : 0.0;
+    for (int a = 0; a < 3; ++a) dr[a] = (a < D && !wall) ? -S.alpha_h2 * (double)s[a] : 0.0;
     Q4<R>* th0 = (Q4<R>*)A.th[0];
-    if (A.mode == 1) {
-        for (int a = 0; a < 3; ++a) A.r_dr[3 * i + a] = dr[a];
+    if (A.mode == 1 || wall) {  // a wall particle never moves and keeps its density
+        if (A.mode == 1)
+            for (int a = 0; a < 3; ++a) A.r_dr[3 * i + a] = dr[a];
         th0[i] = th[i];
         return;
     }
@@ -1407,7 +1419,6 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
         for (int a = 0; a < D; ++a) A.pos[a][i] += dr[a];
     // first half of substep 0
     const double dt = Dy.dt[0];
-    const int ph = A.phase[i];
     const double rho = A.rho[i] + 0.5 * dt * A.drho[i];
     for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt * A.vel[a][i];
     A.rho[i] = rho;
@@ -1686,7 +1697,8 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
         g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], th[j]}}; },
         [&](uint32_t j, const Recs<R, 2>& rj) {
             const Q4<R> gj = rj.q[0];
-            if (Geo<R>::phase(gj) == phi) return;
+            const int phj = Geo<R>::phase(gj);
+            if (phj == phi || phj == kWall) return;  // walls carry no colour
             R r[3];
             Geo<R>::template rij<D>(gi, gj, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -1751,9 +1763,10 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
         vi = vin[i];
     }
     const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
-    const int cnt = c.lane ? cnt_i : 0;
     const int phi = Geo<R>::phase(gi);
-    const bool surface = c.lane && (fl & kFlagNearInterface) && !(S.flags & kNoSurface);
+    const bool wall_i = phi == kWall;  // a wall particle has no rates and never moves
+    const int cnt = (c.lane && !wall_i) ? cnt_i : 0;
+    const bool surface = c.lane && !wall_i && (fl & kFlagNearInterface) && !(S.flags & kNoSurface);
     const Q4<R> ci = surface ? ci_i : Q4<R>{0, 0, 0, 0};
     const bool penalty = !(S.flags & kNoPenalty);
     // cross pairs: the neighbour's gradient enters negated (one colour field,
@@ -1762,7 +1775,8 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     const bool r3 = (S.flags & kPenaltyR3) != 0;
     const R gamma = (R)S.gamma;
     const R xg = (R)(S.xi * S.gamma);
-    const R rho0_i = (R)S.rho0[phi], rho0_o = (R)S.rho0[phi ^ 1];
+    const R rho0_i = (R)S.rho0[phi & 1], rho0_o = (R)S.rho0[(phi & 1) ^ 1];
+    const R grav[3] = {(R)S.grav[0], (R)S.grav[1], (R)S.grav[2]};
     const R phi_i_x = rho0_i / (rho0_i + rho0_o);  // phi_i for a cross pair
     const R phi_j_x = rho0_o / (rho0_i + rho0_o);
     const R pen_x = R(-4) * phi_i_x * phi_j_x * xg;
@@ -1781,18 +1795,27 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
             const Q4<R> tj = rj.q[1];
             const Q4<R> vj = rj.q[2];
-            const R Vj = tj.y;
             // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
             const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
-            const R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
+            R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
+            R rhoR = tj.x, pR = tj.z, Vj = tj.y;
+            const bool wall_j = Geo<R>::phase(gj) == kWall;
+            if (wall_j) {
+                // the wall's mirrored state: rho_R = rho_i, U_R = 2 U_w - U_L,
+                // p_R = p_i - rho_i g . r_ij, volume V_i
+                rhoR = ti.x;
+                pR = ti.z - ti.x * (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]);
+                UR = R(2) * UR - UL;
+                Vj = ti.y;
+            }
             const R dU = UL - UR;
             const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
-            const R Pstar = (ti.x * tj.z + tj.x * ti.z + beta * c0 * ti.x * tj.x * dU) / (ti.x + tj.x);
+            const R Pstar = (ti.x * pR + rhoR * ti.z + beta * c0 * ti.x * rhoR * dU) / (ti.x + rhoR);
             const R fp = Pstar * dW * Vj;
             sp[0] += fp * e[0];
             sp[1] += fp * e[1];
             if (D == 3) sp[2] += fp * e[2];
-            if (!surface) return;
+            if (!surface || wall_j) return;  // walls carry no colour
             const bool same = Geo<R>::phase(gj) == phi;
             const Q4<R> cj = col[j];
             const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
@@ -1854,7 +1877,13 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
         ss[a] = group_sum<G>(ss[a]);
     }
     unsigned long long m0 = 0, m1 = 0;
-    if (c.lane && g == 0) {
+    if (c.lane && g == 0 && wall_i) {
+        // a wall keeps its velocity: the record of the kicked velocities
+        // carries it on; it has no rates
+        ((Q4<R>*)A.vbuf[slot ^ 1])[i] = vi;
+        if (A.mode == 1)
+            for (int a = 0; a < 3; ++a) A.r_acc[3 * i + a] = A.r_accp[3 * i + a] = A.r_accs[3 * i + a] = 0.0;
+    } else if (c.lane && g == 0) {
         const R inv_rho = R(1) / ti.x;
         const R avv[3] = {av_i.x, av_i.y, av_i.z};
         double acc[3];
@@ -1885,7 +1914,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             vout[i] = Q4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
             unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
             if (phi == 0) m0 = bits;
-            else m1 = bits;
+            else m1 = bits;  // (a wall never gets here)
         }
     }
     if (A.mode == 1) return;  // block-uniform
@@ -1982,7 +2011,9 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         vi = vk[i];
     }
     const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
-    const int cnt = c.lane ? cnt_i : 0;
+    const bool wall_i = Geo<R>::phase(gi) == kWall;  // a wall keeps its density
+    const int cnt = (c.lane && !wall_i) ? cnt_i : 0;
+    const R grav[3] = {(R)S.grav[0], (R)S.grav[1], (R)S.grav[2]};
     R s = 0;
     nl.run(
         g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vk[j]}}; },
@@ -1997,9 +2028,13 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
             const Q4<R> vj = rj.q[2];
             const R vie = (vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
             const R vje = (vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
-            // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e
-            const R Ustar = (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
-            s += (vie + Ustar) * dW * tj.y;
+            // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e;
+            // against a wall's mirror (rho_R = rho_i, U_R = 2 U_w - U_L,
+            // p_R = p_i - rho_i g . r_ij, volume V_i): U* = U_w + g . r_ij / (2 c0)
+            const bool wall_j = Geo<R>::phase(gj) == kWall;
+            const R Ustar = wall_j ? -vje + (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]) * R(0.5) * inv_c0
+                                   : (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
+            s += (vie + Ustar) * dW * (wall_j ? ti.y : tj.y);
         });
     s = group_sum<G>(s);
     // the acoustic steps of this substep and, if another one follows in the
@@ -2028,9 +2063,13 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         dt2 = Dy.dt[(kk + 1) & 1];
     }
     if (!c.lane || g != 0) return;
-    const double drho = 2.0 * (double)ti.x * (double)s;
+    const double drho = wall_i ? 0.0 : 2.0 * (double)ti.x * (double)s;
     if (A.mode == 1) {
         A.r_drho[i] = drho;
+        return;
+    }
+    if (wall_i) {
+        if (next) ((Q4<R>*)A.th[slot ^ 1])[i] = ti;
         return;
     }
     double rho = rho_i + 0.5 * dt * drho;
@@ -2077,7 +2116,8 @@ __global__ __launch_bounds__(kWave) void k_obs_partial(DevArrays A, int pass)
     s = __builtin_amdgcn_readfirstlane(s);
     if (s < 0) return;
     const SysConst& S = A.sc[s];
-    const bool lane = i < S.p_off + S.p_n;
+    // observables are of the fluids: wall particles are left out
+    const bool lane = i < S.p_off + S.p_n && A.phase[i] != kWall;
     double f[kObsPart];
     for (int k = 0; k < kObsPart; ++k) f[k] = 0.0;
     if (lane) {
@@ -2342,7 +2382,7 @@ __global__ __launch_bounds__(kBlock) void k_load_particles(DevArrays A, int64_t 
     const int64_t o = p_off + i;
     bool wrong = false;
     int ph = phase[i];
-    if (ph != 0 && ph != 1) {
+    if (ph != 0 && ph != 1 && ph != kWall) {
         wrong = true;
         ph = ph < 0 ? 0 : 1;
     }
@@ -2358,7 +2398,7 @@ __global__ __launch_bounds__(kBlock) void k_load_particles(DevArrays A, int64_t 
         A.pos[a][o] = q;
         A.vel[a][o] = v;
     }
-    const double r0 = ph ? rho0.y : rho0.x;
+    const double r0 = ph == kWall ? 1.0 : (ph ? rho0.y : rho0.x);
     const double m = mass ? mass[i] : r0 / sigma0;
     const double r = rho ? rho[i] : r0;
     wrong |= !isfinite(m) || !(m > 0.0) || !isfinite(r) || !(r > 0.0);

@@ -7,7 +7,8 @@ point, and zero or prescribed velocity.  It holds none of the method's
 arithmetic: it draws random numbers and lays out lattices, nothing more, so it
 can feed both the HIP library and the CPU oracle with identical arrays.
 
-Phase 0 is fluid k (the droplet or pool), phase 1 is fluid l.  The sound speed
+Phase 0 is fluid k (the droplet or pool), phase 1 is fluid l, phase 2 a wall
+particle (fixed; its velocity is the wall's).  The sound speed
 follows the paper's rule c0 = 10 U (section 2), with U the larger of the initial
 speed and the capillary velocity sqrt((d-1) gamma / (rho_k R)).
 """
@@ -214,3 +215,74 @@ def acoustic_wave_2d(n_side=24, amp_v=1e-3, seed=0):
     p = base_params(2, (1.0, 1.0), dp, (1.0, 1.0), (0.0, 0.0), 0.0, 0.1)
     return {"name": "acoustic_wave_2d", "params": p, "pos": pos, "vel": vel, "phase": phase,
             "R": 0.0}
+
+
+WALL = 2
+WALL_LAYERS = 3  # 3 dp of wall behind a wall face covers the 2.6 dp kernel support
+
+
+def with_walls(pos, vel, phase, box, dp, axis, v_lo=None, v_hi=None, layers=WALL_LAYERS):
+    """Closes a periodic box along `axis` with two walls: every particle moves
+    up by layers * dp, and lattice layers of wall particles fill [0, layers dp)
+    and [L + layers dp, L + 2 layers dp), where L is the box's old length along
+    the axis; the box grows to L + 2 layers dp.  The two walls' outer layers
+    meet across the periodic boundary, so no fluid particle sees through a
+    wall.  v_lo, v_hi: the walls' velocities (default at rest).  Returns
+    (pos, vel, phase, box)."""
+    dim = pos.shape[1]
+    box = [float(b) for b in box]
+    L = box[axis]
+    counts = [int(round(b / dp)) for b in box]
+    counts[axis] = layers
+    slab = lattice(dim, counts, dp)
+    lo = slab.copy()
+    hi = slab.copy()
+    hi[:, axis] += L + layers * dp
+    pos = pos.copy()
+    pos[:, axis] += layers * dp
+    wv = np.zeros((2 * len(slab), dim))
+    if v_lo is not None:
+        wv[:len(slab)] = np.asarray(v_lo, dtype=np.float64)
+    if v_hi is not None:
+        wv[len(slab):] = np.asarray(v_hi, dtype=np.float64)
+    box[axis] = L + 2 * layers * dp
+    return (np.vstack([pos, lo, hi]), np.vstack([vel, wv]),
+            np.concatenate([phase, np.full(2 * len(slab), WALL, np.int32)]).astype(np.int32), box)
+
+
+def droplet_impact_wall_3d(n_per_unit=32, seed=0, U0=50.0, amp=0.05, box=(8.0, 8.0, 1.5), D=1.0):
+    """The high-velocity impact of section 5.4: a drop of diameter D (fluid k,
+    rho 1, eta 0.005, gamma 0.1, velocity (0, 0, -U0)) in air (rho 1e-3, eta
+    5e-5) in an 8 x 8 x 1.5 box whose floor the drop's bottom touches; walls at
+    the floor and the ceiling, periodic sides.  U0 = 50 gives Re = 1e4 and
+    We = 2.5e4 (Eq. 38).  At 32 particles per unit length: 3,145,728 fluid
+    particles and 393,216 wall particles."""
+    dp = 1.0 / n_per_unit
+    counts = tuple(int(round(b / dp)) for b in box)
+    pts0 = lattice(3, counts, dp)
+    centre = np.array([box[0] / 2, box[1] / 2, D / 2])
+    in_drop = np.linalg.norm(pts0 - centre, axis=1) < D / 2
+    phase = np.where(in_drop, 0, 1).astype(np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    vel = np.zeros_like(pos)
+    vel[in_drop, 2] = -U0
+    pos, vel, phase, box3 = with_walls(pos, vel, phase, box, dp, axis=2)
+    p = base_params(3, box3, dp, (1.0, 1e-3), (5e-3, 5e-5), 0.1, 10.0 * U0)
+    return {"name": "droplet_impact_wall_3d", "params": p, "pos": pos, "vel": vel, "phase": phase,
+            "R": D / 2, "centre": centre + np.array([0.0, 0.0, WALL_LAYERS * dp])}
+
+
+def channel_2d(n_side=20, seed=0, rho=(1.0, 1.0), eta=(0.05, 0.05), v_wall=0.0, gamma=0.0, c0=1.0, amp=0.05):
+    """Fluid k filling a 1 x 1 periodic square closed by walls along y (the
+    bottom at rest, the top moving with (v_wall, 0)): the setting of the wall
+    checks and of the Couette shear of section 5.2."""
+    dp = 1.0 / n_side
+    pts0 = lattice(2, (n_side, n_side), dp)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = jitter(rng, pts0, dp, amp)
+    vel = np.zeros_like(pos)
+    phase = np.zeros(len(pos), np.int32)
+    pos, vel, phase, box = with_walls(pos, vel, phase, (1.0, 1.0), dp, axis=1, v_hi=(v_wall, 0.0))
+    p = base_params(2, box, dp, rho, eta, gamma, c0)
+    return {"name": "channel_2d", "params": p, "pos": pos, "vel": vel, "phase": phase, "R": 0.0}
