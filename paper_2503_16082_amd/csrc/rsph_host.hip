@@ -136,6 +136,8 @@ struct rsph_system {
     int64_t c_off = 0, ncells = 0;
     int row = -1;
     bool has_particles = false;
+    // every particle of a fluid has the same mass (SysConst::mphase)
+    bool uniform_mass = true;
     bool faulted = false;
     bool rates_valid = false;
     // as of the host's last read of the system's device state
@@ -231,6 +233,9 @@ SysConst make_const(const rsph_params& p)
     S.cfl_ac = p.cfl_ac;
     S.coincident2 = (1e-9 * h) * (1e-9 * h);
     S.close2 = (1e-3 * p.dp) * (1e-3 * p.dp);
+    S.inv_c0sq = c0 > 0 ? 1.0 / (c0 * c0) : 0.0;
+    // the default masses (uniform per fluid); upload_particles checks given ones
+    for (int f = 0; f < 2; ++f) S.mphase[f] = p.rho0[f] / S.sigma0;
     return S;
 }
 
@@ -665,6 +670,9 @@ DevArrays kernel_view(rsph_pool* P)
 {
     DevArrays A = P->A;
     A.work = P->timing ? P->work_dev : nullptr;
+    A.packed = 1;
+    for (const rsph_system* s : P->systems)
+        if (s && !s->uniform_mass) A.packed = 0;
     return A;
 }
 
@@ -950,6 +958,28 @@ void validate_particles(const rsph_params& p, int64_t n, const double* pos, cons
     if (rho)
         for (int64_t i = 0; i < n; ++i)
             if (!std::isfinite(rho[i]) || !(rho[i] > 0)) fail(RSPH_EINVAL, "rho must be finite and > 0");
+}
+
+// The per-fluid masses of the particles given (NULL: the defaults): a fluid
+// whose particles all have one mass keeps it in the constants, which lets the
+// substep passes recover a neighbour's volume from its density alone; any
+// other mix of masses sends the pool through the passes that gather the volume.
+void set_fluid_masses(rsph_system* s, int64_t n, const int32_t* phase, const double* mass)
+{
+    s->uniform_mass = true;
+    if (!mass) return;
+    bool seen[2] = {false, false};
+    for (int64_t i = 0; i < n; ++i) {
+        if (phase[i] == kWall) continue;  // the substep passes never read a wall's mass
+        const int f = phase[i];
+        if (!seen[f]) {
+            seen[f] = true;
+            s->sc.mphase[f] = mass[i];
+        } else if (mass[i] != s->sc.mphase[f]) {
+            s->uniform_mass = false;
+            return;
+        }
+    }
 }
 
 // Uploads particles into the system's (already planned) slot range.
@@ -1253,6 +1283,7 @@ rsph_status rsph_set_particles(rsph_system* s, int64_t n, const double* pos, con
         s->sc.c_off = placed.c_off;
         s->sc.fuse_dt = placed.fuse_dt;
         s->sc.p_n = n;
+        set_fluid_masses(s, n, phase, mass);
         HIPCHECK(hipMemcpy((void*)(P->A.sc + s->row), &s->sc, sizeof(SysConst), hipMemcpyHostToDevice));
         upload_particles(s, pos, vel, phase, mass, rho);
         reset_dyn(s, keep);
@@ -1608,6 +1639,7 @@ rsph_status rsph_pool_admit(rsph_pool* P, const rsph_params* params, int64_t n, 
             repack(P, members);
             s->has_particles = true;
             s->sc.p_n = n;
+            set_fluid_masses(s, n, phase, mass);
             HIPCHECK(hipMemcpy((void*)(P->A.sc + s->row), &s->sc, sizeof(SysConst), hipMemcpyHostToDevice));
             upload_particles(s, pos, vel, phase, mass, nullptr);
             reset_dyn(s, false);
@@ -1788,6 +1820,9 @@ extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_
         s.sc = make_const(*params);
         s.ncells = s.sc.ncells;
         s.n = n;
+        // masses on the device are not inspected: given ones take the passes
+        // that gather each neighbour's volume
+        s.uniform_mass = mass == nullptr;
         Layout L = plan({}, &s);
         CountCarver count;
         DevArrays probe;
@@ -1820,7 +1855,7 @@ extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_
         int32_t bad_h = 0;
         HIPCHECK(hipMemcpyAsync(&bad_h, bad, sizeof bad_h, hipMemcpyDeviceToHost, P.stream));
         HIPCHECK(hipStreamSynchronize(P.stream));
-        if (bad_h) fail(RSPH_EINVAL, "a fluid outside {0,1}, a non-finite value, or a mass or density <= 0");
+        if (bad_h) fail(RSPH_EINVAL, "a phase outside {0,1,2}, a non-finite value, or a mass or density <= 0");
         reset_dyn(&s, false);
         check_spacing(&s);
         // one evaluation, as rsph_eval_rates

@@ -92,6 +92,8 @@ struct SysConst {
     double grav[3];
     double coincident2;   // (1e-9 h)^2
     double close2;        // (1e-3 dp)^2
+    double mphase[2];     // the mass of every particle of fluid k and of fluid l, when uniform
+    double inv_c0sq;      // 1 / c0^2
 };
 
 // Advection-step state of a system (device resident; each change is made by
@@ -141,6 +143,11 @@ struct DevArrays {
     int32_t mode;    // 0 = step, 1 = evaluate rates only (no state update)
     int32_t dt_pass; // 1: some system's substeps are ended by the separate substep pass
     int32_t one_sys_waves;  // pool of one system: its 64-slot blocks (0 otherwise)
+    // 1: every system's fluid masses are uniform per fluid, so the substep
+    // passes gather two records per neighbour, {frozen position} and
+    // {velocity, pressure}, and recover rho = rho0 + p / c0^2 and V = m / rho
+    int32_t packed;
+    int32_t pad_;
     // FP64 state, structure of arrays
     double* pos[3];
     double* vel[3];
@@ -169,7 +176,8 @@ struct DevArrays {
     int32_t* wave_sys;
     // pair-loop inputs (float4 or double4 records)
     void* geo;     // frozen positions + tag
-    void* vbuf[2]; // velocity, substep parity
+    void* vbuf[2]; // velocity records by substep parity; packed: [0] {v, p} as the substep
+                   // starts, [1] {kicked v, p} (force writes [1], continuity writes [0])
     void* th[2];   // {rho, V, p, 0}, substep parity
     void* col;     // {grad C, 1/|grad C|}
     void* av;      // viscous acceleration

@@ -215,12 +215,14 @@ __device__ __forceinline__ double rsqrt_r<double>(double x) { return rsqrt(x); }
 template <>
 __device__ __forceinline__ float rsqrt_r<float>(float x) { return rsqrtf(x); }
 
+// 1/x: in FP32 the hardware reciprocal (within 1 ulp; the arguments here are
+// densities and sums of them, never denormal), in FP64 the exact quotient
 template <typename R>
 __device__ __forceinline__ R recip(R x);
 template <>
 __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 template <>
-__device__ __forceinline__ float recip<float>(float x) { return __frcp_rn(x); }
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ int cell_of(double x, const SysConst& S, int a)
 {
@@ -302,6 +304,21 @@ struct PassChunk {
                               : P == Pass::Shift      ? RSPH_CHUNK_2D_SHIFT
                                                       : RSPH_CHUNK_2D_ADVECTION;
     static constexpr int N = D == 2 ? N2 : (P == Pass::Advection ? 2 : Chunk<R, D>::N);
+};
+// Waves per SIMD that a pass's register allocation must leave room for (1:
+// the compiler's own choice), for the FP32 records of the 3D substep passes.
+#ifndef RSPH_WAVES_FORCE_3D
+#define RSPH_WAVES_FORCE_3D 1
+#endif
+#ifndef RSPH_WAVES_CONTINUITY_3D
+#define RSPH_WAVES_CONTINUITY_3D 1
+#endif
+template <typename R, int D, Pass P>
+struct Waves {
+    static constexpr int N = (D == 3 && sizeof(R) == 4)
+                                 ? (P == Pass::Force ? RSPH_WAVES_FORCE_3D
+                                                     : (P == Pass::Continuity ? RSPH_WAVES_CONTINUITY_3D : 1))
+                                 : 1;
 };
 // at least 4 lanes: a 256-thread block then covers at most 64 slots, i.e. lies
 // inside one system, which the per-block partial maxima rely on
@@ -388,6 +405,33 @@ __device__ __forceinline__ T group_sum(T v)
     for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// The packed substep passes gather {v, p} per neighbour and recover the rest
+// of its state from the pressure: rho = rho0 + p / c0^2 (Eq. 3 solved for the
+// density) and V = m / rho with the fluid's one particle mass.  Both sides of
+// a pair recover a particle's values from the same record, so a pair's terms
+// stay antisymmetric.
+template <typename R>
+struct FromPressure {
+    R rho0[2], mass[2], inv_c0sq;
+    __device__ __forceinline__ explicit FromPressure(const SysConst& S)
+    {
+        for (int f = 0; f < 2; ++f) {
+            rho0[f] = (R)S.rho0[f];
+            mass[f] = (R)S.mphase[f];
+        }
+        inv_c0sq = (R)S.inv_c0sq;
+    }
+    // density and mass of a particle of fluid ph (a wall's are never used)
+    __device__ __forceinline__ R rho(int ph, R p) const { return ((ph & 1) ? rho0[1] : rho0[0]) + p * inv_c0sq; }
+    __device__ __forceinline__ R m(int ph) const { return (ph & 1) ? mass[1] : mass[0]; }
+    // {rho, V, p, 0}
+    __device__ __forceinline__ Q4<R> operator()(int ph, R p) const
+    {
+        const R r = rho(ph, p);
+        return Q4<R>{r, m(ph) / r, p, R(0)};
+    }
+};
 
 __device__ __forceinline__ bool substep_on(const SysDyn& D, int mode)
 {
@@ -1409,10 +1453,13 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
     double dr[3];
     for (int a = 0; a < 3; ++a) dr[a] = (a < D && !wall) ? -S.alpha_h2 * (double)s[a] : 0.0;
     Q4<R>* th0 = (Q4<R>*)A.th[0];
+    // the packed substep passes take the pressure beside the velocity
+    R* p_rec = reinterpret_cast<R*>((Q4<R>*)A.vbuf[0] + i) + 3;
     if (A.mode == 1 || wall) {  // a wall particle never moves and keeps its density
         if (A.mode == 1)
             for (int a = 0; a < 3; ++a) A.r_dr[3 * i + a] = dr[a];
-        th0[i] = th[i];
+        if (A.packed) *p_rec = th[i].z;
+        else th0[i] = th[i];
         return;
     }
     if (!(S.flags & kNoShift))
@@ -1422,7 +1469,9 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
     const double rho = A.rho[i] + 0.5 * dt * A.drho[i];
     for (int a = 0; a < D; ++a) A.pos[a][i] += 0.5 * dt * A.vel[a][i];
     A.rho[i] = rho;
-    th0[i] = Q4<R>{(R)rho, (R)(A.mass[i] / rho), (R)(S.c0sq * (rho - S.rho0[ph])), (R)0};
+    const R p = (R)(S.c0sq * (rho - S.rho0[ph]));
+    if (A.packed) *p_rec = p;
+    else th0[i] = Q4<R>{(R)rho, (R)(A.mass[i] / rho), p, (R)0};
 }
 
 // ---------------------------------------------------------------------------
@@ -1656,7 +1705,7 @@ __global__ void k_reset_ksub_max(DevArrays A)
 // substep pair pass 1: colour gradient (Eq. 22) of interface particles
 // ---------------------------------------------------------------------------
 
-template <typename R, int D>
+template <typename R, int D, bool PK = false>
 __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
@@ -1685,8 +1734,10 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     const bool on = c.lane && (fl & kFlagInterface);
     if (!__any(on)) return;  // wave without interface particles
     const SysConst& S = A.sc[c.s];
+    // the substep's volumes: packed, from the {v, p} records
     const int slot = A.mode ? 0 : (int)(Dy.ksub & 1);
-    const Q4<R>* th = (const Q4<R>*)A.th[slot];
+    const Q4<R>* th = (const Q4<R>*)(PK ? A.vbuf[0] : A.th[slot]);
+    const FromPressure<R> fp(S);
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const Q4<R> gi = on ? gi_i : Q4<R>{0, 0, 0, 0};
@@ -1703,7 +1754,8 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
             Geo<R>::template rij<D>(gi, gj, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
-            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * rj.q[1].y * inv_r;
+            const R Vj = PK ? fp.m(phj) * recip<R>(fp.rho(phj, rj.q[1].w)) : rj.q[1].y;
+            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * Vj * inv_r;
             gsum[0] += f * r[0];
             gsum[1] += f * r[1];
             if (D == 3) gsum[2] += f * r[2];
@@ -1725,8 +1777,9 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 // with the projected penalty (Eqs. 24, 27, 30, 33), kick
 // ---------------------------------------------------------------------------
 
-template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
+template <typename R, int D, bool PK = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Waves<R, D, Pass::Force>::N))) void k_force(
+    DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
@@ -1752,18 +1805,22 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     const SysConst& S = A.sc[c.s];
     const int64_t kk = A.mode ? 0 : Dy.ksub;
     const int slot = (int)(kk & 1);
+    // packed: the {v, p} records as the substep starts, and the kicked ones
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
-    const Q4<R>* vin = (const Q4<R>*)A.vbuf[slot];
+    const Q4<R>* vin = (const Q4<R>*)A.vbuf[PK ? 0 : slot];
+    Q4<R>* vout = (Q4<R>*)A.vbuf[PK ? 1 : slot ^ 1];
+    const FromPressure<R> fpr(S);
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const R c0 = (R)S.c0, inv_c0 = (R)S.inv_c0;
-    Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
-    if (c.lane) {
-        ti = th[i];
-        vi = vin[i];
-    }
     const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
     const int phi = Geo<R>::phase(gi);
+    Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
+    if (c.lane) {
+        vi = vin[i];
+        ti = PK ? fpr(phi, vi.w) : th[i];
+    }
+    const R m_i = PK ? fpr.m(phi) : R(0);  // packed: the fluid's particle mass
     const bool wall_i = phi == kWall;  // a wall particle has no rates and never moves
     const int cnt = (c.lane && !wall_i) ? cnt_i : 0;
     const bool surface = c.lane && !wall_i && (fl & kFlagNearInterface) && !(S.flags & kNoSurface);
@@ -1782,9 +1839,14 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     const R pen_x = R(-4) * phi_i_x * phi_j_x * xg;
     const R gni = (ci.x * ci.x + ci.y * ci.y + ci.z * ci.z) * ci.w;  // |grad C_i|
     R sp[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+    constexpr int NR = PK ? 2 : 3;
     nl.run(
-        g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vin[j]}}; },
-        [&](uint32_t j, const Recs<R, 3>& rj) {
+        g, cnt,
+        [&](uint32_t j) {
+            if constexpr (PK) return Recs<R, 2>{{geo[j], vin[j]}};
+            else return Recs<R, 3>{{geo[j], th[j], vin[j]}};
+        },
+        [&](uint32_t j, const Recs<R, NR>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
             Geo<R>::template rij<D>(gi, gj, S, cellr, r);
@@ -1793,25 +1855,45 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             const R rr = r2 * inv_r;
             const R dW = wendland_dw<R>(rr * inv_h, coef);
             const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
-            const Q4<R> tj = rj.q[1];
-            const Q4<R> vj = rj.q[2];
+            const Q4<R> vj = rj.q[NR - 1];
+            const int phj = Geo<R>::phase(gj);
             // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
             const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
             R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
-            R rhoR = tj.x, pR = tj.z, Vj = tj.y;
-            const bool wall_j = Geo<R>::phase(gj) == kWall;
+            // packed: rho_j from the pressure, V_j = m_j / rho_j folded into the
+            // one reciprocal below
+            R rhoR, pR, mR = m_i, Vj = 0;
+            if constexpr (PK) {
+                rhoR = fpr.rho(phj, vj.w);
+                pR = vj.w;
+                mR = fpr.m(phj);
+            } else {
+                rhoR = rj.q[1].x;
+                pR = rj.q[1].z;
+                Vj = rj.q[1].y;
+            }
+            const bool wall_j = phj == kWall;
             if (wall_j) {
                 // the wall's mirrored state: rho_R = rho_i, U_R = 2 U_w - U_L,
                 // p_R = p_i - rho_i g . r_ij, volume V_i
                 rhoR = ti.x;
                 pR = ti.z - ti.x * (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]);
                 UR = R(2) * UR - UL;
+                mR = m_i;
                 Vj = ti.y;
             }
             const R dU = UL - UR;
             const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
-            const R Pstar = (ti.x * pR + rhoR * ti.z + beta * c0 * ti.x * rhoR * dU) / (ti.x + rhoR);
-            const R fp = Pstar * dW * Vj;
+            const R num = ti.x * pR + rhoR * ti.z + beta * c0 * ti.x * rhoR * dU;
+            // P* V_j = num V_j / (rho_i + rho_R)
+            R fp;
+            if constexpr (PK) {
+                const R q = recip<R>((ti.x + rhoR) * rhoR);  // V_j / (m_j (rho_i + rho_R))
+                Vj = mR * (ti.x + rhoR) * q;
+                fp = num * mR * q * dW;
+            } else {
+                fp = num * recip<R>(ti.x + rhoR) * dW * Vj;
+            }
             sp[0] += fp * e[0];
             sp[1] += fp * e[1];
             if (D == 3) sp[2] += fp * e[2];
@@ -1880,7 +1962,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     if (c.lane && g == 0 && wall_i) {
         // a wall keeps its velocity: the record of the kicked velocities
         // carries it on; it has no rates
-        ((Q4<R>*)A.vbuf[slot ^ 1])[i] = vi;
+        vout[i] = vi;
         if (A.mode == 1)
             for (int a = 0; a < 3; ++a) A.r_acc[3 * i + a] = A.r_accp[3 * i + a] = A.r_accs[3 * i + a] = 0.0;
     } else if (c.lane && g == 0) {
@@ -1891,7 +1973,6 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             acc[a] = a < D ? (double)(R(-2) * inv_rho * sp[a]) + (double)(inv_rho * ss[a]) +
                                  (double)avv[a] + S.grav[a]
                            : 0.0;
-        Q4<R>* vout = (Q4<R>*)A.vbuf[slot ^ 1];
         if (A.mode == 1) {
             for (int a = 0; a < 3; ++a) {
                 A.r_acc[3 * i + a] = acc[a];
@@ -1911,7 +1992,8 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
                 bad |= !isfinite(v[a]);
             }
             if (bad) flag_health(Dy, kHealthNonFinite);
-            vout[i] = Q4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
+            // packed: the pressure rides on to the continuity pass
+            vout[i] = Q4<R>{(R)v[0], (R)v[1], (R)v[2], PK ? vi.w : (R)0};
             unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(v2));
             if (phi == 0) m0 = bits;
             else m1 = bits;  // (a wall never gets here)
@@ -1944,8 +2026,9 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 // second half-step, and the first half-step of the next substep
 // ---------------------------------------------------------------------------
 
-template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t group)
+template <typename R, int D, bool PK = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Waves<R, D, Pass::Continuity>::N))) void
+k_continuity(DevArrays A, int64_t group)
 {
     constexpr int G = Lanes<D>::G;
     int g;
@@ -2000,41 +2083,61 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         kk = Dy.ksub - 1;
     }
     const int slot = (int)(kk & 1);
+    // packed: the kicked {v, p} records
     const Q4<R>* th = (const Q4<R>*)A.th[slot];
-    const Q4<R>* vk = (const Q4<R>*)A.vbuf[slot ^ 1];
+    const Q4<R>* vk = (const Q4<R>*)A.vbuf[PK ? 1 : slot ^ 1];
+    const FromPressure<R> fpr(S);
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const R inv_c0 = (R)S.inv_c0;
+    const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
     Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
     if (c.lane) {
-        ti = th[i];
         vi = vk[i];
+        ti = PK ? fpr(Geo<R>::phase(gi), vi.w) : th[i];
     }
-    const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
     const bool wall_i = Geo<R>::phase(gi) == kWall;  // a wall keeps its density
     const int cnt = (c.lane && !wall_i) ? cnt_i : 0;
     const R grav[3] = {(R)S.grav[0], (R)S.grav[1], (R)S.grav[2]};
     R s = 0;
+    constexpr int NR = PK ? 2 : 3;
     nl.run(
-        g, cnt, [&](uint32_t j) { return Recs<R, 3>{{geo[j], th[j], vk[j]}}; },
-        [&](uint32_t j, const Recs<R, 3>& rj) {
+        g, cnt,
+        [&](uint32_t j) {
+            if constexpr (PK) return Recs<R, 2>{{geo[j], vk[j]}};
+            else return Recs<R, 3>{{geo[j], th[j], vk[j]}};
+        },
+        [&](uint32_t j, const Recs<R, NR>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
             Geo<R>::template rij<D>(gi, gj, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
-            const Q4<R> tj = rj.q[1];
-            const Q4<R> vj = rj.q[2];
+            const Q4<R> vj = rj.q[NR - 1];
+            const int phj = Geo<R>::phase(gj);
             const R vie = (vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
             const R vje = (vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
-            // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e;
+            // U* = (rho_i U_L + rho_j U_R + (p_i - p_j)/c0) / (rho_i + rho_j), U = -v.e,
+            // so v_i.e + U* = (rho_j (v_i - v_j).e + (p_i - p_j)/c0) / (rho_i + rho_j);
             // against a wall's mirror (rho_R = rho_i, U_R = 2 U_w - U_L,
             // p_R = p_i - rho_i g . r_ij, volume V_i): U* = U_w + g . r_ij / (2 c0)
-            const bool wall_j = Geo<R>::phase(gj) == kWall;
-            const R Ustar = wall_j ? -vje + (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]) * R(0.5) * inv_c0
-                                   : (-ti.x * vie - tj.x * vje + (ti.z - tj.z) * inv_c0) / (ti.x + tj.x);
-            s += (vie + Ustar) * dW * (wall_j ? ti.y : tj.y);
+            if (phj == kWall) {
+                const R Ustar = -vje + (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]) * R(0.5) * inv_c0;
+                s += (vie + Ustar) * dW * ti.y;
+                return;
+            }
+            R rhoj, pj, q;
+            if constexpr (PK) {  // V_j / (rho_i + rho_j) = m_j / ((rho_i + rho_j) rho_j)
+                rhoj = fpr.rho(phj, vj.w);
+                pj = vj.w;
+                q = fpr.m(phj) * recip<R>((ti.x + rhoj) * rhoj);
+            } else {
+                rhoj = rj.q[1].x;
+                pj = rj.q[1].z;
+                q = rj.q[1].y * recip<R>(ti.x + rhoj);
+            }
+            s += (rhoj * (vie - vje) + (ti.z - pj) * inv_c0) * q * dW;
         });
     s = group_sum<G>(s);
     // the acoustic steps of this substep and, if another one follows in the
@@ -2069,7 +2172,10 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         return;
     }
     if (wall_i) {
-        if (next) ((Q4<R>*)A.th[slot ^ 1])[i] = ti;
+        if (next) {
+            if (PK) ((Q4<R>*)A.vbuf[0])[i] = vi;
+            else ((Q4<R>*)A.th[slot ^ 1])[i] = ti;
+        }
         return;
     }
     double rho = rho_i + 0.5 * dt * drho;
@@ -2078,8 +2184,9 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         rho += 0.5 * dt2 * drho;
         for (int a = 0; a < D; ++a) pos_i[a] += 0.5 * dt2 * vel_i[a];
         const int ph = Geo<R>::phase(gi);
-        ((Q4<R>*)A.th[slot ^ 1])[i] =
-            Q4<R>{(R)rho, (R)(mass_i / rho), (R)(S.c0sq * (rho - S.rho0[ph])), (R)0};
+        const R p = (R)(S.c0sq * (rho - S.rho0[ph]));
+        if (PK) ((Q4<R>*)A.vbuf[0])[i] = Q4<R>{vi.x, vi.y, vi.z, p};
+        else ((Q4<R>*)A.th[slot ^ 1])[i] = Q4<R>{(R)rho, (R)(mass_i / rho), p, (R)0};
     }
     for (int a = 0; a < D; ++a) A.pos[a][i] = pos_i[a];
     A.rho[i] = rho;
@@ -2325,6 +2432,24 @@ void launch_bin(const Launch& L, const DevArrays& A, int64_t group)
 constexpr int G2 = Lanes<2>::G;
 constexpr int G3 = Lanes<3>::G;
 
+// the substep passes: the packed form when every fluid's masses are uniform
+#define RSPH_DISPATCH_PK(KERNEL, EV, ...)                                                          \
+    do {                                                                                           \
+        if (!A.packed) {                                                                           \
+            RSPH_DISPATCH(KERNEL, G2, G3, EV, __VA_ARGS__);                                        \
+        } else if (L.fp64) {                                                                       \
+            if (L.dim == 2)                                                                        \
+                go(KERNEL<double, 2, true>, slot_grid(A.P, G2), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+            else                                                                                   \
+                go(KERNEL<double, 3, true>, slot_grid(A.P, G3), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+        } else {                                                                                   \
+            if (L.dim == 2)                                                                        \
+                go(KERNEL<float, 2, true>, slot_grid(A.P, G2), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+            else                                                                                   \
+                go(KERNEL<float, 3, true>, slot_grid(A.P, G3), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+        }                                                                                          \
+    } while (0)
+
 void launch_neighbours(const Launch& L, const DevArrays& A, Ev ev)
 {
     RSPH_DISPATCH(k_neighbours, G2, G3, ev, A);
@@ -2345,9 +2470,9 @@ void launch_advection(const Launch& L, const DevArrays& A, Ev ev)
 
 void launch_shift(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_shift, G2, G3, ev, A); }
 
-void launch_colour(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_colour, G2, G3, ev, A); }
+void launch_colour(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH_PK(k_colour, ev, A); }
 
-void launch_force(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_force, G2, G3, ev, A); }
+void launch_force(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH_PK(k_force, ev, A); }
 
 void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group)
 {
@@ -2357,7 +2482,7 @@ void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group)
 
 void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group)
 {
-    RSPH_DISPATCH(k_continuity, G2, G3, ev, A, group);
+    RSPH_DISPATCH_PK(k_continuity, ev, A, group);
 }
 
 // ---------------------------------------------------------------------------

@@ -344,6 +344,66 @@ def test_fp64_trajectory_matches_oracle_3d_large():
     s.close()
 
 
+# ---------------------------------------------------------------------------
+# particle masses that differ within a fluid: the substep passes then gather
+# each neighbour's volume (with one mass per fluid they recover it from the
+# pressure the velocity record carries)
+# ---------------------------------------------------------------------------
+
+def varied_masses(p, phase, seed, spread=0.05):
+    rng = np.random.default_rng(seed)
+    d = p["dim"]
+    base = np.asarray(list(p["rho0"]) + [1.0])[phase] / O.sigma0(d, p["dp"] * p.get("h_over_dp", 1.3), p["dp"])
+    return base * (1.0 + spread * rng.uniform(-1.0, 1.0, size=len(phase)))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eval_rates_parity_particle_masses(dim, precision):
+    if dim == 2:
+        w = WL.static_droplet_2d(n_side=40, R=0.2, seed=7)
+    else:
+        w = WL.static_droplet_3d(n_side=16, R=0.3, seed=7)
+    p, pos, vel, rho, _, phase = perturbed_state(w, seed=8)
+    mass = varied_masses(p, phase, seed=9)
+    say(f"eval particle masses dim={dim} precision={precision}")
+    g = gpu_rates(p, pos, vel, rho, mass, phase, precision)
+    ref = O.eval_rates(p, pos, vel, rho, mass, phase)
+    compare_rates(g, ref, precision, f"masses/d{dim}/p{precision}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_trajectory_particle_masses(precision):
+    """3 advection steps of the 2D static droplet with particle masses spread
+    by 5% within each fluid, against the oracle: the stepping path that
+    gathers each neighbour's volume."""
+    w = WL.static_droplet_2d(n_side=40, R=0.2, seed=3)
+    p = w["params"]
+    mass = varied_masses(p, w["phase"], seed=4)
+    say(f"trajectory particle masses precision={precision}")
+    st = O.State(p, w["pos"], w["vel"], w["phase"], mass=mass)
+    st.step(3)
+    s = rsph.System(p, precision=precision)
+    s.set_particles(w["pos"], w["vel"], w["phase"], mass=mass)
+    s.step(3)
+    o = s.observables()
+    ref = st.observables()
+    assert o["n_outer"] == 3 and o["health"] == 0
+    # the mixed form's FP32 |v| maxima may shift a substep count by one
+    assert abs(o["n_sub"] - ref["n_sub"]) <= (0 if precision == 0 else 3)
+    ev = normwise(s.read("vel"), st.vel)
+    er = normwise(s.read("rho") - np.asarray(p["rho0"])[w["phase"]],
+                  st.rho - np.asarray(p["rho0"])[w["phase"]])
+    dpos = s.read("pos") - O.wrap(p, st.pos)
+    dpos -= np.round(dpos)
+    say(f"particle masses p{precision}: vel {ev:.2e} rho {er:.2e} pos {np.abs(dpos).max():.2e}")
+    if precision == 0:
+        assert ev < 1e-9 and er < 1e-9 and np.abs(dpos).max() < 1e-12
+    else:
+        assert ev < 1e-4 and er < 1e-4 and np.abs(dpos).max() < 1e-4 * p["dp"]
+    s.close()
+
+
 def test_bitwise_determinism_and_resume():
     w = WL.static_droplet_2d(n_side=40, R=0.2, seed=6)
     p = w["params"]

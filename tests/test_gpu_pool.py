@@ -154,7 +154,7 @@ def test_invalid_particles_rejected():
         s.set_particles(pos, w["vel"], w["phase"])
     assert e.value.name == "EINVAL"
     bad_phase = w["phase"].copy()
-    bad_phase[0] = 2
+    bad_phase[0] = 3  # 0 and 1 are the fluids, 2 a wall
     with pytest.raises(rsph.RsphError) as e:
         s.set_particles(w["pos"], w["vel"], bad_phase)
     assert e.value.name == "EINVAL"

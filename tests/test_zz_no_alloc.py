@@ -87,7 +87,7 @@ def test_noalloc_rejects_oversized_and_invalid_input():
         rsph.eval_rates_noalloc(p, n, pos.data_ptr(), vel.data_ptr(), ph.data_ptr(), acc.data_ptr(),
                                 rate.data_ptr(), precision=0)
     assert e.value.name == "EINVAL" and "scratch" in str(e.value)
-    # a fluid id outside {0, 1} is caught on the device and rejected
+    # a phase outside {0, 1, 2} is caught on the device and rejected
     w = WL.static_droplet_2d(n_side=30)
     p = dict(w["params"])
     bad = w["phase"].copy()
