@@ -305,21 +305,6 @@ struct PassChunk {
                                                       : RSPH_CHUNK_2D_ADVECTION;
     static constexpr int N = D == 2 ? N2 : (P == Pass::Advection ? 2 : Chunk<R, D>::N);
 };
-// Waves per SIMD that a pass's register allocation must leave room for (1:
-// the compiler's own choice), for the FP32 records of the 3D substep passes.
-#ifndef RSPH_WAVES_FORCE_3D
-#define RSPH_WAVES_FORCE_3D 1
-#endif
-#ifndef RSPH_WAVES_CONTINUITY_3D
-#define RSPH_WAVES_CONTINUITY_3D 1
-#endif
-template <typename R, int D, Pass P>
-struct Waves {
-    static constexpr int N = (D == 3 && sizeof(R) == 4)
-                                 ? (P == Pass::Force ? RSPH_WAVES_FORCE_3D
-                                                     : (P == Pass::Continuity ? RSPH_WAVES_CONTINUITY_3D : 1))
-                                 : 1;
-};
 // at least 4 lanes: a 256-thread block then covers at most 64 slots, i.e. lies
 // inside one system, which the per-block partial maxima rely on
 static_assert(RSPH_LANES_2D >= 4 && RSPH_LANES_3D >= 4, "lanes per slot");
@@ -798,8 +783,9 @@ constexpr int kStageCap = 2304;
 // from the end of one row into the start of the next thus stages two compact
 // boxes instead of one box as wide as the grid.
 struct Stage {
-    // x, y, z offsets from the candidate's own cell corner; w holds the bits
-    // of (box-local x cell << 1) | phase
+    // x offset from its box's x origin (the lower corner of the box's first
+    // x cell), y and z offsets from the candidate's own cell corner; w holds
+    // the bits of (box-local x cell << 2) | phase
     float4 q[kStageCap];
     int32_t off[kStageCells + 1];  // LDS offset of each union cell (box 0's cells, then box 1's)
     int32_t gs[kStageCells];       // first global slot of each union cell
@@ -898,7 +884,8 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
     }
     if (t == 0) {
         const int total = L.wsum[0] + L.wsum[1];
-        L.ok = fits_cells && total <= kStageCap;
+        // lanes past the end of a range read up to 2 G - 1 entries beyond it
+        L.ok = fits_cells && total <= kStageCap - 2 * kMaxLanes;
         for (int q = 0; q < 2; ++q) {
             L.dims[q][0] = ux[q];
             L.dims[q][1] = uy[q];
@@ -928,7 +915,7 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
         double xj[3];
         load_pos<D>(A, j, xj);
         float4 c4;
-        c4.x = (float)(xj[0] - (double)cx * S.cell[0]);
+        c4.x = (float)((double)lx * S.cell[0] + (xj[0] - (double)cx * S.cell[0]));
         c4.y = (float)(xj[1] - (double)cy * S.cell[1]);
         c4.z = 0.f;
         if (D == 3) {
@@ -1139,11 +1126,18 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
             cellf[a] = (float)S.cell[a];
             if (a < D) oi[a] = (float)(xi[a] - (double)ci[a] * S.cell[a]);
         }
-        const float cut_hi = (float)(S.cut2 * (1.0 + 1e-5)), cut_lo = (float)(S.cut2 * (1.0 - 1e-5));
         const int i32 = (int)i;
         // the particle's cell, local to its box
         const int lx = ci[0] - L.lo[box][0] + 1, ly = ci[1] - L.lo[box][1] + 1;
         const int lz = D == 3 ? ci[2] - L.lo[box][2] + 1 : 0;
+        // x offsets from the box's x origin: each rounds to within 2^-24 X of
+        // its value, X the box's width, so the FP32 r^2 of a pair is within
+        // (2^-23 X / h + 2^-22) (2h)^2 of the FP64 one; candidates within three
+        // times that (at least 1e-5) of the cut-off take the exact test
+        const float xo = (float)((double)lx * S.cell[0] + (xi[0] - (double)ci[0] * S.cell[0]));
+        const double band =
+            fmax(1e-5, 3.0 * (ldexp((double)L.dims[box][0] * S.cell[0] * S.inv_h, -23) + ldexp(1.0, -22)));
+        const float cut_hi = (float)(S.cut2 * (1.0 + band)), cut_lo = (float)(S.cut2 * (1.0 - band));
         const int zr = D == 3 ? 1 : 0;
         for (int dz = -zr; dz <= zr; ++dz) {
             const float rz0 = oi[2] - (float)dz * cellf[2];
@@ -1168,23 +1162,28 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                     const int ke = contiguous ? re : L.off[u0 + sgm + 1];
                     // slots fit in 32 bits (the slot capacity is checked on the host)
                     const int jofs = L.gs[contiguous ? u0 : u0 + sgm] - kb;
-#pragma unroll 2
-                    for (int k0 = kb; k0 < ke; k0 += G) {
-                        // lanes past the range read the range's first entry and discard it
-                        const int k = k0 + g;
-                        const bool valid = k < ke;
-                        const float4 q = L.q[valid ? k : kb];
-                        const int w = __float_as_int(q.w);
-                        const int dx = (w >> 2) - lx;
-                        const float ax = (oi[0] - q.x) - (float)dx * cellf[0];
+                    // two entries per lane and iteration; lanes past the range
+                    // read entries beyond it (inside the staging array) and
+                    // discard them
+                    auto test = [&](int k, const float4& q) {
+                        const float ax = xo - q.x;
                         const float ay = ry0 - q.y;
                         const float az = D == 3 ? rz0 - q.z : 0.f;
                         const float r2f = ax * ax + ay * ay + az * az;
                         const int j = jofs + k;
-                        bool hit = valid && j != i32 && r2f < cut_hi;
-                        if (hit && r2f >= cut_lo)  // within the FP32 error of the cut-off
+                        bool hit = k < ke && j != i32 && r2f < cut_hi;
+                        if (hit && r2f >= cut_lo) {  // within the FP32 error of the cut-off
+                            const int dx = (__float_as_int(q.w) >> 2) - lx;
                             hit = exact_r2<D>(A, xi, j, image_offset(S, ci[0] + dx, 0), ky, kz) < S.cut2;
+                        }
                         append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
+                    };
+                    for (int k0 = kb; k0 < ke; k0 += 2 * G) {
+                        const int ka = k0 + g, kc = k0 + G + g;
+                        const float4 qa = L.q[ka];
+                        const float4 qc = L.q[kc];
+                        test(ka, qa);
+                        test(kc, qc);
                     }
                 }
             }
@@ -1280,8 +1279,11 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
         cnt = cnt_i;
     }
     const bool wall_i = phi == kWall;  // a wall particle: its B only
+    // the harmonic mean of Eq. 13 takes two values: eta_i within the fluid
+    // (and against a wall), 2 eta_i eta_o / (eta_i + eta_o) across
     const R eta_i = (R)(phi ? S.eta[1] : S.eta[0]);
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
+    const R eta_x = eta_i + eta_o > R(0) ? R(2) * eta_i * eta_o / (eta_i + eta_o) : R(0);
     nl.run(
         g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
         [&](uint32_t j, const Recs<R, 2>& rj) {
@@ -1297,9 +1299,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             // velocity, with the mirror's volume V_i
             const int phj = Geo<R>::phase(gj);
             const bool wall_j = phj == kWall;
-            const R eta_j = (phj == phi || wall_j) ? eta_i : eta_o;
-            const R es = eta_i + eta_j;
-            const R eta_bar = es > R(0) ? R(2) * eta_i * eta_j / es : R(0);
+            const R eta_bar = (phj == phi || wall_j) ? eta_i : eta_x;
             const R f = wall_i ? R(0) : eta_bar * dW * inv_r * (wall_j ? vi.w : Vj);
             av[0] += f * (vi.x - vj.x);
             av[1] += f * (vi.y - vj.y);
@@ -1778,8 +1778,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 // ---------------------------------------------------------------------------
 
 template <typename R, int D, bool PK = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Waves<R, D, Pass::Force>::N))) void k_force(
-    DevArrays A)
+__global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
     int g;
@@ -2027,8 +2026,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Waves<R,
 // ---------------------------------------------------------------------------
 
 template <typename R, int D, bool PK = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Waves<R, D, Pass::Continuity>::N))) void
-k_continuity(DevArrays A, int64_t group)
+__global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t group)
 {
     constexpr int G = Lanes<D>::G;
     int g;

@@ -101,8 +101,43 @@ def test_static_droplet_laplace_jump_trajectories():
     assert abs(jumps[rsph.FP64] / j_or - 1.0) < 0.01
     assert abs(jumps[rsph.MIXED] / jumps[rsph.FP64] - 1.0) < 0.01
     # the value itself at R / dp = 10 and density ratio 1000 is reported, not
-    # asserted: the jump against gamma / R is checked at R / dp = 45 below
+    # asserted (the penalty's spurious currents set it); the jump against
+    # gamma / R is asserted at density ratio 1 below
     assert j_or > 0
+
+
+@pytest.mark.parametrize("n_side", [50, 100, 200])
+def test_ratio1_laplace_jump_against_gamma_over_r(n_side):
+    """Young-Laplace (Eq. 37, 2D: p_in - p_out = gamma / R) for the static
+    droplet at density ratio 1 (rho 1/1, eta 0.05/0.05, gamma 1, R = 0.2) at
+    R/dp = 10, 20, 40, both forms: the jump averaged over t in [0.25, 0.6]
+    (the drop still oscillates about its lattice start) lies 4-9 % above
+    gamma / R, growing slowly with resolution, so the bound asserted is 10 %
+    (the 1 % of a converged method is not met), and the mixed form's mean
+    equals the FP64 form's to 1e-5."""
+    R = 0.2
+    w = WL.static_droplet_2d(n_side=n_side, R=R, seed=2, rho=(1.0, 1.0), eta=(0.05, 0.05))
+    p = w["params"]
+    jumps = {}
+    for prec in (rsph.FP64, rsph.MIXED):
+        s = rsph.System(p, precision=prec)
+        s.set_particles(w["pos"], w["vel"], w["phase"])
+        js = []
+        while True:
+            s.step(5)
+            o = s.observables()
+            assert o["health"] == 0
+            if o["t"] >= 0.25:
+                js.append(o["p_in"] - o["p_out"])
+            if o["t"] >= 0.6:
+                break
+        jumps[prec] = float(np.mean(js))
+        s.close()
+    ratio = jumps[rsph.FP64] / (p["gamma"] / R)
+    say(f"ratio-1 Laplace R/dp={R * n_side:.0f}: jump {jumps[rsph.FP64]:.4f} (mixed {jumps[rsph.MIXED]:.4f}), "
+        f"gamma/R {p['gamma'] / R:.4f}, ratio {ratio:.4f}")
+    assert abs(ratio - 1.0) < 0.10
+    assert abs(jumps[rsph.MIXED] / jumps[rsph.FP64] - 1.0) < 1e-5
 
 
 def relaxation_observables(s, steps, tail, every=10):
