@@ -134,9 +134,20 @@ def pmc_traffic(args):
     import hashlib
     f_csv, w_csv, cf_csv, cw_csv = args.pmc_traffic
     dim = 2 if args.workload in ("square2d", "droplet2d") else 3
-    kname = f"k_force<{'float' if args.precision == 'mixed' else 'double'}, {dim}>"
-    fetch, nf = active_mean(pmc_per_dispatch(f_csv, kname, "FETCH_SIZE"))
-    write, nw = active_mean(pmc_per_dispatch(w_csv, kname, "WRITE_SIZE"))
+    # the force pass in either record form (k_force<R, D> or k_force<R, D, packed>)
+    kname = f"k_force<{'float' if args.precision == 'mixed' else 'double'}, {dim}"
+    # the launches with work are those that write (a launch cycle also issues
+    # substep launches that exit at once, which still fetch their slot-only
+    # loads); the two runs dispatch the same sequence, so the fetch counts of
+    # those same dispatches are averaged
+    f_all = pmc_per_dispatch(f_csv, kname, "FETCH_SIZE")
+    w_all = pmc_per_dispatch(w_csv, kname, "WRITE_SIZE")
+    write, nw = active_mean(w_all)
+    if len(f_all) == len(w_all):
+        act = [k for k, x in enumerate(w_all) if x > 0.25 * max(w_all)]
+        fetch, nf = sum(f_all[k] for k in act) / len(act), len(act)
+    else:
+        fetch, nf = active_mean(f_all)
     cf = max(pmc_per_dispatch(cf_csv, "copyBuffer", "FETCH_SIZE"))
     cw = max(pmc_per_dispatch(cw_csv, "copyBuffer", "WRITE_SIZE"))
     f_scale = COPY_BYTES / (cf * 1024.0)

@@ -184,9 +184,12 @@ rsph_status rsph_create_system(const rsph_params* params, void* hip_stream, rsph
  * 10 max(u_ref, largest |vel|, walls included) here (section 2).  Resets t, counters, density
  * rates and the fault state unless opts has RSPH_KEEP_CLOCK (then t and
  * counters are kept: resume).  The arrays are host memory owned by the caller
- * and copied before the call returns.  EINVAL (nothing changed) on n < 1,
- * NaN/Inf, a phase outside {0,1,2}, mass or rho <= 0, two particles closer than
- * 1e-3 dp, or c0 = 0 with u_ref = 0 and every velocity zero.
+ * and copied before the call returns.  EINVAL (nothing changed) on n < 1 or
+ * n > 2^26 (the slots of one pool), NaN/Inf, a phase outside {0,1,2}, mass or
+ * rho <= 0, two particles closer than 1e-3 dp, or c0 = 0 with u_ref = 0 and
+ * every velocity zero.  When every particle of a fluid has the same mass (the
+ * default masses do), the substep passes take that mass from the system's
+ * constants: results are the same either way, to rounding.
  * The extra rho argument (beyond particles, velocities, fluids and masses) lets
  * a caller restore a state for a bitwise resume. */
 #define RSPH_KEEP_CLOCK 1u

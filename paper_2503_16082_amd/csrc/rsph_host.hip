@@ -421,7 +421,7 @@ Layout plan(const std::vector<rsph_system*>& sys, const rsph_system* extra)
     L.P = std::max<int64_t>((L.P + kBlock - 1) / kBlock * kBlock, kBlock);
     L.C = std::max<int64_t>(L.C, 1);
     if (L.C > kMaxCells) fail(RSPH_EINVAL, "more than 2048*2048 cells in one pool");
-    if (L.P > (int64_t)INT32_MAX / 2) fail(RSPH_EINVAL, "too many particle slots");
+    if (L.P > kMaxSlots) fail(RSPH_EINVAL, "too many particle slots (2^26 per pool)");
     return L;
 }
 
@@ -445,7 +445,8 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
     std::vector<void*> old_allocs;
     size_t old_bytes = P->bytes;
     if (grow) {
-        const int64_t Pc = std::max<int64_t>(L.P, P->P_cap + P->P_cap / 2 / kBlock * kBlock);
+        const int64_t Pc = std::max<int64_t>(
+            L.P, std::min<int64_t>(kMaxSlots / kBlock * kBlock, P->P_cap + P->P_cap / 2 / kBlock * kBlock));
         const int64_t Cc = std::max<int64_t>(L.C, P->C_cap + P->C_cap / 2);
         const int Sc = std::max(S, P->S_cap + P->S_cap / 2 + 1);
         int64_t Pg = P->standalone ? L.P : Pc;
@@ -460,7 +461,7 @@ void repack(rsph_pool* P, const std::vector<rsph_system*>& members)
             auto cells_for = [&](int64_t p) { return std::max<int64_t>(Cg, p / 4); };
             auto fits = [&](int64_t p) { return arrays_bytes(P, p, cells_for(p), Sb) <= P->budget; };
             if (fits(Pg)) {
-                const int64_t top = (int64_t)INT32_MAX / 2 / kBlock * kBlock;
+                const int64_t top = kMaxSlots / kBlock * kBlock;
                 int64_t lo = Pg, hi = Pg;
                 while (hi < top && fits(std::min(top, hi * 2))) hi = std::min(top, hi * 2);
                 lo = hi;
@@ -944,7 +945,7 @@ void validate_particles(const rsph_params& p, int64_t n, const double* pos, cons
                         const int32_t* phase, const double* mass, const double* rho)
 {
     if (n < 1) fail(RSPH_EINVAL, "n must be >= 1");
-    if (n > (int64_t)INT32_MAX / 2) fail(RSPH_EINVAL, "too many particles");
+    if (n > kMaxSlots) fail(RSPH_EINVAL, "too many particles (2^26 per pool)");
     if (!pos || !vel || !phase) fail(RSPH_EINVAL, "pos, vel and phase are required");
     const int d = p.dim;
     for (int64_t i = 0; i < n * d; ++i)
@@ -1530,7 +1531,7 @@ rsph_status rsph_read_neighbours(rsph_system* s, int64_t n, int64_t cap, int64_t
             const int64_t w = slot / kWave - w0, lane = slot % kWave;
             const int64_t dst = start[id[slot]];
             for (int q = 0; q < cnt[k]; ++q)
-                idx[dst + q] = id[nb[(w * A.kmax + q) * kWave + lane]];
+                idx[dst + q] = id[nb[(w * A.kmax + q) * kWave + lane] & kNbrIndexMask];
         }
     });
 }
@@ -1804,7 +1805,7 @@ extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_
         validate_params(params);
         if (!(params->c0 > 0)) fail(RSPH_EINVAL, "this entry point needs c0 > 0");
         if (n < 1) fail(RSPH_EINVAL, "n must be >= 1");
-        if (n > (int64_t)INT32_MAX / 2) fail(RSPH_EINVAL, "too many particles");
+        if (n > kMaxSlots) fail(RSPH_EINVAL, "too many particles (2^26 per pool)");
         if (!pos || !vel || !phase || !acc || !drho_rate) fail(RSPH_EINVAL, "pos, vel, phase, acc and drho are required");
         char* base = (char*)scratch_address();
         // a pool of one system whose arrays live in the scratch array

@@ -12,7 +12,11 @@
 //    FP64 form) so that one neighbour gather is one or two 16-byte loads;
 //  * neighbour lists are stored per wavefront, transposed: entry k of lane l of
 //    wave w is nbr[(w * kmax + k) * 64 + l], so the 64 lanes of a wave read 256
-//    contiguous bytes at every step k.
+//    contiguous bytes at every step k.  An entry holds the neighbour's slot in
+//    its low 26 bits and, in two bits per axis (x at bit 26, y at 28, z at 30),
+//    the particle's cell minus the neighbour's stencil cell, plus one (0, 1 or
+//    2): the mixed form rebuilds r_ij from the FP32 offsets in the cells and
+//    these cell differences.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,6 +33,9 @@ constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lat
 constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
 constexpr int kMaxCellsPerAxis = 512;  // 9 bits per axis in the mixed-form geometry tag
 constexpr int kMaxLanes = 16;  // lanes per particle slot in the pair passes (at most)
+constexpr int kNbrIndexBits = 26;
+constexpr uint32_t kNbrIndexMask = (1u << kNbrIndexBits) - 1u;
+constexpr int64_t kMaxSlots = (int64_t)1 << kNbrIndexBits;  // slots of a pool (at most)
 
 // method switches (mirror of the public RSPH_* flags)
 constexpr uint32_t kNoPenalty = 1u;

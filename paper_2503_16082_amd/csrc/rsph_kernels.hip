@@ -73,8 +73,8 @@ __device__ __forceinline__ Slot slot_of(const DevArrays& A)
 
 // Iterates lane g of particle i's group over list entries g, g + G, ... in
 // order.  Entries are taken CH at a time: the CH indices are loaded together,
-// then the neighbour records of all CH (load(j)), then body(j, record) runs
-// for each valid entry in list order.  The gathers of CH iterations are thus
+// then the neighbour records of all CH (load(slot)), then body(entry, record)
+// runs for each valid entry in list order.  The gathers of CH iterations are thus
 // in flight at once, while every sum accumulates in the order of the list.
 // Entries past the count reuse the group's first entry (a valid slot), so every
 // load stays inside the arrays.
@@ -92,7 +92,7 @@ __device__ __forceinline__ void for_neighbours(const DevArrays& A, int64_t i, in
         }
         decltype(load(0u)) rec[CH];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) rec[u] = load(jb[u]);
+        for (int u = 0; u < CH; ++u) rec[u] = load(jb[u] & kNbrIndexMask);
 #pragma unroll
         for (int u = 0; u < CH; ++u)
             if (k0 + u * G < cnt) body(jb[u], rec[u]);
@@ -147,9 +147,10 @@ struct Geo<double> {
     __device__ static int phase(const Q4<double>& g) { return (int)g.w & 3; }
     __device__ static bool interface(const Q4<double>& g) { return ((int)g.w >> 2) != 0; }
     template <int D>
-    __device__ static void rij(const Q4<double>& gi, const Q4<double>& gj, const SysConst& S,
+    __device__ static void rij(const Q4<double>& gi, const Q4<double>& gj, uint32_t e, const SysConst& S,
                                const double* cellr, double* r)
     {
+        (void)e;
         (void)cellr;
         double d = gi.x - gj.x;
         if (d > S.half_box[0]) d -= S.box[0];
@@ -184,27 +185,17 @@ struct Geo<float> {
     }
     __device__ static int phase(const Q4<float>& g) { return (int)((__float_as_uint(g.w) >> 28) & 3u); }
     __device__ static bool interface(const Q4<float>& g) { return ((__float_as_uint(g.w) >> 27) & 1u) != 0; }
+    // r_ij = (o_i - o_j) + (c_i - c_j) cell, the cell differences (periodic
+    // wrap included) taken from the list entry e
     template <int D>
-    __device__ static void rij(const Q4<float>& gi, const Q4<float>& gj, const SysConst& S,
+    __device__ static void rij(const Q4<float>& gi, const Q4<float>& gj, uint32_t e, const SysConst& S,
                                const float* cellr, float* r)
     {
-        const uint32_t ti = __float_as_uint(gi.w), tj = __float_as_uint(gj.w);
-        int dc = (int)(ti & 511u) - (int)(tj & 511u);
-        if (dc > 1) dc -= S.ncell[0];
-        else if (dc < -1) dc += S.ncell[0];
-        r[0] = (gi.x - gj.x) + (float)dc * cellr[0];
-        dc = (int)((ti >> 9) & 511u) - (int)((tj >> 9) & 511u);
-        if (dc > 1) dc -= S.ncell[1];
-        else if (dc < -1) dc += S.ncell[1];
-        r[1] = (gi.y - gj.y) + (float)dc * cellr[1];
-        if (D == 3) {
-            dc = (int)((ti >> 18) & 511u) - (int)((tj >> 18) & 511u);
-            if (dc > 1) dc -= S.ncell[2];
-            else if (dc < -1) dc += S.ncell[2];
-            r[2] = (gi.z - gj.z) + (float)dc * cellr[2];
-        } else {
-            r[2] = 0.0f;
-        }
+        (void)S;
+        r[0] = (gi.x - gj.x) + (float)((int)((e >> 26) & 3u) - 1) * cellr[0];
+        r[1] = (gi.y - gj.y) + (float)((int)((e >> 28) & 3u) - 1) * cellr[1];
+        if (D == 3) r[2] = (gi.z - gj.z) + (float)((int)(e >> 30) - 1) * cellr[2];
+        else r[2] = 0.0f;
     }
 };
 
@@ -342,10 +333,11 @@ __device__ __forceinline__ Slot slot_of_group(const DevArrays& A, int& g)
     return lookup_slot(A, i);
 }
 
-// Neighbour-list walk of the substep passes, lane g of particle i's group
+// Neighbour-list walk of the pair passes, lane g of particle i's group
 // taking entries g, g + G, ... in order, CH at a time: the records of a chunk
-// are gathered together and the indices of the next chunk are loaded while
-// the current one is evaluated.  The first chunk's indices are requested by
+// are gathered together (load(slot)) and the indices of the next chunk are
+// loaded while the current one is evaluated; body(entry, records) gets the
+// whole list entry, cell differences included.  The first chunk's indices are requested by
 // start(), which needs only the slot, so that their latency overlaps the
 // system lookup; entries past the count hold stale values and are never used
 // as addresses (a lane past the count reuses its group's first entry).
@@ -371,7 +363,7 @@ struct NbrList {
             for (int u = 0; u < CH; ++u) jb[u] = k0 + u * G < cnt ? jn[u] : jn[0];
             decltype(load(0u)) rec[CH];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) rec[u] = load(jb[u]);
+            for (int u = 0; u < CH; ++u) rec[u] = load(jb[u] & kNbrIndexMask);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int k = k0 + (CH + u) * G;
@@ -957,17 +949,25 @@ __device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi,
 }
 
 // Ordered append of the hits of G consecutive candidates tested by the lanes
-// of a group: the ballot keeps the list in candidate order.
-template <int G>
-__device__ __forceinline__ void append_hits(bool hit, uint32_t entry, int gshift, uint32_t below, uint32_t* out,
+// of a group: the ballot keeps the list in candidate order.  entry() makes the
+// list entry of a hit.
+template <int G, typename Entry>
+__device__ __forceinline__ void append_hits(bool hit, Entry&& entry, int gshift, uint32_t below, uint32_t* out,
                                             int kmax, int& cnt)
 {
     const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
     if (hit) {
         const int at = cnt + __popc(gm & below);
-        if (at < kmax) out[(int64_t)at * kWave] = entry;
+        if (at < kmax) out[(int64_t)at * kWave] = entry();
     }
     cnt += __popc(gm);
+}
+
+// list entry: slot j and, per axis, the particle's cell minus the stencil
+// cell's, plus one (the stencil offsets dx, dy, dz are -1, 0 or 1)
+__device__ __forceinline__ uint32_t nbr_entry(int64_t j, int dx, int dy, int dz)
+{
+    return (uint32_t)j | ((uint32_t)(1 - dx) << 26) | ((uint32_t)(1 - dy) << 28) | ((uint32_t)(1 - dz) << 30);
 }
 
 // Every candidate of the 3^d stencil tested by the exact FP64 predicate on
@@ -1007,7 +1007,8 @@ __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, co
                     if (j < je && j != i) {
                         hit = exact_r2<D>(A, xi, j, kx, ky, kz) < S.cut2;
                     }
-                    append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
+                    append_hits<G>(hit, [&] { return nbr_entry(j, dx, dy, dz); }, gshift, below, out, A.kmax,
+                                   cnt);
                 }
             }
         }
@@ -1171,12 +1172,14 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                         const float az = D == 3 ? rz0 - q.z : 0.f;
                         const float r2f = ax * ax + ay * ay + az * az;
                         const int j = jofs + k;
-                        bool hit = k < ke && j != i32 && r2f < cut_hi;
-                        if (hit && r2f >= cut_lo) {  // within the FP32 error of the cut-off
-                            const int dx = (__float_as_int(q.w) >> 2) - lx;
-                            hit = exact_r2<D>(A, xi, j, image_offset(S, ci[0] + dx, 0), ky, kz) < S.cut2;
-                        }
-                        append_hits<G>(hit, (uint32_t)j, gshift, below, out, A.kmax, cnt);
+                        // (no short circuit: one mask, no branch)
+                        bool hit = (k < ke) & (j != i32) & (r2f < cut_hi);
+                        // the stencil x offset of the candidate's cell
+                        auto dx = [&] { return (__float_as_int(q.w) >> 2) - lx; };
+                        if (hit && r2f >= cut_lo)  // within the FP32 error of the cut-off
+                            hit = exact_r2<D>(A, xi, j, image_offset(S, ci[0] + dx(), 0), ky, kz) < S.cut2;
+                        append_hits<G>(hit, [&] { return nbr_entry(j, dx(), dy, dz); }, gshift, below, out, A.kmax,
+                                       cnt);
                     };
                     for (int k0 = kb; k0 < ke; k0 += 2 * G) {
                         const int ka = k0 + g, kc = k0 + G + g;
@@ -1286,10 +1289,10 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     const R eta_x = eta_i + eta_o > R(0) ? R(2) * eta_i * eta_o / (eta_i + eta_o) : R(0);
     nl.run(
         g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
-        [&](uint32_t j, const Recs<R, 2>& rj) {
+        [&](uint32_t ent, const Recs<R, 2>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
-            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
@@ -1424,10 +1427,10 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
             if constexpr (D == 3) return Recs<R, 3>{{geo[j], b0[j], b1[j]}};
             else return Recs<R, 2>{{geo[j], b0[j]}};
         },
-        [&](uint32_t j, const Recs<R, D>& rj) {
+        [&](uint32_t ent, const Recs<R, D>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
-            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const Q4<R> Bj0 = rj.q[1];
@@ -1746,12 +1749,12 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     R gsum[3] = {0, 0, 0};
     nl.run(
         g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], th[j]}}; },
-        [&](uint32_t j, const Recs<R, 2>& rj) {
+        [&](uint32_t ent, const Recs<R, 2>& rj) {
             const Q4<R> gj = rj.q[0];
             const int phj = Geo<R>::phase(gj);
             if (phj == phi || phj == kWall) return;  // walls carry no colour
             R r[3];
-            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const R Vj = PK ? fp.m(phj) * recip<R>(fp.rho(phj, rj.q[1].w)) : rj.q[1].y;
@@ -1845,10 +1848,10 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             if constexpr (PK) return Recs<R, 2>{{geo[j], vin[j]}};
             else return Recs<R, 3>{{geo[j], th[j], vin[j]}};
         },
-        [&](uint32_t j, const Recs<R, NR>& rj) {
+        [&](uint32_t ent, const Recs<R, NR>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
-            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const R rr = r2 * inv_r;
@@ -1898,7 +1901,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             if (D == 3) sp[2] += fp * e[2];
             if (!surface || wall_j) return;  // walls carry no colour
             const bool same = Geo<R>::phase(gj) == phi;
-            const Q4<R> cj = col[j];
+            const Q4<R> cj = col[ent & kNbrIndexMask];
             const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
             // Pi e = gamma (|g| e - g (g . e) / |g|)
             const R gie = (ci.x * e[0] + ci.y * e[1] + ci.z * e[2]) * ci.w;
@@ -2105,10 +2108,10 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
             if constexpr (PK) return Recs<R, 2>{{geo[j], vk[j]}};
             else return Recs<R, 3>{{geo[j], th[j], vk[j]}};
         },
-        [&](uint32_t j, const Recs<R, NR>& rj) {
+        [&](uint32_t ent, const Recs<R, NR>& rj) {
             const Q4<R> gj = rj.q[0];
             R r[3];
-            Geo<R>::template rij<D>(gi, gj, S, cellr, r);
+            Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_r<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
