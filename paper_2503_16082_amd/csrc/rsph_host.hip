@@ -138,6 +138,8 @@ struct rsph_system {
     bool has_particles = false;
     // every particle of a fluid has the same mass (SysConst::mphase)
     bool uniform_mass = true;
+    // the system holds wall particles
+    bool has_walls = true;
     bool faulted = false;
     bool rates_valid = false;
     // as of the host's last read of the system's device state
@@ -353,7 +355,7 @@ size_t plan_arrays(Mem& M, int dim, int precision, DevArrays& A, int32_t*& mask,
     A.flags = M.template take<uint8_t>(Pc);
     A.nbr = M.template take<uint32_t>(Pc * (size_t)A.kmax);
     A.ncount = M.template take<int32_t>(Pc);
-    A.xd = M.template take<double>(Pc * 4);
+    A.xd = M.template take<double>(Pc * (dim == 2 ? 2 : 4));
     A.r_acc = M.template take<double>(3 * Pc);
     A.r_accp = M.template take<double>(3 * Pc);
     A.r_accs = M.template take<double>(3 * Pc);
@@ -672,8 +674,11 @@ DevArrays kernel_view(rsph_pool* P)
     DevArrays A = P->A;
     A.work = P->timing ? P->work_dev : nullptr;
     A.packed = 1;
-    for (const rsph_system* s : P->systems)
+    A.walls = 0;
+    for (const rsph_system* s : P->systems) {
         if (s && !s->uniform_mass) A.packed = 0;
+        if (s && s->has_walls) A.walls = 1;
+    }
     return A;
 }
 
@@ -967,6 +972,7 @@ void validate_particles(const rsph_params& p, int64_t n, const double* pos, cons
 // other mix of masses sends the pool through the passes that gather the volume.
 void set_fluid_masses(rsph_system* s, int64_t n, const int32_t* phase, const double* mass)
 {
+    s->has_walls = std::find(phase, phase + n, kWall) != phase + n;
     s->uniform_mass = true;
     if (!mass) return;
     bool seen[2] = {false, false};
@@ -1821,9 +1827,6 @@ extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_
         s.sc = make_const(*params);
         s.ncells = s.sc.ncells;
         s.n = n;
-        // masses on the device are not inspected: given ones take the passes
-        // that gather each neighbour's volume
-        s.uniform_mass = mass == nullptr;
         Layout L = plan({}, &s);
         CountCarver count;
         DevArrays probe;
@@ -1838,7 +1841,8 @@ extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_
         }
         ScratchCarver carve{base, kScratchBytes};
         plan_arrays(carve, P.dim, P.precision, P.A, P.d_mask, P.d_targets, P.work_dev, L.P, L.C, 1);
-        int32_t* bad = carve.take<int32_t>(1);
+        // what the load finds: invalid input, walls, per-fluid mass range
+        unsigned long long* probe_d = carve.take<unsigned long long>(kLoadProbeWords);
         P.P_cap = L.P;
         P.C_cap = L.C;
         P.S_cap = 1;
@@ -1846,17 +1850,29 @@ extern "C" rsph_status rsph_eval_rates_noalloc(const rsph_params* params, int64_
         // the scratch keeps the last call's contents: clear what starts at zero
         launch_fill_i32(Lc, P.A.cell_cnt, L.C, 0);
         launch_fill_i32(Lc, P.work_dev, P.A.work_cap, 0);
-        launch_fill_i32(Lc, bad, 1, 0);
+        launch_fill_i32(Lc, (int32_t*)probe_d, 2, 0);
+        launch_fill_i32(Lc, (int32_t*)(probe_d + 1), 4, -1);
+        launch_fill_i32(Lc, (int32_t*)(probe_d + 3), 4, 0);
         repack(&P, {&s});
         s.has_particles = true;
         s.sc.p_n = n;
         HIPCHECK(hipMemcpyAsync((void*)(P.A.sc + s.row), &s.sc, sizeof(SysConst), hipMemcpyHostToDevice, P.stream));
         launch_load_particles(Lc, P.A, s.p_off, n, pos, vel, phase, mass, rho, s.sc.box, s.sc.rho0, s.sc.sigma0,
-                              bad);
-        int32_t bad_h = 0;
-        HIPCHECK(hipMemcpyAsync(&bad_h, bad, sizeof bad_h, hipMemcpyDeviceToHost, P.stream));
+                              probe_d);
+        unsigned long long probe_h[kLoadProbeWords] = {};
+        HIPCHECK(hipMemcpyAsync(probe_h, probe_d, sizeof probe_h, hipMemcpyDeviceToHost, P.stream));
         HIPCHECK(hipStreamSynchronize(P.stream));
-        if (bad_h) fail(RSPH_EINVAL, "a phase outside {0,1,2}, a non-finite value, or a mass or density <= 0");
+        if (probe_h[0] & 1ull)
+            fail(RSPH_EINVAL, "a phase outside {0,1,2}, a non-finite value, or a mass or density <= 0");
+        // the same choice of pair passes as the allocating path makes on the host
+        s.has_walls = (probe_h[0] & 2ull) != 0;
+        s.uniform_mass = true;
+        for (int f = 0; f < 2; ++f) {
+            if (probe_h[1 + f] > probe_h[3 + f]) continue;  // no particle of this fluid
+            if (probe_h[1 + f] != probe_h[3 + f]) s.uniform_mass = false;
+            else std::memcpy(&s.sc.mphase[f], &probe_h[1 + f], sizeof(double));
+        }
+        HIPCHECK(hipMemcpyAsync((void*)(P.A.sc + s.row), &s.sc, sizeof(SysConst), hipMemcpyHostToDevice, P.stream));
         reset_dyn(&s, false);
         check_spacing(&s);
         // one evaluation, as rsph_eval_rates

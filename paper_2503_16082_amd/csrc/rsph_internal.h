@@ -154,7 +154,9 @@ struct DevArrays {
     // passes gather two records per neighbour, {frozen position} and
     // {velocity, pressure}, and recover rho = rho0 + p / c0^2 and V = m / rho
     int32_t packed;
-    int32_t pad_;
+    // 1: some system holds wall particles (0: the substep passes leave out the
+    // wall branches)
+    int32_t walls;
     // FP64 state, structure of arrays
     double* pos[3];
     double* vel[3];
@@ -192,7 +194,8 @@ struct DevArrays {
     uint8_t* flags;
     uint32_t* nbr;
     int32_t* ncount;
-    double* xd;      // frozen FP64 position {x, y, z, phase} per slot, read by the density summation
+    double* xd;      // frozen FP64 position per slot (D doubles, phase in the signs of x and y),
+                     // read by the neighbour build and the density summation
     // rates written by an evaluation (FP64, slot order)
     double* r_acc;    // 3 * P
     double* r_accp;
@@ -245,9 +248,14 @@ void launch_force(const Launch& L, const DevArrays& A, Ev ev);
 void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group);
 void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group);
 void launch_observables(const Launch& L, const DevArrays& A);
+// what the device-side particle load found: probe[0] bit 0 an invalid input,
+// bit 1 a wall particle; probe[1 + f] and probe[3 + f] the smallest and the
+// largest mass bits of fluid f (positive doubles order as their bits); the
+// caller sets probe to {0, ~0, ~0, 0, 0} first
+constexpr int kLoadProbeWords = 5;
 void launch_load_particles(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, const double* pos,
                            const double* vel, const int32_t* phase, const double* mass, const double* rho,
-                           const double* box, const double* rho0, double sigma0, int32_t* bad);
+                           const double* box, const double* rho0, double sigma0, unsigned long long* probe);
 void launch_store_rates(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, double* acc, double* drho);
 
 constexpr int kObsPart = 16;  // partial sums per wave and pass

@@ -103,6 +103,19 @@ template <typename R, int N>
 struct Recs {
     Q4<R> q[N];
 };
+
+// The FP64 position of a slot as the rank pass leaves it, with the phase's
+// two bits in the sign bits of x and y (positions are wrapped into [0, L), so
+// their signs are free): 16 bytes per slot in 2D; in 3D a 32-byte slot of
+// which a reader takes the 24 bytes of x, y, z (two loads, one cache line).
+template <int D>
+__device__ __forceinline__ void store_pos(const DevArrays& A, int64_t j, const double* x, int ph)
+{
+    const double x0 = (ph & 1) ? -x[0] : x[0];
+    const double x1 = (ph & 2) ? -x[1] : x[1];
+    if constexpr (D == 2) ((double2*)A.xd)[j] = double2{x0, x1};
+    else ((double4*)A.xd)[j] = double4{x0, x1, x[2], 0.0};
+}
 struct Pos3 {
     double x[3];
     int ph;
@@ -459,7 +472,8 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
     }
     const double rho = A.rho[i], drho = A.drho[i], mass = A.mass[i];
     const int32_t id = A.id[i], phase = A.phase[i];
-    const double4 xold = ((const double4*)A.xd)[i];  // position at the last binning
+    double xo[3];
+    load_pos<D>(A, i, xo);  // position at the last binning
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;  // wave-uniform: a wave lies in one system or in none
     SysDyn& Dy = A.sd[c.s];
@@ -501,7 +515,6 @@ __global__ __launch_bounds__(kBlock) void k_key(DevArrays A, int64_t group)
         // one cell of motion since then (periodic distance) is counted, once
         // per advection step, when the step begins
         if (A.mode == 0 && Dy.binned) {
-            const double xo[3] = {xold.x, xold.y, xold.z};
             bool far = false;
             for (int a = 0; a < D; ++a) {
                 const int dc = abs(ck[a] - cell_of(xo[a], S, a));
@@ -728,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
             A.vel[a][d] = v[a];
             v2 += v[a] * v[a];
         }
-        ((double4*)A.xd)[d] = double4{x[0], x[1], x[2], (double)ph};
+        store_pos<D>(A, d, x, ph);
         A.rho[d] = rho;
         A.drho[d] = drho;
         A.mass[d] = mass;
@@ -791,21 +804,21 @@ struct Stage {
 
 __device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-// FP64 position of slot j from its packed record (16 bytes read in 2D)
+// FP64 position of slot j from its packed record, and its phase
 template <int D>
-__device__ __forceinline__ void load_pos(const DevArrays& A, int64_t j, double* x)
+__device__ __forceinline__ void load_pos(const DevArrays& A, int64_t j, double* x, int* ph = nullptr)
 {
+    double2 q;
     if constexpr (D == 2) {
-        const double2 q = ((const double2*)A.xd)[2 * j];
-        x[0] = q.x;
-        x[1] = q.y;
+        q = ((const double2*)A.xd)[j];
         x[2] = 0.0;
     } else {
-        const double4 q = ((const double4*)A.xd)[j];
-        x[0] = q.x;
-        x[1] = q.y;
-        x[2] = q.z;
+        q = ((const double2*)A.xd)[2 * j];
+        x[2] = A.xd[4 * j + 2];
     }
+    x[0] = fabs(q.x);
+    x[1] = fabs(q.y);
+    if (ph) *ph = (signbit(q.x) ? 1 : 0) | (signbit(q.y) ? 2 : 0);
 }
 
 // periodic image offset along axis a of the stencil cell c (unwrapped: one
@@ -905,7 +918,8 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
         const int cy = wrap_cell(L.lo[q][1] - 1 + ly, S.ncell[1]);
         const int64_t j = L.gs[lo] + (k - L.off[lo]);
         double xj[3];
-        load_pos<D>(A, j, xj);
+        int phj;
+        load_pos<D>(A, j, xj, &phj);
         float4 c4;
         c4.x = (float)((double)lx * S.cell[0] + (xj[0] - (double)cx * S.cell[0]));
         c4.y = (float)(xj[1] - (double)cy * S.cell[1]);
@@ -914,7 +928,7 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
             const int cz = wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]);
             c4.z = (float)(xj[2] - (double)cz * S.cell[2]);
         }
-        c4.w = __int_as_float((lx << 2) | (A.phase[j] & 3));
+        c4.w = __int_as_float((lx << 2) | phj);
         L.q[k] = c4;
     }
     __syncthreads();
@@ -1035,8 +1049,9 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
     for_neighbours<G, CH>(
         A, i, g, live ? cnt : 0,
         [&](uint32_t j) {
-            const double4 q = ((const double4*)A.xd)[j];  // one 32-byte record per neighbour
-            return Pos3{{q.x, q.y, q.z}, (int)q.w};
+            Pos3 q;  // one record of D doubles per neighbour
+            load_pos<D>(A, j, q.x, &q.ph);
+            return q;
         },
         [&](uint32_t j, const Pos3& rj) {
             cross |= rj.ph != ph && rj.ph != kWall;  // walls carry no colour
@@ -1780,7 +1795,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 // with the projected penalty (Eqs. 24, 27, 30, 33), kick
 // ---------------------------------------------------------------------------
 
-template <typename R, int D, bool PK = false>
+template <typename R, int D, bool PK = false, bool WL = true>
 __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 {
     constexpr int G = Lanes<D>::G;
@@ -1874,7 +1889,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
                 pR = rj.q[1].z;
                 Vj = rj.q[1].y;
             }
-            const bool wall_j = phj == kWall;
+            const bool wall_j = WL && phj == kWall;  // WL: the pool holds walls
             if (wall_j) {
                 // the wall's mirrored state: rho_R = rho_i, U_R = 2 U_w - U_L,
                 // p_R = p_i - rho_i g . r_ij, volume V_i
@@ -2028,7 +2043,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
 // second half-step, and the first half-step of the next substep
 // ---------------------------------------------------------------------------
 
-template <typename R, int D, bool PK = false>
+template <typename R, int D, bool PK = false, bool WL = true>
 __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t group)
 {
     constexpr int G = Lanes<D>::G;
@@ -2123,7 +2138,7 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
             // so v_i.e + U* = (rho_j (v_i - v_j).e + (p_i - p_j)/c0) / (rho_i + rho_j);
             // against a wall's mirror (rho_R = rho_i, U_R = 2 U_w - U_L,
             // p_R = p_i - rho_i g . r_ij, volume V_i): U* = U_w + g . r_ij / (2 c0)
-            if (phj == kWall) {
+            if (WL && phj == kWall) {  // WL: the pool holds walls
                 const R Ustar = -vje + (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]) * R(0.5) * inv_c0;
                 s += (vie + Ustar) * dW * ti.y;
                 return;
@@ -2433,7 +2448,31 @@ void launch_bin(const Launch& L, const DevArrays& A, int64_t group)
 constexpr int G2 = Lanes<2>::G;
 constexpr int G3 = Lanes<3>::G;
 
-// the substep passes: the packed form when every fluid's masses are uniform
+// the substep passes: the packed form when every fluid's masses are uniform,
+// and without the wall branches when no system holds walls (PK and WL are
+// the template arguments after the record type and dimension)
+#define RSPH_GO_PW(KERNEL, PKV, WLV, EV, ...)                                                      \
+    do {                                                                                           \
+        if (L.fp64) {                                                                              \
+            if (L.dim == 2)                                                                        \
+                go(KERNEL<double, 2, PKV, WLV>, slot_grid(A.P, G2), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+            else                                                                                   \
+                go(KERNEL<double, 3, PKV, WLV>, slot_grid(A.P, G3), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+        } else {                                                                                   \
+            if (L.dim == 2)                                                                        \
+                go(KERNEL<float, 2, PKV, WLV>, slot_grid(A.P, G2), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+            else                                                                                   \
+                go(KERNEL<float, 3, PKV, WLV>, slot_grid(A.P, G3), dim3(kBlock), L.stream, EV, __VA_ARGS__); \
+        }                                                                                          \
+    } while (0)
+#define RSPH_DISPATCH_PW(KERNEL, EV, ...)                                                          \
+    do {                                                                                           \
+        if (A.packed && A.walls) RSPH_GO_PW(KERNEL, true, true, EV, __VA_ARGS__);                  \
+        else if (A.packed) RSPH_GO_PW(KERNEL, true, false, EV, __VA_ARGS__);                       \
+        else if (A.walls) RSPH_GO_PW(KERNEL, false, true, EV, __VA_ARGS__);                        \
+        else RSPH_GO_PW(KERNEL, false, false, EV, __VA_ARGS__);                                    \
+    } while (0)
+// the colour pass takes the packed form only
 #define RSPH_DISPATCH_PK(KERNEL, EV, ...)                                                          \
     do {                                                                                           \
         if (!A.packed) {                                                                           \
@@ -2473,7 +2512,7 @@ void launch_shift(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH(k_
 
 void launch_colour(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH_PK(k_colour, ev, A); }
 
-void launch_force(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH_PK(k_force, ev, A); }
+void launch_force(const Launch& L, const DevArrays& A, Ev ev) { RSPH_DISPATCH_PW(k_force, ev, A); }
 
 void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group)
 {
@@ -2483,7 +2522,7 @@ void launch_dt_substep(const Launch& L, const DevArrays& A, int64_t group)
 
 void launch_continuity(const Launch& L, const DevArrays& A, Ev ev, int64_t group)
 {
-    RSPH_DISPATCH_PK(k_continuity, ev, A, group);
+    RSPH_DISPATCH_PW(k_continuity, ev, A, group);
 }
 
 // ---------------------------------------------------------------------------
@@ -2501,7 +2540,7 @@ __global__ __launch_bounds__(kBlock) void k_load_particles(DevArrays A, int64_t 
                                                            const double* pos, const double* vel,
                                                            const int32_t* phase, const double* mass,
                                                            const double* rho, double3 box, double2 rho0,
-                                                           double sigma0, int32_t* bad)
+                                                           double sigma0, unsigned long long* probe)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -2533,7 +2572,13 @@ __global__ __launch_bounds__(kBlock) void k_load_particles(DevArrays A, int64_t 
     A.drho[o] = 0.0;
     A.id[o] = (int32_t)i;
     A.phase[o] = ph;
-    if (wrong) atomicOr(bad, 1);
+    if (wrong) atomicOr(probe, 1ull);
+    if (ph == kWall) atomicOr(probe, 2ull);
+    else if (!wrong) {
+        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+        atomicMin(probe + 1 + ph, mb);
+        atomicMax(probe + 3 + ph, mb);
+    }
 }
 
 // Rates of the last evaluation, from slot order into the caller's order:
@@ -2551,12 +2596,12 @@ __global__ __launch_bounds__(kBlock) void k_store_rates(DevArrays A, int64_t p_o
 
 void launch_load_particles(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, const double* pos,
                            const double* vel, const int32_t* phase, const double* mass, const double* rho,
-                           const double* box, const double* rho0, double sigma0, int32_t* bad)
+                           const double* box, const double* rho0, double sigma0, unsigned long long* probe)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_load_particles, flat_grid(n), dim3(kBlock), 0, L.stream, A, p_off, n, L.dim, pos,
                            vel, phase, mass, rho, double3{box[0], box[1], box[2]}, double2{rho0[0], rho0[1]},
-                           sigma0, bad);
+                           sigma0, probe);
 }
 
 void launch_store_rates(const Launch& L, const DevArrays& A, int64_t p_off, int64_t n, double* acc, double* drho)
