@@ -372,15 +372,19 @@ def test_eval_rates_parity_particle_masses(dim, precision):
     compare_rates(g, ref, precision, f"masses/d{dim}/p{precision}")
 
 
+@pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_trajectory_particle_masses(precision):
-    """3 advection steps of the 2D static droplet with particle masses spread
-    by 5% within each fluid, against the oracle: the stepping path that
-    gathers each neighbour's volume."""
-    w = WL.static_droplet_2d(n_side=40, R=0.2, seed=3)
+def test_trajectory_particle_masses(precision, dim):
+    """3 advection steps of a static droplet with particle masses spread by 5%
+    within each fluid, against the oracle: the stepping path that gathers each
+    neighbour's volume (in 3D the one-mass-per-fluid path is the default)."""
+    if dim == 2:
+        w = WL.static_droplet_2d(n_side=40, R=0.2, seed=3)
+    else:
+        w = WL.static_droplet_3d(n_side=16, R=0.3, seed=3)
     p = w["params"]
     mass = varied_masses(p, w["phase"], seed=4)
-    say(f"trajectory particle masses precision={precision}")
+    say(f"trajectory particle masses dim={dim} precision={precision}")
     st = O.State(p, w["pos"], w["vel"], w["phase"], mass=mass)
     st.step(3)
     s = rsph.System(p, precision=precision)
