@@ -678,6 +678,10 @@ DevArrays kernel_view(rsph_pool* P)
     // slower per launch at 40,000 particles, so 2D keeps three records
     A.packed = P->dim == 3 ? 1 : 0;
     A.walls = 0;
+    // an idle substep launch over 8.4M slots fetched 0.5 GB of slot-only loads
+    // and took 0.26 ms; small pools keep the loads ahead of the state check,
+    // which shortens their latency-bound launches
+    A.state_first = P->A.P >= ((int64_t)1 << 20) ? 1 : 0;
     for (const rsph_system* s : P->systems) {
         if (s && !s->uniform_mass) A.packed = 0;
         if (s && s->has_walls) A.walls = 1;

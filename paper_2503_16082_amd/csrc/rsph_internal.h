@@ -157,6 +157,10 @@ struct DevArrays {
     // 1: some system holds wall particles (0: the substep passes leave out the
     // wall branches)
     int32_t walls;
+    // 1: a large pool, whose substep passes check the system's state before
+    // any slot load, so that a launch with nothing to do reads almost nothing
+    int32_t state_first;
+    int32_t pad_;
     // FP64 state, structure of arrays
     double* pos[3];
     double* vel[3];

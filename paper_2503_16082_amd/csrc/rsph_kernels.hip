@@ -1723,6 +1723,20 @@ __global__ void k_reset_ksub_max(DevArrays A)
 // substep pair pass 1: colour gradient (Eq. 22) of interface particles
 // ---------------------------------------------------------------------------
 
+// The substep as it starts, for the continuity pass that ends it: taken by
+// the first thread of the system's first block (no pass before the
+// continuity pass reads these fields; taking it twice stores the same values)
+template <int G>
+__device__ __forceinline__ void colour_snapshot(const DevArrays& A, const Slot& c, SysDyn& Dy)
+{
+    if (A.mode == 0 && threadIdx.x == 0 && logical_block() * (kBlock / G) == A.sc[c.s].p_off) {
+        Dy.sub_state = Dy.state;
+        Dy.sub_health = Dy.health;
+        Dy.sub_ksub = Dy.ksub;
+        Dy.sub_tau = Dy.tau;
+    }
+}
+
 template <typename R, int D, bool PK = false>
 __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
 {
@@ -1730,6 +1744,12 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     int g;
     const int64_t i = group_slot<G>(g);
     if (i >= A.P) return;
+    if (A.state_first) {
+        const Slot c0 = lookup_slot(A, i);
+        if (c0.s < 0) return;
+        colour_snapshot<G>(A, c0, A.sd[c0.s]);
+        if (!substep_on(A.sd[c0.s], A.mode)) return;
+    }
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     NbrList<G, PassChunk<R, D, Pass::Colour>::N> nl;
@@ -1740,14 +1760,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
-    if (A.mode == 0 && threadIdx.x == 0 && logical_block() * (kBlock / G) == A.sc[c.s].p_off) {
-        // the substep as it starts, for the continuity pass that ends it (no
-        // pass before that reads these fields)
-        Dy.sub_state = Dy.state;
-        Dy.sub_health = Dy.health;
-        Dy.sub_ksub = Dy.ksub;
-        Dy.sub_tau = Dy.tau;
-    }
+    colour_snapshot<G>(A, c, Dy);
     if (!substep_on(Dy, A.mode)) return;
     const bool on = c.lane && (fl & kFlagInterface);
     if (!__any(on)) return;  // wave without interface particles
@@ -1802,6 +1815,10 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     int g;
     const int64_t i = group_slot<G>(g);
     if (i >= A.P) return;
+    if (A.state_first) {
+        const Slot c0 = lookup_slot(A, i);
+        if (c0.s < 0 || !substep_on(A.sd[c0.s], A.mode)) return;
+    }
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* col = (const Q4<R>*)A.col;
@@ -2050,6 +2067,16 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
     int g;
     const int64_t i = group_slot<G>(g);
     if (i >= A.P) return;
+    if (A.state_first) {
+        // the same exits as below, before any slot load
+        const Slot c0 = lookup_slot(A, i);
+        if (c0.s < 0) return;
+        const SysDyn& D0 = A.sd[c0.s];
+        const bool idle = A.mode == 1           ? !D0.stepping
+                          : A.sc[c0.s].fuse_dt ? D0.sub_state != kSubstepping
+                                               : D0.state != kSubstepping && D0.state != kEnding;
+        if (idle) return;
+    }
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
     NbrList<G, PassChunk<R, D, Pass::Continuity>::N> nl;

@@ -317,6 +317,32 @@ def test_fp64_trajectory_method_switches(case):
     s.close()
 
 
+def test_fp64_trajectory_large_pool_matches_oracle():
+    """2 advection steps of a 2D static droplet of 1,048,576 particles in the
+    FP64 form against the oracle: above a million slots the substep passes
+    check the system's state before any slot load, and a separate pass ends
+    each substep."""
+    w = WL.static_droplet_2d(n_side=1024, R=0.2, seed=5)
+    p = w["params"]
+    say(f"trajectory static droplet 2D n={len(w['pos'])}, 2 advection steps")
+    st = O.State(p, w["pos"], w["vel"], w["phase"])
+    st.step(2)
+    s = rsph.System(p, precision=0)
+    s.set_particles(w["pos"], w["vel"], w["phase"])
+    s.step(2)
+    o = s.observables()
+    ref = st.observables()
+    assert o["n_outer"] == 2 and o["n_sub"] == ref["n_sub"] and o["health"] == 0
+    ev = normwise(s.read("vel"), st.vel)
+    er = normwise(s.read("rho") - np.asarray(p["rho0"])[w["phase"]],
+                  st.rho - np.asarray(p["rho0"])[w["phase"]])
+    dpos = s.read("pos") - O.wrap(p, st.pos)
+    dpos -= np.round(dpos)
+    say(f"large pool trajectory vel {ev:.2e} rho {er:.2e} pos {np.abs(dpos).max():.2e}")
+    assert ev < 1e-9 and er < 1e-9 and np.abs(dpos).max() < 1e-12
+    s.close()
+
+
 def test_fp64_trajectory_matches_oracle_3d_large():
     """2 advection steps (80 substeps) of a 3D static droplet of 74,088
     particles: past the fused-size limit, so a pass of its own ends each
