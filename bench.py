@@ -410,6 +410,59 @@ def cpu_baseline(w, min_seconds, max_steps=5000):
     }
 
 
+# The oracle's CPU baselines of the benchmark set: (name, workload builder,
+# advection steps timed).  The static droplet in full (200 steps), a 50-step
+# window of the square droplet, one step of the 3D droplet and of the impact.
+CPU_PLAN = [
+    ("static_droplet_2d (2,500 particles, 200 steps)", lambda: WL.static_droplet_2d(n_side=50), 200),
+    ("square_droplet_2d (40,000 particles, steps 1-50)", lambda: WL.square_droplet_2d(n_side=200), 50),
+    ("static_droplet_3d (262,144 particles, 1 step)", lambda: WL.static_droplet_3d(n_side=64), 1),
+    ("droplet_impact_3d (8,388,608 particles, 1 step)", lambda: WL.droplet_impact_3d(), 1),
+]
+
+
+def cpu_plan_leg(k):
+    """One entry of CPU_PLAN timed on the oracle with the OpenMP threads of
+    this process; one JSON line."""
+    from oracle import oracle as O
+    name, build, steps = CPU_PLAN[k]
+    w = build()
+    p = w["params"]
+    n = w["pos"].shape[0]
+    model, threads = host_cpu()
+    need = ORACLE_BYTES[p["dim"]] * n
+    avail = mem_available_bytes()
+    if avail and need > 0.8 * avail:
+        print(json.dumps({"workload": name, "threads": threads, "skipped": "host memory"}), flush=True)
+        return
+    st = O.State(p, O.wrap(p, w["pos"]), w["vel"], w["phase"])
+    t0 = time.perf_counter()
+    st.step(steps)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"workload": name, "particles": n, "threads": threads, "cpu_model": model, "steps": steps,
+                      "substeps": int(st.clock.n_sub), "seconds": dt, "particle_steps_per_s": n * steps / dt,
+                      "particle_substeps_per_s": n * st.clock.n_sub / dt}), flush=True)
+
+
+def cpu_baselines(single_max):
+    """Every entry of CPU_PLAN on all of the host's threads, and the entries
+    up to single_max on one thread (the plain figure), each in a child
+    process that sets OMP_NUM_THREADS before the oracle loads."""
+    import subprocess
+    runs = [(k, None) for k in range(len(CPU_PLAN))] + [(k, 1) for k in range(min(single_max + 1, len(CPU_PLAN)))]
+    for k, threads in runs:
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-plan-leg", str(k)], env=env,
+                           capture_output=True, text=True)
+        sys.stdout.write(r.stdout)
+        sys.stdout.flush()
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr)
+            raise SystemExit(r.returncode)
+
+
 def served_leg(args, log_jobs=False):
     """Served form on the mixed droplet stream: the saturated job rate is taken
     from a probe batch that arrives all at once; the full stream then arrives
@@ -499,12 +552,23 @@ def main():
     ap.add_argument("--no-accel-check", action="store_true",
                     help="skip the single-evaluation acceleration check against the oracle")
     ap.add_argument("--copy-probe", action="store_true", help="1 GiB device copy (counter reference)")
+    ap.add_argument("--cpu-baselines", action="store_true",
+                    help="the oracle on the host's cores over the benchmark set (no GPU): one JSON line each")
+    ap.add_argument("--cpu-single-max", type=int, default=2,
+                    help="--cpu-baselines: also run the first entries up to this index on one thread")
+    ap.add_argument("--cpu-plan-leg", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--pmc-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the force-pass traffic line of --workload/--precision from rocprofv3 --pmc output")
     ap.add_argument("--trace-summary", metavar="DB", help="markdown table of a rocprofv3 kernel-trace database")
     ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
                     help="markdown table of pair-kernel utilisation from rocprofv3 --pmc output")
     args = ap.parse_args()
+    if args.cpu_plan_leg is not None:
+        cpu_plan_leg(args.cpu_plan_leg)
+        return
+    if args.cpu_baselines:
+        cpu_baselines(args.cpu_single_max)
+        return
     if args.copy_probe:
         copy_probe()
         return

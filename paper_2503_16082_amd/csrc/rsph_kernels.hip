@@ -219,6 +219,17 @@ __device__ __forceinline__ double rsqrt_r<double>(double x) { return rsqrt(x); }
 template <>
 __device__ __forceinline__ float rsqrt_r<float>(float x) { return rsqrtf(x); }
 
+// 1/r for a squared pair distance: in FP32 the hardware reciprocal square root
+// alone (within 1 ulp), without the scaling rsqrtf adds for denormal
+// arguments, which a pair distance never is (pairs closer than 1e-9 h are
+// flagged).  Squared gradient norms can be denormal and take rsqrt_r.
+template <typename R>
+__device__ __forceinline__ R rsqrt_dist(R r2);
+template <>
+__device__ __forceinline__ double rsqrt_dist<double>(double r2) { return rsqrt(r2); }
+template <>
+__device__ __forceinline__ float rsqrt_dist<float>(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
 // 1/x: in FP32 the hardware reciprocal (within 1 ulp; the arguments here are
 // densities and sums of them, never denormal), in FP64 the exact quotient
 template <typename R>
@@ -403,18 +414,26 @@ __device__ __forceinline__ T group_sum(T v)
 // stay antisymmetric.
 template <typename R>
 struct FromPressure {
-    R rho0[2], mass[2], inv_c0sq;
+    // scalars, not arrays: an array indexed by the phase is placed in LDS
+    R rho0_k, rho0_l, m_k, m_l, inv_c0sq;
     __device__ __forceinline__ explicit FromPressure(const SysConst& S)
+        : rho0_k((R)S.rho0[0]), rho0_l((R)S.rho0[1]), m_k((R)S.mphase[0]), m_l((R)S.mphase[1]),
+          inv_c0sq((R)S.inv_c0sq)
     {
-        for (int f = 0; f < 2; ++f) {
-            rho0[f] = (R)S.rho0[f];
-            mass[f] = (R)S.mphase[f];
-        }
-        inv_c0sq = (R)S.inv_c0sq;
     }
-    // density and mass of a particle of fluid ph (a wall's are never used)
-    __device__ __forceinline__ R rho(int ph, R p) const { return ((ph & 1) ? rho0[1] : rho0[0]) + p * inv_c0sq; }
-    __device__ __forceinline__ R m(int ph) const { return (ph & 1) ? mass[1] : mass[0]; }
+    // density and mass of a particle of fluid ph (a wall's are never used);
+    // the select is taken between values, not members (a select between the
+    // members' addresses made the compiler keep them in an LDS table)
+    __device__ __forceinline__ R rho(int ph, R p) const
+    {
+        const R a = rho0_l, b = rho0_k;
+        return ((ph & 1) ? a : b) + p * inv_c0sq;
+    }
+    __device__ __forceinline__ R m(int ph) const
+    {
+        const R a = m_l, b = m_k;
+        return (ph & 1) ? a : b;
+    }
     // {rho, V, p, 0}
     __device__ __forceinline__ Q4<R> operator()(int ph, R p) const
     {
@@ -1309,7 +1328,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const R inv_r = rsqrt_r<R>(r2);
+            const R inv_r = rsqrt_dist<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
             const Q4<R> vj = rj.q[1];
             const R Vj = vj.w;  // volume, stored beside the velocity
@@ -1447,7 +1466,7 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const R inv_r = rsqrt_r<R>(r2);
+            const R inv_r = rsqrt_dist<R>(r2);
             const Q4<R> Bj0 = rj.q[1];
             const Q4<R> Bj1 = D == 3 ? rj.q[D - 1] : Q4<R>{0, 0, 0, 0};
             const R Vj = D == 2 ? Bj0.z : Bj1.z;  // volume, stored beside B
@@ -1784,7 +1803,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const R inv_r = rsqrt_r<R>(r2);
+            const R inv_r = rsqrt_dist<R>(r2);
             const R Vj = PK ? fp.m(phj) * recip<R>(fp.rho(phj, rj.q[1].w)) : rj.q[1].y;
             const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * Vj * inv_r;
             gsum[0] += f * r[0];
@@ -1885,7 +1904,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const R inv_r = rsqrt_r<R>(r2);
+            const R inv_r = rsqrt_dist<R>(r2);
             const R rr = r2 * inv_r;
             const R dW = wendland_dw<R>(rr * inv_h, coef);
             const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
@@ -2155,7 +2174,7 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const R inv_r = rsqrt_r<R>(r2);
+            const R inv_r = rsqrt_dist<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
             const Q4<R> vj = rj.q[NR - 1];
             const int phj = Geo<R>::phase(gj);

@@ -86,6 +86,35 @@ def test_pmc_traffic_line(tmp_path, monkeypatch):
     assert bench.recorded_traffic("square_droplet_2d", "mixed") == 4000.0 * 1024 * 2.0 + 1000.0 * 1024
 
 
+def test_pmc_traffic_pairs_fetch_with_the_launches_that_write(tmp_path, monkeypatch):
+    # an idle substep launch still fetches its slot-only loads (here 1500 KiB,
+    # above a quarter of the largest) but writes nothing: it is left out
+    kern = "void rsph::k_force<float, 3, true, false>(rsph::DevArrays)"
+    f_csv, w_csv = tmp_path / "f.csv", tmp_path / "w.csv"
+    cf_csv, cw_csv = tmp_path / "cf.csv", tmp_path / "cw.csv"
+    write_counters(f_csv, kern, "FETCH_SIZE", [4000.0, 1500.0, 4000.0])
+    write_counters(w_csv, kern, "WRITE_SIZE", [1000.0, 0.0, 1000.0])
+    write_counters(cf_csv, "__amd_rocclr_copyBuffer", "FETCH_SIZE", [(1 << 20) / 2])
+    write_counters(cw_csv, "__amd_rocclr_copyBuffer", "WRITE_SIZE", [1 << 20])
+    traffic = tmp_path / "traffic.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(traffic))
+    args = types.SimpleNamespace(pmc_traffic=[str(f_csv), str(w_csv), str(cf_csv), str(cw_csv)],
+                                 workload="impact3d", precision="mixed")
+    bench.pmc_traffic(args)
+    line = traffic.read_text().split()
+    assert line[0] == "droplet_impact_3d" and float(line[3]) == 4000.0 * 1024 * 2.0
+
+
+def test_cpu_plan_leg_prints_a_baseline_line():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-plan-leg", "0"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    import json
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["particles"] == 2500 and d["steps"] == 200 and d["substeps"] >= 200
+    assert d["particle_steps_per_s"] > 0 and d["threads"] >= 1 and d["cpu_model"]
+
+
 def test_bench_line_keys_documented():
     # the keys the driver reads are produced by the default mode
     src = open(os.path.join(ROOT, "bench.py")).read()
