@@ -258,8 +258,8 @@ rsph_status rsph_read_particles(rsph_system* sys, int32_t field, int64_t n, doub
 /* Binning of the last rebuild (the cell-linked list behind the kernel's
  * compact support of section 5, cells of edge >= 2h): per particle (caller
  * order) its cell key cx + nx (cy + ny cz) and its rank in cell order (cells
- * ascending, then caller index ascending), into caller-owned host arrays of n
- * entries.  EINVAL if n differs from the particle count. */
+ * ascending, then x ascending, then caller index ascending), into caller-owned
+ * host arrays of n entries.  EINVAL if n differs from the particle count. */
 rsph_status rsph_read_binning(rsph_system* sys, int64_t n, uint32_t* key, int64_t* rank);
 
 /* Neighbour lists of the last rebuild in caller indices: every j != i with

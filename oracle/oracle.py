@@ -119,7 +119,7 @@ def lib():
         L.orc_cell_keys.restype = None
         L.orc_cell_keys.argtypes = [vp, i64, vp, vp]
         L.orc_bin.restype = None
-        L.orc_bin.argtypes = [vp, i64, vp, vp, vp]
+        L.orc_bin.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_neighbours_brute.restype = i64
         L.orc_neighbours_brute.argtypes = [vp, i64, vp, vp, vp, i64]
         L.orc_neighbours_cells.restype = i64
@@ -202,14 +202,17 @@ def cell_keys(p, pos):
     return key
 
 
-def bin_particles(p, key):
-    """Stable counting sort by cell key: returns (perm, cell_start)."""
+def bin_particles(p, key, pos):
+    """Counting sort by cell key, each cell ordered by (x, index): returns
+    (perm, cell_start)."""
     P = make_params(p)
     ok, nc = grid(p)
     key = np.ascontiguousarray(key, dtype=np.uint32)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    assert pos.shape == (key.shape[0], p["dim"])
     perm = np.zeros(key.shape[0], np.int64)
     cs = np.zeros(int(np.prod(nc)) + 1, np.int64)
-    lib().orc_bin(C.byref(P), key.shape[0], _ptr(key), _ptr(perm), _ptr(cs))
+    lib().orc_bin(C.byref(P), key.shape[0], _ptr(key), _ptr(pos), _ptr(perm), _ptr(cs))
     return perm, cs
 
 

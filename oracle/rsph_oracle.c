@@ -207,11 +207,14 @@ void orc_cell_keys(const orc_params* P, int64_t n, const double* pos, uint32_t* 
     }
 }
 
-/* Stable counting sort of particle indices by cell key (ties keep index order).
- * perm[k] is the index of the k-th particle in cell order; cell_start has
- * n_cells + 1 entries. */
-void orc_bin(const orc_params* P, int64_t n, const uint32_t* key, int64_t* perm,
-             int64_t* cell_start)
+/* Counting sort of particle indices by cell key, then each cell's members
+ * ordered by x coordinate, ties by index (an insertion sort per cell): the order
+ * (cell key, x, index).  The method fixes no order within a cell; this one lets
+ * a neighbour search cut a cell to an x range.  perm[k] is the index of the
+ * k-th particle in that order; cell_start has n_cells + 1 entries.  pos holds
+ * n points of dim coordinates. */
+void orc_bin(const orc_params* P, int64_t n, const uint32_t* key, const double* pos,
+             int64_t* perm, int64_t* cell_start)
 {
     int32_t nc[3];
     orc_grid(P, nc);
@@ -223,6 +226,20 @@ void orc_bin(const orc_params* P, int64_t n, const uint32_t* key, int64_t* perm,
     for (int64_t c = 0; c < ncells; ++c) fill[c] = cell_start[c];
     for (int64_t i = 0; i < n; ++i) perm[fill[key[i]]++] = i;
     free(fill);
+    int d = P->dim;
+    for (int64_t c = 0; c < ncells; ++c)
+        for (int64_t k = cell_start[c] + 1; k < cell_start[c + 1]; ++k) {
+            int64_t m = perm[k];
+            int64_t q = k;
+            while (q > cell_start[c]) {
+                int64_t o = perm[q - 1];
+                double xo = pos[o * d], xm = pos[m * d];
+                if (xo < xm || (xo == xm && o < m)) break;
+                perm[q] = o;
+                --q;
+            }
+            perm[q] = m;
+        }
 }
 
 /* Periodic minimum image of r_i - r_j along each axis, then |r_ij|^2 summed in
@@ -293,7 +310,7 @@ static void cells_build(const orc_params* P, int64_t n, const double* pos, cells
     C->cell_start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(C->ncells + 1));
     C->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     orc_cell_keys(P, n, pos, key);
-    orc_bin(P, n, key, C->perm, C->cell_start);
+    orc_bin(P, n, key, pos, C->perm, C->cell_start);
     free(key);
 }
 

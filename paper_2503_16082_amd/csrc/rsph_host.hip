@@ -673,10 +673,10 @@ DevArrays kernel_view(rsph_pool* P)
 {
     DevArrays A = P->A;
     A.work = P->timing ? P->work_dev : nullptr;
-    // the packed substep passes pay off in 3D (8.4M particles: force 2.81 ->
-    // 2.55 ms, continuity 2.43 -> 1.73 ms); in 2D they measured 2-2.4x
-    // slower per launch at 40,000 particles, so 2D keeps three records
-    A.packed = P->dim == 3 ? 1 : 0;
+    // the packed substep passes (8.4M particles in 3D: force 2.81 -> 2.55 ms,
+    // continuity 2.43 -> 1.73 ms; 40,000 in 2D: 0.6 % more particle-steps/s,
+    // a 256-system pool 1.8 %) whenever every system's fluid masses are uniform
+    A.packed = 1;
     A.walls = 0;
     // an idle substep launch over 8.4M slots fetched 0.5 GB of slot-only loads
     // and took 0.26 ms; small pools keep the loads ahead of the state check,

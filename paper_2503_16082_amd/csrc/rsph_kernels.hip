@@ -713,8 +713,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_small(DevArrays A, int64_t n
 }
 
 // Final, canonical order: within its cell a particle's rank is the number of
-// cell members with a smaller caller index (ids are unique), so the sorted
-// order is (cell, id) whatever order the atomics produced.  Each particle then
+// cell members before it in (x, caller index) order (ids are unique), so the
+// sorted order is (cell, x, id) whatever order the atomics produced; the
+// neighbour pass relies on each cell's members ascending in x.  Each particle then
 // moves its state from the snapshot into its sorted slot of the primary arrays
 // and writes its packed position record; the per-fluid |v| maxima of each 64
 // source slots go to the partials of the advection time step.  On grids
@@ -744,14 +745,20 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
         const SysConst& S = A.sc[c.s];
         const int64_t base = S.p_off - A.cell_start[S.c_off];
         const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
+        const double xme = x[0];
+        const double* xs = A.pos2[0];
+        auto before = [&](int32_t t) {
+            const double xt = xs[t];
+            return (int)(xt < xme || (xt == xme && A.id2[t] < me));
+        };
         int r = 0;
         // four members at a time, their loads in flight together
         int64_t k = b;
         for (; k + 4 <= e; k += 4) {
             const int32_t t0 = A.tmp[k], t1 = A.tmp[k + 1], t2 = A.tmp[k + 2], t3 = A.tmp[k + 3];
-            r += (A.id2[t0] < me) + (A.id2[t1] < me) + (A.id2[t2] < me) + (A.id2[t3] < me);
+            r += before(t0) + before(t1) + before(t2) + before(t3);
         }
-        for (; k < e; ++k) r += A.id2[A.tmp[k]] < me;
+        for (; k < e; ++k) r += before(A.tmp[k]);
         const int64_t d = b + r;
         A.perm[d] = (int32_t)i;
         double v2 = 0.0;
@@ -796,11 +803,24 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
 // predicate.  The three cells of
 // a stencil row are consecutive both in LDS and, unless the row wraps around
 // the periodic box, in the cell-sorted slots, so a row is scanned as one range.
+// The members of a cell ascend in x (the binning order), so a row's first and
+// last cells are cut to the x sub-bins that reach within the cut-off: each
+// staged cell holds, per edge of kXBins equal sub-bins, the first entry at or
+// past that edge, and the entries cut off lie beyond the cut-off in x alone.
 // Blocks whose union does not fit fall back to testing every candidate in FP64
 // from global memory; both paths produce the same list in the same order
 // (stencil cells in z, y, x order, slots ascending within a cell).
 constexpr int kStageCells = 128;
 constexpr int kStageCap = 2304;
+constexpr int kXBins = 8;
+
+// x edge s (0..kXBins) of the box-local x cell l: l w + s w / kXBins in FP32,
+// one rounding per operation, so the staging and the candidate loop compute
+// the same value
+__device__ __forceinline__ float xbin_edge(int l, int s, float w, float ws)
+{
+    return __fadd_rn(__fmul_rn((float)l, w), __fmul_rn((float)s, ws));
+}
 
 // The union is kept as two boxes: one for the particles in the cell row
 // (y, z) of the block's first particle, one for the rest.  A block that runs
@@ -813,6 +833,9 @@ struct Stage {
     float4 q[kStageCap];
     int32_t off[kStageCells + 1];  // LDS offset of each union cell (box 0's cells, then box 1's)
     int32_t gs[kStageCells];       // first global slot of each union cell
+    // per union cell and x edge s: the first entry whose x offset is at or past
+    // the edge (the cell's end if none)
+    uint16_t xb[kStageCells * (kXBins + 1)];
     int32_t lo[2][3], hi[2][3];    // per box: cell-coordinate bounds of its particles
     int32_t dims[2][3];            // per box: extent (cells)
     int32_t ubase[2];              // per box: its first union cell
@@ -877,16 +900,18 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
         nb[q] = ux[q] * uy[q] * uz[q];
     }
     const int ncu = nb[0] + nb[1];
-    const bool fits_cells = nb[0] > 0 && ncu <= kStageCells;
-    // per union cell: count and first slot (one thread per cell), then offsets
-    int cnt = 0, gs = 0;
+    // (the staged cell coordinate cx takes 23 bits)
+    const bool fits_cells = nb[0] > 0 && ncu <= kStageCells && S.ncell[0] < (1 << 23);
+    // per union cell (one thread each): its cell coordinates, count and first slot
+    int cnt = 0, gs = 0, lx = 0, cx = 0, cy = 0, cz = 0;
     if (fits_cells && t < ncu) {
         const int q = t >= nb[0];
         const int u = t - (q ? nb[0] : 0);
-        const int lx = u % ux[q], ly = (u / ux[q]) % uy[q], lz = u / (ux[q] * uy[q]);
-        const int cx = wrap_cell(L.lo[q][0] - 1 + lx, S.ncell[0]);
-        const int cy = wrap_cell(L.lo[q][1] - 1 + ly, S.ncell[1]);
-        const int cz = D == 3 ? wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]) : 0;
+        lx = u % ux[q];
+        const int ly = (u / ux[q]) % uy[q], lz = u / (ux[q] * uy[q]);
+        cx = wrap_cell(L.lo[q][0] - 1 + lx, S.ncell[0]);
+        cy = wrap_cell(L.lo[q][1] - 1 + ly, S.ncell[1]);
+        cz = D == 3 ? wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]) : 0;
         const int64_t gc = S.c_off + cx + (int64_t)S.ncell[0] * (cy + (int64_t)S.ncell[1] * cz);
         const int a0 = A.cell_start[gc];
         cnt = A.cell_start[gc + 1] - a0;
@@ -901,15 +926,22 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
     }
     if (lane == 63) L.wsum[wv] = x;
     __syncthreads();
-    const int before = wv == 0 ? 0 : L.wsum[0];
+    const int o0 = (wv == 0 ? 0 : L.wsum[0]) + x - cnt;
+    const int total = L.wsum[0] + L.wsum[1];
+    // lanes past the end of a range read up to 2 G - 1 entries beyond it
+    const bool ok = fits_cells && total <= kStageCap - 2 * kMaxLanes;
     if (fits_cells && t < ncu) {
-        L.off[t] = before + x - cnt;
+        L.off[t] = o0;
         L.gs[t] = gs;
     }
+    // each cell's entries get their slot and cell coordinates, which the
+    // entry pass below replaces by the staged record
+    if (ok && t < ncu)
+        for (int m = 0; m < cnt; ++m)
+            L.q[o0 + m] = float4{__int_as_float(gs + m), __int_as_float(lx | (cx << 8)), __int_as_float(cy),
+                                 __int_as_float(cz)};
     if (t == 0) {
-        const int total = L.wsum[0] + L.wsum[1];
-        // lanes past the end of a range read up to 2 G - 1 entries beyond it
-        L.ok = fits_cells && total <= kStageCap - 2 * kMaxLanes;
+        L.ok = ok;
         for (int q = 0; q < 2; ++q) {
             L.dims[q][0] = ux[q];
             L.dims[q][1] = uy[q];
@@ -921,34 +953,47 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
     }
     __syncthreads();
     if (!L.ok) return box;  // block-uniform
-    const int total = L.off[ncu];
     for (int k = t; k < total; k += kBlock) {
-        // union cell holding entry k: binary search over the offsets
-        int lo = 0, hi = ncu;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (L.off[mid] <= k) lo = mid;
-            else hi = mid;
-        }
-        const int q = lo >= nb[0];
-        const int u = lo - (q ? nb[0] : 0);
-        const int lx = u % ux[q], ly = (u / ux[q]) % uy[q], lz = u / (ux[q] * uy[q]);
-        const int cx = wrap_cell(L.lo[q][0] - 1 + lx, S.ncell[0]);
-        const int cy = wrap_cell(L.lo[q][1] - 1 + ly, S.ncell[1]);
-        const int64_t j = L.gs[lo] + (k - L.off[lo]);
+        const float4 dsc = L.q[k];
+        const int64_t j = __float_as_int(dsc.x);
+        const int lxk = __float_as_int(dsc.y) & 0xff, cxk = __float_as_int(dsc.y) >> 8;
         double xj[3];
         int phj;
         load_pos<D>(A, j, xj, &phj);
         float4 c4;
-        c4.x = (float)((double)lx * S.cell[0] + (xj[0] - (double)cx * S.cell[0]));
-        c4.y = (float)(xj[1] - (double)cy * S.cell[1]);
-        c4.z = 0.f;
-        if (D == 3) {
-            const int cz = wrap_cell(L.lo[q][2] - 1 + lz, S.ncell[2]);
-            c4.z = (float)(xj[2] - (double)cz * S.cell[2]);
-        }
-        c4.w = __int_as_float((lx << 2) | phj);
+        c4.x = (float)((double)lxk * S.cell[0] + (xj[0] - (double)cxk * S.cell[0]));
+        c4.y = (float)(xj[1] - (double)__float_as_int(dsc.z) * S.cell[1]);
+        c4.z = D == 3 ? (float)(xj[2] - (double)__float_as_int(dsc.w) * S.cell[2]) : 0.f;
+        c4.w = __int_as_float((lxk << 2) | phj);
         L.q[k] = c4;
+    }
+    __syncthreads();
+    // the sub-bin starts of each cell: a lower bound per x edge over the
+    // cell's entries, which ascend in x (branch-free, the searches of one cell
+    // interleaved)
+    if (t < ncu) {
+        const float w = (float)S.cell[0], ws = (float)(S.cell[0] / kXBins);
+        const int e = o0 + cnt;
+        float edge[kXBins + 1];
+        int at[kXBins + 1];
+#pragma unroll
+        for (int sb = 0; sb <= kXBins; ++sb) {
+            edge[sb] = xbin_edge(lx, sb, w, ws);
+            at[sb] = o0;
+        }
+        if (cnt > 0) {
+            int n = cnt;
+            while (n > 1) {
+                const int half = n >> 1;
+#pragma unroll
+                for (int sb = 0; sb <= kXBins; ++sb) at[sb] += L.q[at[sb] + half].x < edge[sb] ? half : 0;
+                n -= half;
+            }
+#pragma unroll
+            for (int sb = 0; sb <= kXBins; ++sb) at[sb] += L.q[at[sb]].x < edge[sb] ? 1 : 0;
+        }
+#pragma unroll
+        for (int sb = 0; sb <= kXBins; ++sb) L.xb[t * (kXBins + 1) + sb] = (uint16_t)min(at[sb], e);
     }
     __syncthreads();
     return box;
@@ -984,14 +1029,25 @@ __device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi,
 // Ordered append of the hits of G consecutive candidates tested by the lanes
 // of a group: the ballot keeps the list in candidate order.  entry() makes the
 // list entry of a hit.
+// The list of the block's 64 slots starts at out (block-uniform); entry e of
+// the slot in lane position sl lies e * kWave + sl words after it.
+struct ListOut {
+    uint32_t* base;
+    uint32_t sl;
+    __device__ __forceinline__ void put(int at, uint32_t v) const
+    {
+        *(uint32_t*)((char*)base + (((uint32_t)at * kWave + sl) << 2)) = v;
+    }
+};
+
 template <int G, typename Entry>
-__device__ __forceinline__ void append_hits(bool hit, Entry&& entry, int gshift, uint32_t below, uint32_t* out,
+__device__ __forceinline__ void append_hits(bool hit, Entry&& entry, int gshift, uint32_t below, const ListOut& out,
                                             int kmax, int& cnt)
 {
-    const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
+    const uint32_t gm = (uint32_t)(__builtin_amdgcn_ballot_w64(hit) >> gshift) & ((1u << G) - 1u);
     if (hit) {
         const int at = cnt + __popc(gm & below);
-        if (at < kmax) out[(int64_t)at * kWave] = entry();
+        if (at < kmax) out.put(at, entry());
     }
     cnt += __popc(gm);
 }
@@ -1007,7 +1063,7 @@ __device__ __forceinline__ uint32_t nbr_entry(int64_t j, int dx, int dy, int dz)
 // positions in global memory (blocks whose union does not fit in LDS).
 template <int D, int G>
 __device__ void scan_global(const DevArrays& A, const SysConst& S, int64_t i, const double* xi, const int* ci,
-                            int ph, bool live, int g, int gshift, uint32_t below, int64_t base, uint32_t* out,
+                            int ph, bool live, int g, int gshift, uint32_t below, int64_t base, const ListOut& out,
                             int& cnt)
 {
     const int zr = D == 3 ? 1 : 0;
@@ -1154,7 +1210,8 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     }
     const int box = stage_union<D>(A, S, L, base, live, ci, g);
     int cnt = 0;
-    uint32_t* out = A.nbr + ((i >> 6) * A.kmax) * kWave + (i & 63);
+    // the block's 64 slots are one 64-slot range: i >> 6 is the logical block
+    const ListOut out{A.nbr + (logical_block() * A.kmax) * kWave, (uint32_t)(i & 63)};
     if (L.ok) {  // block-uniform
         float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
         for (int a = 0; a < 3; ++a) {
@@ -1173,6 +1230,20 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
         const double band =
             fmax(1e-5, 3.0 * (ldexp((double)L.dims[box][0] * S.cell[0] * S.inv_h, -23) + ldexp(1.0, -22)));
         const float cut_hi = (float)(S.cut2 * (1.0 + band)), cut_lo = (float)(S.cut2 * (1.0 - band));
+        // The sub-bins of a row's first and last cells that the particle
+        // reaches: an entry left of the first cell's edge s_lo - 1 has x offset
+        // below xo - reach, one at or right of the last cell's edge s_hi above
+        // xo + reach.  With reach = sqrt(cut_hi) (1 + 2^-12) either has
+        // fl(ax^2) >= cut_hi, and so r^2 in FP32 as well (every rounding of a
+        // sum of squares is monotone): the FP32 test rejects it.
+        const float w = cellf[0], ws = (float)(S.cell[0] / kXBins);
+        const float reach = sqrtf(cut_hi) * (1.f + 0x1p-12f);
+        const float lo_x = xo - reach, hi_x = xo + reach;
+        int s_lo = 0, s_hi = 0;
+        for (int sb = 0; sb <= kXBins; ++sb) {
+            s_lo += xbin_edge(lx - 1, sb, w, ws) <= lo_x;
+            s_hi += xbin_edge(lx + 1, sb, w, ws) <= hi_x;
+        }
         const int zr = D == 3 ? 1 : 0;
         for (int dz = -zr; dz <= zr; ++dz) {
             const float rz0 = oi[2] - (float)dz * cellf[2];
@@ -1180,23 +1251,25 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
             for (int dy = -1; dy <= 1; ++dy) {
                 const float ry0 = oi[1] - (float)dy * cellf[1];
                 const double ky = image_offset(S, ci[1] + dy, 1);
-                // the row's three cells
+                // the row's three cells, the first and last cut to the
+                // particle's reach in x
                 int u0 = 0, rb = 0, re = 0;
                 bool contiguous = true;
                 if (live) {
                     u0 = L.ubase[box] + (lx - 1) + L.dims[box][0] * ((ly + dy) + L.dims[box][1] * (lz + dz));
-                    rb = L.off[u0];
-                    re = L.off[u0 + 3];
-                    contiguous = L.gs[u0 + 1] - L.gs[u0] == L.off[u0 + 1] - rb &&
+                    rb = s_lo == 0 ? L.off[u0] : (int)L.xb[u0 * (kXBins + 1) + s_lo - 1];
+                    re = s_hi > kXBins ? L.off[u0 + 3] : (int)L.xb[(u0 + 2) * (kXBins + 1) + s_hi];
+                    contiguous = L.gs[u0 + 1] - L.gs[u0] == L.off[u0 + 1] - L.off[u0] &&
                                  L.gs[u0 + 2] - L.gs[u0 + 1] == L.off[u0 + 2] - L.off[u0 + 1];
                 }
                 // a row that wraps around the box is scanned cell by cell
                 const int nseg = contiguous ? 1 : 3;
                 for (int sgm = 0; sgm < nseg; ++sgm) {
-                    const int kb = contiguous ? rb : L.off[u0 + sgm];
-                    const int ke = contiguous ? re : L.off[u0 + sgm + 1];
+                    const int kb = contiguous || sgm == 0 ? rb : L.off[u0 + sgm];
+                    const int ke = contiguous || sgm == 2 ? re : L.off[u0 + sgm + 1];
                     // slots fit in 32 bits (the slot capacity is checked on the host)
-                    const int jofs = L.gs[contiguous ? u0 : u0 + sgm] - kb;
+                    const int uc = contiguous ? u0 : u0 + sgm;
+                    const int jofs = L.gs[uc] - L.off[uc];
                     // two entries per lane and iteration; lanes past the range
                     // read entries beyond it (inside the staging array) and
                     // discard them

@@ -127,7 +127,7 @@ def test_binning_bit_exact(dim, precision):
     s.set_particles(pos, np.zeros_like(pos), phase)
     key, rank = s.binning()
     kref = O.cell_keys(p, pos)
-    perm, _ = O.bin_particles(p, kref)
+    perm, _ = O.bin_particles(p, kref, pos)
     rref = np.empty_like(perm)
     rref[perm] = np.arange(len(perm))
     assert np.array_equal(key, kref)

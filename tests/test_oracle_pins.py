@@ -158,11 +158,16 @@ def test_oblique_cut_off_pairs_follow_the_plain_sum(dim):
     assert 0 < inside < 12  # both sides of the cut-off occur
 
 
-def test_binning_is_stable_counting_sort():
-    p, pos = _hard_positions(2, 3)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_binning_orders_cells_then_x_then_index(dim):
+    """The binning order is (cell key, x, index): numpy's lexicographic sort.
+    The positions hold particles that share x (the cut-off pairs share y and
+    z, the face particles share x with other face particles in 2D and 3D)."""
+    p, pos = _hard_positions(dim, 3)
     key = O.cell_keys(p, pos)
-    perm, cs = O.bin_particles(p, key)
-    ref = np.lexsort((np.arange(len(key)), key))
+    perm, cs = O.bin_particles(p, key, pos)
+    ref = np.lexsort((np.arange(len(key)), pos[:, 0], key))
+    assert len(np.unique(pos[:, 0])) < len(pos)  # ties in x occur
     assert np.array_equal(perm, ref)
     assert np.array_equal(cs, np.searchsorted(np.sort(key), np.arange(len(cs)), side="left"))
 
