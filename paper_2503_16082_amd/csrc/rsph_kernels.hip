@@ -116,6 +116,24 @@ __device__ __forceinline__ void store_pos(const DevArrays& A, int64_t j, const d
     if constexpr (D == 2) ((double2*)A.xd)[j] = double2{x0, x1};
     else ((double4*)A.xd)[j] = double4{x0, x1, x[2], 0.0};
 }
+
+// FP64 position of slot j from its packed record, and its phase
+template <int D>
+__device__ __forceinline__ void load_pos(const DevArrays& A, int64_t j, double* x, int* ph = nullptr)
+{
+    double2 q;
+    if constexpr (D == 2) {
+        q = ((const double2*)A.xd)[j];
+        x[2] = 0.0;
+    } else {
+        q = ((const double2*)A.xd)[2 * j];
+        x[2] = A.xd[4 * j + 2];
+    }
+    x[0] = fabs(q.x);
+    x[1] = fabs(q.y);
+    if (ph) *ph = (signbit(q.x) ? 1 : 0) | (signbit(q.y) ? 2 : 0);
+}
+
 struct Pos3 {
     double x[3];
     int ph;
@@ -829,7 +847,7 @@ __device__ __forceinline__ float xbin_edge(int l, int s, float w, float ws)
 struct Stage {
     // x offset from its box's x origin (the lower corner of the box's first
     // x cell), y and z offsets from the candidate's own cell corner; w holds
-    // the bits of (box-local x cell << 2) | phase
+    // the bits of -(box-local x cell << 26) (mod 2^32)
     float4 q[kStageCap];
     int32_t off[kStageCells + 1];  // LDS offset of each union cell (box 0's cells, then box 1's)
     int32_t gs[kStageCells];       // first global slot of each union cell
@@ -845,23 +863,6 @@ struct Stage {
 };
 
 __device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
-
-// FP64 position of slot j from its packed record, and its phase
-template <int D>
-__device__ __forceinline__ void load_pos(const DevArrays& A, int64_t j, double* x, int* ph = nullptr)
-{
-    double2 q;
-    if constexpr (D == 2) {
-        q = ((const double2*)A.xd)[j];
-        x[2] = 0.0;
-    } else {
-        q = ((const double2*)A.xd)[2 * j];
-        x[2] = A.xd[4 * j + 2];
-    }
-    x[0] = fabs(q.x);
-    x[1] = fabs(q.y);
-    if (ph) *ph = (signbit(q.x) ? 1 : 0) | (signbit(q.y) ? 2 : 0);
-}
 
 // periodic image offset along axis a of the stencil cell c (unwrapped: one
 // cell either way of the particle's own)
@@ -958,13 +959,12 @@ __device__ __forceinline__ int stage_union(const DevArrays& A, const SysConst& S
         const int64_t j = __float_as_int(dsc.x);
         const int lxk = __float_as_int(dsc.y) & 0xff, cxk = __float_as_int(dsc.y) >> 8;
         double xj[3];
-        int phj;
-        load_pos<D>(A, j, xj, &phj);
+        load_pos<D>(A, j, xj);
         float4 c4;
         c4.x = (float)((double)lxk * S.cell[0] + (xj[0] - (double)cxk * S.cell[0]));
         c4.y = (float)(xj[1] - (double)__float_as_int(dsc.z) * S.cell[1]);
         c4.z = D == 3 ? (float)(xj[2] - (double)__float_as_int(dsc.w) * S.cell[2]) : 0.f;
-        c4.w = __int_as_float((lxk << 2) | phj);
+        c4.w = __uint_as_float(0u - ((uint32_t)lxk << 26));
         L.q[k] = c4;
     }
     __syncthreads();
@@ -1270,6 +1270,13 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                     // slots fit in 32 bits (the slot capacity is checked on the host)
                     const int uc = contiguous ? u0 : u0 + sgm;
                     const int jofs = L.gs[uc] - L.off[uc];
+                    const int kself = i32 - jofs;  // the particle itself: slot jofs + k == i
+                    // The list entry of candidate k is k + ebase + q.w (mod 2^32):
+                    // jofs + k is the slot, and (1 + lx) << 26 plus the staged
+                    // -(lx_j << 26) is (1 - dx) << 26 with dx = lx_j - lx in
+                    // {-1, 0, 1}, as nbr_entry lays the entry out.
+                    const uint32_t ebase = (uint32_t)jofs + ((uint32_t)(1 + lx) << 26) +
+                                           ((uint32_t)(1 - dy) << 28) + ((uint32_t)(1 - dz) << 30);
                     // two entries per lane and iteration; lanes past the range
                     // read entries beyond it (inside the staging array) and
                     // discard them
@@ -1278,14 +1285,15 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
                         const float ay = ry0 - q.y;
                         const float az = D == 3 ? rz0 - q.z : 0.f;
                         const float r2f = ax * ax + ay * ay + az * az;
-                        const int j = jofs + k;
+                        const uint32_t qw = __float_as_uint(q.w);
                         // (no short circuit: one mask, no branch)
-                        bool hit = (k < ke) & (j != i32) & (r2f < cut_hi);
-                        // the stencil x offset of the candidate's cell
-                        auto dx = [&] { return (__float_as_int(q.w) >> 2) - lx; };
-                        if (hit && r2f >= cut_lo)  // within the FP32 error of the cut-off
-                            hit = exact_r2<D>(A, xi, j, image_offset(S, ci[0] + dx(), 0), ky, kz) < S.cut2;
-                        append_hits<G>(hit, [&] { return nbr_entry(j, dx(), dy, dz); }, gshift, below, out, A.kmax,
+                        bool hit = (k < ke) & (k != kself) & (r2f < cut_hi);
+                        if (hit && r2f >= cut_lo) {  // within the FP32 error of the cut-off
+                            // the stencil x offset of the candidate's cell
+                            const int dx = (int)((0u - qw) - ((uint32_t)lx << 26)) >> 26;
+                            hit = exact_r2<D>(A, xi, jofs + k, image_offset(S, ci[0] + dx, 0), ky, kz) < S.cut2;
+                        }
+                        append_hits<G>(hit, [&] { return (uint32_t)k + ebase + qw; }, gshift, below, out, A.kmax,
                                        cnt);
                     };
                     for (int k0 = kb; k0 < ke; k0 += 2 * G) {
