@@ -223,9 +223,14 @@ struct Geo<float> {
                                const float* cellr, float* r)
     {
         (void)S;
-        r[0] = (gi.x - gj.x) + (float)((int)((e >> 26) & 3u) - 1) * cellr[0];
-        r[1] = (gi.y - gj.y) + (float)((int)((e >> 28) & 3u) - 1) * cellr[1];
-        if (D == 3) r[2] = (gi.z - gj.z) + (float)((int)(e >> 30) - 1) * cellr[2];
+        // each 2-bit field holds 1 - dx (dx the stencil offset, -1..1); with
+        // its low bit flipped it is dx in two's complement, which a signed
+        // bit-field extract returns: r = (o_i - o_j) - dx cell, the same
+        // single rounding as (o_i - o_j) + (1 - dx - 1) cell
+        const uint32_t f = e ^ 0x54000000u;
+        r[0] = (gi.x - gj.x) - (float)((int32_t)(f << 4) >> 30) * cellr[0];
+        r[1] = (gi.y - gj.y) - (float)((int32_t)(f << 2) >> 30) * cellr[1];
+        if (D == 3) r[2] = (gi.z - gj.z) - (float)((int32_t)f >> 30) * cellr[2];
         else r[2] = 0.0f;
     }
 };
