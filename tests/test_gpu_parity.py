@@ -150,6 +150,34 @@ def test_neighbour_sets_equal_brute_force(dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
+def test_neighbour_sets_on_large_compressed_lattices(dim):
+    """Many blocks whose stencil rows do not wrap, where the rows' first and
+    last cells are cut to each particle's reach in x: a jittered lattice
+    whose density varies by +-25 % along x and y (a periodic warp), against
+    the oracle's cell search (itself pinned to brute force)."""
+    n_side = 160 if dim == 2 else 36
+    dp = 1.0 / n_side
+    p = WL.base_params(dim, (1.0,) * dim, dp, (1.0, 1.0), (0.0, 0.0), 0.0, 1.0)
+    rng = np.random.default_rng(11)
+    pos = WL.lattice(dim, (n_side,) * dim, dp)
+    pos = pos + rng.uniform(-0.3 * dp, 0.3 * dp, pos.shape)
+    for a in range(2):
+        pos[:, a] = pos[:, a] + 0.25 / (2 * np.pi) * np.sin(2 * np.pi * pos[:, a])
+    pos = O.wrap(p, pos)
+    phase = (rng.uniform(size=len(pos)) < 0.5).astype(np.int32)
+    say(f"neighbours, warped lattice dim={dim} n={len(pos)}")
+    s = rsph.System(p)
+    s.set_particles(pos, np.zeros_like(pos), phase)
+    start, idx = s.neighbours(cap_per=300)
+    rs, ri = O.neighbours_cells(p, pos, cap_per=300)
+    assert np.array_equal(start, rs)
+    owner = np.repeat(np.arange(len(pos)), np.diff(start))
+    got = idx[:start[-1]][np.lexsort((idx[:start[-1]], owner))]
+    assert np.array_equal(got, ri[:rs[-1]])  # the oracle's lists ascend in j
+    s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("with_lattice", [False, True])
 def test_neighbour_predicate_at_oblique_cut_off_pairs(dim, with_lattice):
     """Pairs at (2h)^2 where a fused multiply-add would decide otherwise than
