@@ -523,6 +523,28 @@ def served(args):
     print(json.dumps(line), flush=True)
 
 
+def roofline_block(gbs, tflops, peak_tf, working_set):
+    """The roofline object of the force pass. Its bound is the unit whose peak the
+    launch uses the larger share of. For HBM that share is the algorithmic bytes
+    over the launch time, and it counts only when the working set exceeds the
+    Infinity Cache; otherwise the bytes come from on-chip caches. For the vector
+    ALU it is the counted operations over the launch time. Both shares are kept
+    beside the chosen one."""
+    hbm_frac = gbs / PEAK_HBM_GBS
+    alu_frac = tflops / peak_tf
+    exceeds = working_set > MALL_BYTES
+    if exceeds and hbm_frac >= alu_frac:
+        head = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": hbm_frac}
+    else:
+        head = {"bound": "alu", "achieved": tflops, "peak": peak_tf, "unit": "TFLOP/s", "frac": alu_frac}
+    head.update({
+        "hbm_achieved_gbs": gbs, "hbm_peak_gbs": PEAK_HBM_GBS, "hbm_frac": hbm_frac,
+        "alu_achieved_tflops": tflops, "alu_peak_tflops": peak_tf, "alu_frac": alu_frac,
+        "working_set_exceeds_mall": exceeds,
+    })
+    return head
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -672,6 +694,16 @@ def main():
     # the force pass streams from HBM only when the workload's working set
     # exceeds the Infinity Cache
     working_set = n * (1300 if dim == 3 else 800)
+    roof = roofline_block(gbs, tflops, peak_tf, working_set)
+    roof.update({
+        "kernel": "force pass (k_force)",
+        "traffic": recorded_traffic(w["name"], args.precision),
+        "algorithmic_bytes_per_launch": algo_bytes,
+        "ops_per_launch": ops,
+        "avg_launch_us": f_avg_ms * 1e3,
+        "launches": f_launch,
+        "empty_kernel_event_us": floor_ms * 1e3,
+    })
     line = {
         "metric": "particle-steps/s",
         "value": value,
@@ -701,24 +733,7 @@ def main():
         "momentum_drift": (float(np.linalg.norm(r["momentum"][1] - r["momentum"][0])
                                  / np.linalg.norm(r["momentum"][0]))
                            if args.workload == "impact3d" else None),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "force pass (k_force)",
-            "achieved": gbs,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": gbs / PEAK_HBM_GBS,
-            "traffic": recorded_traffic(w["name"], args.precision),
-            "algorithmic_bytes_per_launch": algo_bytes,
-            "avg_launch_us": f_avg_ms * 1e3,
-            "launches": f_launch,
-            "empty_kernel_event_us": floor_ms * 1e3,
-            "working_set_exceeds_mall": working_set > MALL_BYTES,
-            "alu_achieved_tflops": tflops,
-            "alu_peak_tflops": peak_tf,
-            "alu_frac": tflops / peak_tf,
-            "ops_per_launch": ops,
-        },
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     if srv is not None:

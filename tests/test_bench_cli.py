@@ -155,3 +155,18 @@ def test_impact_sample_is_chosen_from_the_inputs():
         np.abs(pos[:, 2] - w["pool_depth"]) < 3 * h)
     assert near.sum() >= 500
     assert np.array_equal(t, bench.input_sample(w, 1000))
+
+
+def test_roofline_bound_is_the_larger_share():
+    import bench
+    big, small = 10 * bench.MALL_BYTES, bench.MALL_BYTES // 2
+    # HBM share 0.5 against ALU 0.25, working set beyond the MALL: HBM-bound
+    r = bench.roofline_block(4000.0, 19.65, 78.6, big)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and abs(r["frac"] - 0.5) < 1e-12
+    # the same rates on a cache-resident working set: the HBM share is no evidence
+    r = bench.roofline_block(4000.0, 19.65, 78.6, small)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and abs(r["frac"] - 0.25) < 1e-12
+    # ALU share 0.31 against HBM 0.22: ALU-bound, both shares kept
+    r = bench.roofline_block(1767.0, 24.24, 78.6, big)
+    assert r["bound"] == "alu" and abs(r["frac"] - 24.24 / 78.6) < 1e-12
+    assert abs(r["hbm_frac"] - 1767.0 / 8000.0) < 1e-12 and r["working_set_exceeds_mall"]
