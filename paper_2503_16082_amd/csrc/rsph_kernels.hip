@@ -818,14 +818,14 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
 // Neighbour lists.  The candidates of one block's particles are staged in LDS:
 // the block's 64 slots lie in a few consecutive cells of one or two cell rows,
 // so the union of their 3^d stencils is at most two small boxes of cells whose
-// particles are copied once per block as FP32 offsets from their own cell
-// corner.  A candidate is tested in
-// FP32 on these split positions.  Candidates within a relative 1e-5 of the
-// cut-off (2h)^2 are decided on the spot by the exact FP64 predicate on the
-// stored positions, so the neighbour set is exactly the one of the FP64
-// predicate.  The three cells of
-// a stencil row are consecutive both in LDS and, unless the row wraps around
-// the periodic box, in the cell-sorted slots, so a row is scanned as one range.
+// particles are copied once per block as FP32 offsets (x from the box's x
+// origin, y and z from their own cell corner).  A candidate is tested in FP32
+// on these split positions.  Candidates within the FP32 error band of the
+// cut-off (2h)^2 (at least a relative 1e-5) are decided on the spot by the
+// exact FP64 predicate on the stored positions, so the neighbour set is
+// exactly the one of the FP64 predicate.  The three cells of a stencil row
+// are consecutive both in LDS and, unless the row wraps around the periodic
+// box, in the cell-sorted slots, so a row is scanned as one range.
 // The members of a cell ascend in x (the binning order), so a row's first and
 // last cells are cut to the x sub-bins that reach within the cut-off: each
 // staged cell holds, per edge of kXBins equal sub-bins, the first entry at or
