@@ -1215,8 +1215,10 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(DevArrays A)
     }
     const int box = stage_union<D>(A, S, L, base, live, ci, g);
     int cnt = 0;
-    // the block's 64 slots are one 64-slot range: i >> 6 is the logical block
-    const ListOut out{A.nbr + (logical_block() * A.kmax) * kWave, (uint32_t)(i & 63)};
+    // a wave's slots lie in one 64-slot range (64 / G of them), whose lists
+    // start at a wave-uniform address
+    const int64_t range = __builtin_amdgcn_readfirstlane((int)(i >> 6));
+    const ListOut out{A.nbr + (range * A.kmax) * kWave, (uint32_t)(i & 63)};
     if (L.ok) {  // block-uniform
         float oi[3] = {0.f, 0.f, 0.f}, cellf[3];
         for (int a = 0; a < 3; ++a) {
