@@ -768,11 +768,15 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
         const SysConst& S = A.sc[c.s];
         const int64_t base = S.p_off - A.cell_start[S.c_off];
         const int64_t b = base + A.cell_start[S.c_off + key], e = base + A.cell_start[S.c_off + key + 1];
-        const double xme = x[0];
+        // x compared through its bit pattern (x + 0 turns -0 into +0): for the
+        // wrapped x >= 0 this is the numeric order, and it stays a strict
+        // total order with the caller index whatever the values, so the ranks
+        // of a cell are always a permutation
         const double* xs = A.pos2[0];
+        const long long kme = __double_as_longlong(x[0] + 0.0);
         auto before = [&](int32_t t) {
-            const double xt = xs[t];
-            return (int)(xt < xme || (xt == xme && A.id2[t] < me));
+            const long long kt = __double_as_longlong(xs[t] + 0.0);
+            return (int)(kt < kme || (kt == kme && A.id2[t] < me));
         };
         int r = 0;
         // four members at a time, their loads in flight together
