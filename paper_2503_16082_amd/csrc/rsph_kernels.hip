@@ -1956,8 +1956,9 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     Q4<R>* vout = (Q4<R>*)A.vbuf[PK ? 1 : slot ^ 1];
     const FromPressure<R> fpr(S);
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
-    const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    const R c0 = (R)S.c0, inv_c0 = (R)S.inv_c0;
+    const R c0 = (R)S.c0, three_inv_c0 = (R)(3.0 * S.inv_c0);
+    // the kernel gradient's constants: 1 / (2h) and coef / h (W' below)
+    const R half_inv_h = (R)(0.5 * S.inv_h), coef_h = (R)(S.dw_coef * S.inv_h);
     const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
     const int phi = Geo<R>::phase(gi);
     Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
@@ -1966,6 +1967,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
         ti = PK ? fpr(phi, vi.w) : th[i];
     }
     const R m_i = PK ? fpr.m(phi) : R(0);  // packed: the fluid's particle mass
+    const R c0_rho_i = c0 * ti.x;
     const bool wall_i = phi == kWall;  // a wall particle has no rates and never moves
     const int cnt = (c.lane && !wall_i) ? cnt_i : 0;
     const bool surface = c.lane && !wall_i && (fl & kFlagNearInterface) && !(S.flags & kNoSurface);
@@ -1998,13 +2000,11 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_dist<R>(r2);
             const R rr = r2 * inv_r;
-            const R dW = wendland_dw<R>(rr * inv_h, coef);
-            const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+            // W'(r) = coef (r/h) (1 - r/(2h))^3
+            const R a = R(1) - rr * half_inv_h;
+            const R dW = coef_h * rr * (a * a * a);
             const Q4<R> vj = rj.q[NR - 1];
             const int phj = Geo<R>::phase(gj);
-            // Eq. 10 states, Eq. 11 limiter, Eqs. 8 and 12
-            const R UL = -(vi.x * e[0] + vi.y * e[1] + vi.z * e[2]);
-            R UR = -(vj.x * e[0] + vj.y * e[1] + vj.z * e[2]);
             // packed: rho_j from the pressure, V_j = m_j / rho_j folded into the
             // one reciprocal below
             R rhoR, pR, mR = m_i, Vj = 0;
@@ -2017,32 +2017,42 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
                 pR = rj.q[1].z;
                 Vj = rj.q[1].y;
             }
+            // Eq. 10 states (U = -v . e), Eq. 11 limiter, Eqs. 8 and 12:
+            // U_L - U_R = (v_j - v_i) . e
+            R dU;
             const bool wall_j = WL && phj == kWall;  // WL: the pool holds walls
             if (wall_j) {
                 // the wall's mirrored state: rho_R = rho_i, U_R = 2 U_w - U_L,
                 // p_R = p_i - rho_i g . r_ij, volume V_i
+                const R UL = -(vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
+                const R Uw = -(vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
+                dU = UL - (R(2) * Uw - UL);
                 rhoR = ti.x;
                 pR = ti.z - ti.x * (grav[0] * r[0] + grav[1] * r[1] + grav[2] * r[2]);
-                UR = R(2) * UR - UL;
                 mR = m_i;
                 Vj = ti.y;
+            } else {
+                dU = ((vj.x - vi.x) * r[0] + (vj.y - vi.y) * r[1] + (vj.z - vi.z) * r[2]) * inv_r;
             }
-            const R dU = UL - UR;
-            const R beta = fmin(R(3) * fmax(dU * inv_c0, R(0)), R(1));
-            const R num = ti.x * pR + rhoR * ti.z + beta * c0 * ti.x * rhoR * dU;
-            // P* V_j = num V_j / (rho_i + rho_R)
+            // beta = min(3 max(dU / c0, 0), 1)
+            const R beta = fmin(fmax(dU * three_inv_c0, R(0)), R(1));
+            const R num = ti.x * pR + rhoR * ti.z + (beta * c0_rho_i) * rhoR * dU;
+            // P* V_j = num V_j / (rho_i + rho_R), summed as P* V_j W' r_ij / r
             R fp;
+            R qv = 0;  // packed: V_j / (m_j (rho_i + rho_R))
             if constexpr (PK) {
-                const R q = recip<R>((ti.x + rhoR) * rhoR);  // V_j / (m_j (rho_i + rho_R))
-                Vj = mR * (ti.x + rhoR) * q;
-                fp = num * mR * q * dW;
+                qv = recip<R>((ti.x + rhoR) * rhoR);
+                fp = num * mR * qv * dW;
             } else {
                 fp = num * recip<R>(ti.x + rhoR) * dW * Vj;
             }
-            sp[0] += fp * e[0];
-            sp[1] += fp * e[1];
-            if (D == 3) sp[2] += fp * e[2];
+            const R fpr_ = fp * inv_r;
+            sp[0] += fpr_ * r[0];
+            sp[1] += fpr_ * r[1];
+            if (D == 3) sp[2] += fpr_ * r[2];
             if (!surface || wall_j) return;  // walls carry no colour
+            if constexpr (PK) Vj = mR * (ti.x + rhoR) * qv;
+            const R e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
             const bool same = Geo<R>::phase(gj) == phi;
             const Q4<R> cj = col[ent & kNbrIndexMask];
             const R gnj = (cj.x * cj.x + cj.y * cj.y + cj.z * cj.z) * cj.w;
