@@ -160,8 +160,9 @@ def test_couette_flow_settles_on_the_linear_profile(precision):
 
 @pytest.mark.xfail(reason="the run stops on the density health check (the air next to a water fragment in "
                           "tension empties) before t = 0.1 in the FP64 and in the mixed form alike, at a time "
-                          "that changes with the lattice jitter's seed: the method as read here, not a "
-                          "precision or parity matter", strict=False)
+                          "that changes with the lattice jitter's seed and with the rounding order of the "
+                          "pair sums (the flow amplifies differences exponentially): the method as read "
+                          "here, not a precision or parity matter", strict=False)
 def test_wall_impact_of_section_5_4_is_stable_to_t_0_1():
     w = WL.droplet_impact_wall_3d(n_per_unit=16)
     p = w["params"]
