@@ -68,16 +68,32 @@ FORCE_BYTES = {  # (per particle, per pair, per near-interface particle)
 }
 
 # Force-pass HBM traffic measured with rocprofv3 --pmc (FETCH_SIZE x 2 and
-# WRITE_SIZE x 1, the scales a 1 GiB device copy reads) for the kernel source
-# whose SHA-256 is recorded; any change of the kernel source voids the figure.
+# WRITE_SIZE x 1, the scales a 1 GiB device copy reads) for the kernel code
+# whose digest is recorded; any change of that code voids the figure.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_pass_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2503_16082_amd", "csrc", "rsph_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_16082_amd", "csrc", f)
+                  for f in ("rsph_kernels.hip", "rsph_internal.h")]
+
+
+def kernel_digest():
+    """SHA-256 of the device code's sources (the kernels and the layout header
+    they include) with comments and blank lines removed, so that a change of
+    wording alone keeps a measurement (the sources hold no string that a
+    comment marker could occur in, other than static_assert messages)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        src = open(path).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(l.rstrip() for l in src.splitlines() if l.strip()).encode())
+    return h.hexdigest()
 
 
 def recorded_traffic(workload, form):
-    import hashlib
     try:
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = kernel_digest()
         for line in open(TRAFFIC_FILE):
             f = line.split()
             if len(f) == 5 and f[0] == workload and f[1] == form and f[2] == sha:
@@ -131,7 +147,6 @@ def active_mean(v):
 
 
 def pmc_traffic(args):
-    import hashlib
     f_csv, w_csv, cf_csv, cw_csv = args.pmc_traffic
     dim = 2 if args.workload in ("square2d", "droplet2d") else 3
     # the force pass in either record form (k_force<R, D> or k_force<R, D, packed>)
@@ -155,7 +170,7 @@ def pmc_traffic(args):
     fetch_b = fetch * 1024.0 * f_scale
     write_b = write * 1024.0 * w_scale
     name = workload(args.workload)["name"]
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    sha = kernel_digest()
     lines = []
     if os.path.exists(TRAFFIC_FILE):
         lines = [l for l in open(TRAFFIC_FILE).read().splitlines()

@@ -1038,8 +1038,9 @@ __device__ __forceinline__ double exact_r2(const DevArrays& A, const double* xi,
 // Ordered append of the hits of G consecutive candidates tested by the lanes
 // of a group: the ballot keeps the list in candidate order.  entry() makes the
 // list entry of a hit.
-// The list of the block's 64 slots starts at out (block-uniform); entry e of
-// the slot in lane position sl lies e * kWave + sl words after it.
+// The lists of a 64-slot range start at base (the same for every lane of a
+// wave); entry e of the slot in lane position sl lies e * kWave + sl words
+// after it.
 struct ListOut {
     uint32_t* base;
     uint32_t sl;

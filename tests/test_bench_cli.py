@@ -1,7 +1,6 @@
 """bench.py without a GPU: the single-GPU contract, and the profiling utilities
 that turn rocprofv3 output into the summaries and the traffic figure."""
 import csv
-import hashlib
 import os
 import sqlite3
 import subprocess
@@ -79,8 +78,7 @@ def test_pmc_traffic_line(tmp_path, monkeypatch):
     assert "other_workload mixed sha 3 4" in lines
     mine = [l.split() for l in lines if l.startswith("square_droplet_2d mixed")]
     assert len(mine) == 1
-    sha = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()
-    assert mine[0][2] == sha
+    assert mine[0][2] == bench.kernel_digest()
     assert float(mine[0][3]) == 4000.0 * 1024 * 2.0   # fetch scaled by the copy's factor 2
     assert float(mine[0][4]) == 1000.0 * 1024 * 1.0
     assert bench.recorded_traffic("square_droplet_2d", "mixed") == 4000.0 * 1024 * 2.0 + 1000.0 * 1024
@@ -170,3 +168,20 @@ def test_roofline_bound_is_the_larger_share():
     r = bench.roofline_block(1767.0, 24.24, 78.6, big)
     assert r["bound"] == "alu" and abs(r["frac"] - 24.24 / 78.6) < 1e-12
     assert abs(r["hbm_frac"] - 1767.0 / 8000.0) < 1e-12 and r["working_set_exceeds_mall"]
+
+
+def test_kernel_digest_ignores_comments_only(tmp_path, monkeypatch):
+    import bench
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.h"
+    a.write_text("// one wording\nint f(int x) { return x + 1; }  // trailing\n/* block\n comment */\n")
+    b.write_text("constexpr int k = 4;\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(a), str(b)])
+    d0 = bench.kernel_digest()
+    a.write_text("// another wording\n\nint f(int x) { return x + 1; }\n")
+    assert bench.kernel_digest() == d0
+    a.write_text("int f(int x) { return x + 2; }\n")
+    assert bench.kernel_digest() != d0
+    a.write_text("int f(int x) { return x + 1; }\n")
+    b.write_text("constexpr int k = 8;\n")
+    assert bench.kernel_digest() != d0
