@@ -695,16 +695,26 @@ def main():
         except Exception as e:  # the oracle is a checker, not the product
             log(f"accel error check skipped: {e}")
 
+    # the served leg and the CPU baseline are reported beside the measured
+    # value: an error in either is recorded in the line, which is still printed
     srv = None
     if not args.no_served:
-        srv = served_leg(args)
-        log(f"served: {srv['particle_steps_per_s']:.3e} particle-steps/s, p50 {srv['step_latency_p50_ms']:.2f} ms, "
-            f"p99 {srv['step_latency_p99_ms']:.2f} ms per step")
+        try:
+            srv = served_leg(args)
+            log(f"served: {srv['particle_steps_per_s']:.3e} particle-steps/s, p50 {srv['step_latency_p50_ms']:.2f} "
+                f"ms, p99 {srv['step_latency_p99_ms']:.2f} ms per step")
+        except Exception as e:
+            extra["served_error"] = f"{type(e).__name__}: {e}"
+            log(f"served leg failed: {e}")
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_seconds)
-        log(f"cpu baseline {cpu}")
+        try:
+            cpu = cpu_baseline(w, args.cpu_seconds)
+            log(f"cpu baseline {cpu}")
+        except Exception as e:
+            extra["cpu_baseline_error"] = f"{type(e).__name__}: {e}"
+            log(f"cpu baseline failed: {e}")
 
     # the force pass streams from HBM only when the workload's working set
     # exceeds the Infinity Cache
