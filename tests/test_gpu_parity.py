@@ -136,10 +136,11 @@ def test_binning_bit_exact(dim, precision):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_neighbour_sets_equal_brute_force(dim):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neighbour_sets_equal_brute_force(dim, precision):
     p, pos, phase = hard_state(dim, 5)
-    say(f"neighbours dim={dim} n={len(pos)}")
-    s = rsph.System(p)
+    say(f"neighbours dim={dim} precision={precision} n={len(pos)}")
+    s = rsph.System(p, precision=precision)
     s.set_particles(pos, np.zeros_like(pos), phase)
     start, idx = s.neighbours()
     bs, bi = O.neighbours_brute(p, pos, cap_per=400)
@@ -150,7 +151,8 @@ def test_neighbour_sets_equal_brute_force(dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_neighbour_sets_on_large_compressed_lattices(dim):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neighbour_sets_on_large_compressed_lattices(dim, precision):
     """Many blocks whose stencil rows do not wrap, where the rows' first and
     last cells are cut to each particle's reach in x: a jittered lattice
     whose density varies by +-25 % along x and y (a periodic warp), against
@@ -165,8 +167,8 @@ def test_neighbour_sets_on_large_compressed_lattices(dim):
         pos[:, a] = pos[:, a] + 0.25 / (2 * np.pi) * np.sin(2 * np.pi * pos[:, a])
     pos = O.wrap(p, pos)
     phase = (rng.uniform(size=len(pos)) < 0.5).astype(np.int32)
-    say(f"neighbours, warped lattice dim={dim} n={len(pos)}")
-    s = rsph.System(p)
+    say(f"neighbours, warped lattice dim={dim} precision={precision} n={len(pos)}")
+    s = rsph.System(p, precision=precision)
     s.set_particles(pos, np.zeros_like(pos), phase)
     start, idx = s.neighbours(cap_per=300)
     rs, ri = O.neighbours_cells(p, pos, cap_per=300)
