@@ -114,7 +114,7 @@ def test_cpu_plan_leg_prints_a_baseline_line():
 
 
 def test_bench_line_keys_documented():
-    # the keys the driver reads are produced by the default mode
+    # the keys of the benchmark line are produced by the default mode
     src = open(os.path.join(ROOT, "bench.py")).read()
     for key in ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
                 "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"]:
