@@ -1861,6 +1861,9 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
         if (c0.s < 0) return;
         colour_snapshot<G>(A, c0, A.sd[c0.s]);
         if (!substep_on(A.sd[c0.s], A.mode)) return;
+        // a wave without interface particles (most of a large pool's) exits
+        // before any other load
+        if (!__any(c0.lane && (A.flags[i] & kFlagInterface))) return;
     }
     // loads that need only the slot, issued together
     const Q4<R>* geo = (const Q4<R>*)A.geo;
