@@ -350,6 +350,8 @@ size_t plan_arrays(Mem& M, int dim, int precision, DevArrays& A, int32_t*& mask,
         A.th[k] = M.template take<char>(Pc * r4);
         A.bm[k] = M.template take<char>(Pc * r4);
     }
+    A.bs = M.template take<char>(Pc * (r4 / 4));
+    A.bt = M.template take<char>(Pc * r4);
     A.col = M.template take<char>(Pc * r4);
     A.av = M.template take<char>(Pc * r4);
     A.flags = M.template take<uint8_t>(Pc);

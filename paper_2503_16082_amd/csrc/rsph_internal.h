@@ -194,7 +194,12 @@ struct DevArrays {
     void* th[2];   // {rho, V, p, 0}, substep parity
     void* col;     // {grad C, 1/|grad C|}
     void* av;      // viscous acceleration
-    void* bm[2];   // correction matrix, 6 unique entries
+    // the shift pass's records (Eq. 14), written by the advection pass:
+    // bm[0] {frozen offsets, V B entries}, bm[1] {V B entries} (3D), bs the
+    // last V B entry, bt the particle's own term B_i sum_j W'_ij V_j r_ij / r
+    void* bm[2];
+    void* bs;
+    void* bt;
     uint8_t* flags;
     uint32_t* nbr;
     int32_t* ncount;

@@ -1399,6 +1399,7 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     R av[3] = {0, 0, 0};
     R M[6] = {0, 0, 0, 0, 0, 0};  // 00 01 02 11 12 22
+    R u[3] = {0, 0, 0};           // sum_j W'_ij V_j r_ij / r, for the shift's B_i term
     int near = 0;
     Q4<R> gi{0, 0, 0, 0}, vi{0, 0, 0, 0};
     int cnt = 0, phi = 0;
@@ -1435,6 +1436,9 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             av[1] += f * (vi.y - vj.y);
             if (D == 3) av[2] += f * (vi.z - vj.z);
             const R gg = dW * Vj * inv_r;
+            u[0] += gg * r[0];
+            u[1] += gg * r[1];
+            if (D == 3) u[2] += gg * r[2];
             M[0] += gg * r[0] * r[0];
             M[1] += gg * r[0] * r[1];
             M[3] += gg * r[1] * r[1];
@@ -1445,7 +1449,10 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             }
             near |= Geo<R>::interface(gj);
         });
-    for (int a = 0; a < D; ++a) av[a] = group_sum<G>(av[a]);
+    for (int a = 0; a < D; ++a) {
+        av[a] = group_sum<G>(av[a]);
+        u[a] = group_sum<G>(u[a]);
+    }
     M[0] = group_sum<G>(M[0]);
     M[1] = group_sum<G>(M[1]);
     M[3] = group_sum<G>(M[3]);
@@ -1495,11 +1502,27 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
             B[1] = B[2] = B[4] = R(0);
         }
     }
-    // the volume rides in a spare component of the B records read by the shift
-    // pass (B02 = 0 in 2D)
+    // the shift pass's records: sum_j (B_i + B_j) W'_ij V_j r_ij / r splits into
+    // B_i u_i, this particle's own term, and sum_j W'_ij (V_j B_j) r_ij / r, which
+    // takes V B of each neighbour beside its frozen offsets: 9 values in 3D
+    // (two 16-byte records and one scalar), 5 in 2D (one record and a scalar)
     const R Vi = th[i].y;
-    ((Q4<R>*)A.bm[0])[i] = Q4<R>{B[0], B[1], D == 2 ? Vi : B[2], B[3]};
-    ((Q4<R>*)A.bm[1])[i] = Q4<R>{B[4], B[5], D == 3 ? Vi : (R)0, (R)0};
+    R VB[6];
+    for (int q = 0; q < 6; ++q) VB[q] = Vi * B[q];
+    Q4<R> t4;
+    t4.x = B[0] * u[0] + B[1] * u[1] + B[2] * u[2];
+    t4.y = B[1] * u[0] + B[3] * u[1] + B[4] * u[2];
+    t4.z = B[2] * u[0] + B[4] * u[1] + B[5] * u[2];
+    t4.w = (R)0;
+    ((Q4<R>*)A.bt)[i] = t4;
+    if (D == 3) {
+        ((Q4<R>*)A.bm[0])[i] = Q4<R>{gi_i.x, gi_i.y, gi_i.z, VB[0]};
+        ((Q4<R>*)A.bm[1])[i] = Q4<R>{VB[1], VB[2], VB[3], VB[4]};
+        ((R*)A.bs)[i] = VB[5];
+    } else {
+        ((Q4<R>*)A.bm[0])[i] = Q4<R>{gi_i.x, gi_i.y, VB[0], VB[1]};
+        ((R*)A.bs)[i] = VB[3];
+    }
     A.flags[i] = (A.flags[i] & kFlagInterface) | (near ? kFlagNearInterface : 0);
     if (A.mode == 1) {
         for (int a = 0; a < 3; ++a) A.r_accv[3 * i + a] = a < D ? (double)(&a4.x)[a] : 0.0;
@@ -1515,6 +1538,12 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
 // half-step of substep 0 (density, pressure by Eq. 3, position)
 // ---------------------------------------------------------------------------
 
+template <typename R>
+struct ShiftRec {
+    Q4<R> q0, q1;  // {offsets, V B 00} and {V B 01 02 11 12} (3D); {offsets, V B 00 01} (2D)
+    R z;           // V B 22 (3D), V B 11 (2D)
+};
+
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
 {
@@ -1523,14 +1552,13 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
     const int64_t i = group_slot<G>(g);
     if (i >= A.P) return;
     // loads that need only the slot, issued together
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[1];
     const Q4<R>* b0 = (const Q4<R>*)A.bm[0];
     const Q4<R>* b1 = (const Q4<R>*)A.bm[1];
+    const R* bz = (const R*)A.bs;
     NbrList<G, PassChunk<R, D, Pass::Shift>::N> nl;
     nl.start(A, i, g);
-    const Q4<R> gi_i = geo[i], b0_i = b0[i];
-    const Q4<R> b1_i = D == 3 ? b1[i] : Q4<R>{0, 0, 0, 0};
+    const Q4<R> gi_i = b0[i], t_i = ((const Q4<R>*)A.bt)[i];
     const int cnt_i = A.ncount[i];
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
@@ -1539,44 +1567,43 @@ __global__ __launch_bounds__(kBlock) void k_shift(DevArrays A)
     const SysConst& S = A.sc[c.s];
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    Q4<R> gi{0, 0, 0, 0}, Bi0{0, 0, 0, 0}, Bi1{0, 0, 0, 0};
+    Q4<R> gi{0, 0, 0, 0};
     int cnt = 0;
     if (c.lane) {
         gi = gi_i;
-        Bi0 = b0_i;
-        Bi1 = b1_i;
         cnt = cnt_i;
     }
     R s[3] = {0, 0, 0};
     nl.run(
         g, cnt,
         [&](uint32_t j) {
-            if constexpr (D == 3) return Recs<R, 3>{{geo[j], b0[j], b1[j]}};
-            else return Recs<R, 2>{{geo[j], b0[j]}};
+            ShiftRec<R> q;
+            q.q0 = b0[j];
+            q.q1 = D == 3 ? b1[j] : Q4<R>{0, 0, 0, 0};
+            q.z = bz[j];
+            return q;
         },
-        [&](uint32_t ent, const Recs<R, D>& rj) {
-            const Q4<R> gj = rj.q[0];
+        [&](uint32_t ent, const ShiftRec<R>& rj) {
             R r[3];
-            Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
+            Geo<R>::template rij<D>(gi, rj.q0, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_dist<R>(r2);
-            const Q4<R> Bj0 = rj.q[1];
-            const Q4<R> Bj1 = D == 3 ? rj.q[D - 1] : Q4<R>{0, 0, 0, 0};
-            const R Vj = D == 2 ? Bj0.z : Bj1.z;  // volume, stored beside B
-            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * Vj * inv_r;  // dW V_j / r
-            // (B_i + B_j) r_ij, symmetric storage 00 01 02 11 12 22
-            const R m00 = Bi0.x + Bj0.x, m01 = Bi0.y + Bj0.y, m11 = Bi0.w + Bj0.w;
+            const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * inv_r;  // dW / r
+            // (V_j B_j) r_ij, symmetric storage 00 01 02 11 12 22
             if (D == 2) {
+                const R m00 = rj.q0.z, m01 = rj.q0.w, m11 = rj.z;
                 s[0] += f * (m00 * r[0] + m01 * r[1]);
                 s[1] += f * (m01 * r[0] + m11 * r[1]);
             } else {
-                const R m02 = Bi0.z + Bj0.z, m12 = Bi1.x + Bj1.x, m22 = Bi1.y + Bj1.y;
+                const R m00 = rj.q0.w, m01 = rj.q1.x, m02 = rj.q1.y, m11 = rj.q1.z, m12 = rj.q1.w, m22 = rj.z;
                 s[0] += f * (m00 * r[0] + m01 * r[1] + m02 * r[2]);
                 s[1] += f * (m01 * r[0] + m11 * r[1] + m12 * r[2]);
                 s[2] += f * (m02 * r[0] + m12 * r[1] + m22 * r[2]);
             }
         });
-    for (int a = 0; a < D; ++a) s[a] = group_sum<G>(s[a]);
+    s[0] = t_i.x + group_sum<G>(s[0]);
+    s[1] = t_i.y + group_sum<G>(s[1]);
+    if (D == 3) s[2] = t_i.z + group_sum<G>(s[2]);
     if (!c.lane || g != 0) return;
     const int ph = A.phase[i];
     const bool wall = ph == kWall;
