@@ -159,9 +159,31 @@ __device__ __forceinline__ double wendland_w(double q, double alpha)
 // ---------------------------------------------------------------------------
 // frozen geometry records (phase 0, 1: the fluids; 2: a wall particle)
 //   FP64: {x, y, z, phase + 4 * interface}
-//   mixed: {x - cx*cell, y - cy*cell, z - cz*cell,
-//           bits(cx | cy<<9 | cz<<18 | interface<<27 | phase<<28)}
+//   mixed: the offsets from the cell corner, |x - cx*cell|, |y - cy*cell|,
+//          |z - cz*cell| (z: 0 in 2D), whose sign bits, free since an offset
+//          is never negative, carry phase bit 0, phase bit 1 and the
+//          interface bit; 12 bytes in 3D, a 16-byte record in 2D
 // ---------------------------------------------------------------------------
+
+struct F3 {
+    float x, y, z;
+};
+
+template <typename R, int D>
+struct GeoT {
+    using T = Q4<R>;
+};
+template <>
+struct GeoT<float, 3> {
+    using T = F3;
+};
+
+// one neighbour's frozen-geometry record and N further 16-byte records
+template <typename GT, typename R, int N>
+struct GRecs {
+    GT g;
+    Q4<R> q[N];
+};
 
 template <typename R>
 struct Geo;
@@ -169,17 +191,19 @@ struct Geo;
 template <>
 struct Geo<double> {
     // w = phase + 4 * (particle has a neighbour of the other fluid)
-    __device__ static Q4<double> make(const double* x, int ph, bool iface, const SysConst& S, const int* c)
+    template <int D>
+    __device__ static void store(void* geo, int64_t i, const double* x, int ph, bool iface, const SysConst& S,
+                                 const int* c)
     {
         (void)S;
         (void)c;
-        return Q4<double>{x[0], x[1], x[2], (double)(ph + (iface ? 4 : 0))};
+        ((Q4<double>*)geo)[i] = Q4<double>{x[0], x[1], x[2], (double)(ph + (iface ? 4 : 0))};
     }
     __device__ static int phase(const Q4<double>& g) { return (int)g.w & 3; }
     __device__ static bool interface(const Q4<double>& g) { return ((int)g.w >> 2) != 0; }
-    template <int D>
-    __device__ static void rij(const Q4<double>& gi, const Q4<double>& gj, uint32_t e, const SysConst& S,
-                               const double* cellr, double* r)
+    template <int D, typename GI, typename GJ>
+    __device__ static void rij(const GI& gi, const GJ& gj, uint32_t e, const SysConst& S, const double* cellr,
+                               double* r)
     {
         (void)e;
         (void)cellr;
@@ -204,23 +228,34 @@ struct Geo<double> {
 
 template <>
 struct Geo<float> {
-    // tag: cell x, y, z in 9 bits each, bit 27 = particle has a neighbour of
-    // the other fluid, bits 28-29 = phase
-    __device__ static Q4<float> make(const double* x, int ph, bool iface, const SysConst& S, const int* c)
+    template <int D>
+    __device__ static void store(void* geo, int64_t i, const double* x, int ph, bool iface, const SysConst& S,
+                                 const int* c)
     {
         float o[3];
-        for (int a = 0; a < 3; ++a) o[a] = (float)(x[a] - (double)c[a] * S.cell[a]);
-        uint32_t tag = (uint32_t)c[0] | ((uint32_t)c[1] << 9) | ((uint32_t)c[2] << 18) |
-                       ((uint32_t)(iface ? 1 : 0) << 27) | ((uint32_t)ph << 28);
-        return Q4<float>{o[0], o[1], o[2], __uint_as_float(tag)};
+        // an offset is x - c cell >= 0 up to the rounding of the cell index
+        // (below one ulp of x): its magnitude is kept, its sign bit set free
+        for (int a = 0; a < 3; ++a) o[a] = fabsf((float)(x[a] - (double)c[a] * S.cell[a]));
+        const bool bit[3] = {(ph & 1) != 0, (ph & 2) != 0, iface};
+        for (int a = 0; a < 3; ++a) o[a] = bit[a] ? -o[a] : o[a];
+        if constexpr (D == 3) ((F3*)geo)[i] = F3{o[0], o[1], o[2]};
+        else ((Q4<float>*)geo)[i] = Q4<float>{o[0], o[1], o[2], 0.f};
     }
-    __device__ static int phase(const Q4<float>& g) { return (int)((__float_as_uint(g.w) >> 28) & 3u); }
-    __device__ static bool interface(const Q4<float>& g) { return ((__float_as_uint(g.w) >> 27) & 1u) != 0; }
+    template <typename GT>
+    __device__ static int phase(const GT& g)
+    {
+        return (int)((__float_as_uint(g.x) >> 31) | ((__float_as_uint(g.y) >> 30) & 2u));
+    }
+    template <typename GT>
+    __device__ static bool interface(const GT& g)
+    {
+        return (__float_as_uint(g.z) >> 31) != 0;
+    }
     // r_ij = (o_i - o_j) + (c_i - c_j) cell, the cell differences (periodic
     // wrap included) taken from the list entry e
-    template <int D>
-    __device__ static void rij(const Q4<float>& gi, const Q4<float>& gj, uint32_t e, const SysConst& S,
-                               const float* cellr, float* r)
+    template <int D, typename GI, typename GJ>
+    __device__ static void rij(const GI& gi, const GJ& gj, uint32_t e, const SysConst& S, const float* cellr,
+                               float* r)
     {
         (void)S;
         // each 2-bit field holds 1 - dx (dx the stencil offset, -1..1); with
@@ -228,9 +263,9 @@ struct Geo<float> {
         // bit-field extract returns: r = (o_i - o_j) - dx cell, the same
         // single rounding as (o_i - o_j) + (1 - dx - 1) cell
         const uint32_t f = e ^ 0x54000000u;
-        r[0] = (gi.x - gj.x) - (float)((int32_t)(f << 4) >> 30) * cellr[0];
-        r[1] = (gi.y - gj.y) - (float)((int32_t)(f << 2) >> 30) * cellr[1];
-        if (D == 3) r[2] = (gi.z - gj.z) - (float)((int32_t)f >> 30) * cellr[2];
+        r[0] = (fabsf(gi.x) - fabsf(gj.x)) - (float)((int32_t)(f << 4) >> 30) * cellr[0];
+        r[1] = (fabsf(gi.y) - fabsf(gj.y)) - (float)((int32_t)(f << 2) >> 30) * cellr[1];
+        if (D == 3) r[2] = (fabsf(gi.z) - fabsf(gj.z)) - (float)((int32_t)f >> 30) * cellr[2];
         else r[2] = 0.0f;
     }
 };
@@ -1165,7 +1200,7 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
     const bool wall = ph == kWall;
     const bool iface = cross && !wall;
     A.flags[i] = iface ? kFlagInterface : 0;
-    ((Q4<R>*)A.geo)[i] = Geo<R>::make(xi, ph, iface, S, ci);
+    Geo<R>::template store<D>(A.geo, i, xi, ph, iface, S, ci);
     const double sigma = S.w0 + wsum;
     double rho = A.rho[i];
     const double mass = A.mass[i];
@@ -1379,12 +1414,14 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     const int64_t i = group_slot<G>(g);
     if (i >= A.P) return;
     // loads that need only the slot, issued together
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    using GT = typename GeoT<R, D>::T;
+    const GT* geo = (const GT*)A.geo;
     const Q4<R>* th = (const Q4<R>*)A.th[1];
     const Q4<R>* vb = (const Q4<R>*)A.vbuf[0];
     NbrList<G, PassChunk<R, D, Pass::Advection>::N> nl;
     nl.start(A, i, g);
-    const Q4<R> gi_i = geo[i], vi_i = vb[i];
+    const GT gi_i = geo[i];
+    const Q4<R> vi_i = vb[i];
     const int cnt_i = A.ncount[i];
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
@@ -1401,7 +1438,8 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     R M[6] = {0, 0, 0, 0, 0, 0};  // 00 01 02 11 12 22
     R u[3] = {0, 0, 0};           // sum_j W'_ij V_j r_ij / r, for the shift's B_i term
     int near = 0;
-    Q4<R> gi{0, 0, 0, 0}, vi{0, 0, 0, 0};
+    GT gi{};
+    Q4<R> vi{0, 0, 0, 0};
     int cnt = 0, phi = 0;
     if (c.lane) {
         gi = gi_i;
@@ -1416,15 +1454,15 @@ __global__ __launch_bounds__(kBlock) void k_advection(DevArrays A)
     const R eta_o = (R)(phi ? S.eta[0] : S.eta[1]);
     const R eta_x = eta_i + eta_o > R(0) ? R(2) * eta_i * eta_o / (eta_i + eta_o) : R(0);
     nl.run(
-        g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], vb[j]}}; },
-        [&](uint32_t ent, const Recs<R, 2>& rj) {
-            const Q4<R> gj = rj.q[0];
+        g, cnt, [&](uint32_t j) { return GRecs<GT, R, 1>{geo[j], {vb[j]}}; },
+        [&](uint32_t ent, const GRecs<GT, R, 1>& rj) {
+            const GT gj = rj.g;
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_dist<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
-            const Q4<R> vj = rj.q[1];
+            const Q4<R> vj = rj.q[0];
             const R Vj = vj.w;  // volume, stored beside the velocity
             // a wall neighbour: the fluid's own viscosity against the wall's
             // velocity, with the mirror's volume V_i
@@ -1893,12 +1931,13 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
         if (!__any(c0.lane && (A.flags[i] & kFlagInterface))) return;
     }
     // loads that need only the slot, issued together
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    using GT = typename GeoT<R, D>::T;
+    const GT* geo = (const GT*)A.geo;
     NbrList<G, PassChunk<R, D, Pass::Colour>::N> nl;
     nl.start(A, i, g);
     const int fl = A.flags[i];
     const int cnt_i = A.ncount[i];
-    const Q4<R> gi_i = geo[i];
+    const GT gi_i = geo[i];
     const Slot c = lookup_slot(A, i);
     if (c.s < 0) return;
     SysDyn& Dy = A.sd[c.s];
@@ -1913,21 +1952,21 @@ __global__ __launch_bounds__(kBlock) void k_colour(DevArrays A)
     const FromPressure<R> fp(S);
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
-    const Q4<R> gi = on ? gi_i : Q4<R>{0, 0, 0, 0};
+    const GT gi = on ? gi_i : GT{};
     const int cnt = on ? cnt_i : 0;
     const int phi = Geo<R>::phase(gi);
     R gsum[3] = {0, 0, 0};
     nl.run(
-        g, cnt, [&](uint32_t j) { return Recs<R, 2>{{geo[j], th[j]}}; },
-        [&](uint32_t ent, const Recs<R, 2>& rj) {
-            const Q4<R> gj = rj.q[0];
+        g, cnt, [&](uint32_t j) { return GRecs<GT, R, 1>{geo[j], {th[j]}}; },
+        [&](uint32_t ent, const GRecs<GT, R, 1>& rj) {
+            const GT gj = rj.g;
             const int phj = Geo<R>::phase(gj);
             if (phj == phi || phj == kWall) return;  // walls carry no colour
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_dist<R>(r2);
-            const R Vj = PK ? fp.m(phj) * recip<R>(fp.rho(phj, rj.q[1].w)) : rj.q[1].y;
+            const R Vj = PK ? fp.m(phj) * recip<R>(fp.rho(phj, rj.q[0].w)) : rj.q[0].y;
             const R f = wendland_dw<R>(r2 * inv_r * inv_h, coef) * Vj * inv_r;
             gsum[0] += f * r[0];
             gsum[1] += f * r[1];
@@ -1962,13 +2001,14 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
         if (c0.s < 0 || !substep_on(A.sd[c0.s], A.mode)) return;
     }
     // loads that need only the slot, issued together
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    using GT = typename GeoT<R, D>::T;
+    const GT* geo = (const GT*)A.geo;
     const Q4<R>* col = (const Q4<R>*)A.col;
     NbrList<G, PassChunk<R, D, Pass::Force>::N> nl;
     nl.start(A, i, g);
     const int fl = A.flags[i];
     const int cnt_i = A.ncount[i];
-    const Q4<R> gi_i = geo[i];
+    const GT gi_i = geo[i];
     // particles away from the interface all read entry 0 (one cache line)
     const Q4<R> ci_i = col[(fl & kFlagNearInterface) ? i : 0];
     const Q4<R> av_i = ((const Q4<R>*)A.av)[i];
@@ -1990,7 +2030,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     const R c0 = (R)S.c0, three_inv_c0 = (R)(3.0 * S.inv_c0);
     // the kernel gradient's constants: 1 / (2h) and coef / h (W' below)
     const R half_inv_h = (R)(0.5 * S.inv_h), coef_h = (R)(S.dw_coef * S.inv_h);
-    const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
+    const GT gi = c.lane ? gi_i : GT{};
     const int phi = Geo<R>::phase(gi);
     Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
     if (c.lane) {
@@ -2021,11 +2061,11 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
     nl.run(
         g, cnt,
         [&](uint32_t j) {
-            if constexpr (PK) return Recs<R, 2>{{geo[j], vin[j]}};
-            else return Recs<R, 3>{{geo[j], th[j], vin[j]}};
+            if constexpr (PK) return GRecs<GT, R, 1>{geo[j], {vin[j]}};
+            else return GRecs<GT, R, 2>{geo[j], {th[j], vin[j]}};
         },
-        [&](uint32_t ent, const Recs<R, NR>& rj) {
-            const Q4<R> gj = rj.q[0];
+        [&](uint32_t ent, const GRecs<GT, R, NR - 1>& rj) {
+            const GT gj = rj.g;
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -2034,7 +2074,7 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
             // W'(r) = coef (r/h) (1 - r/(2h))^3
             const R a = R(1) - rr * half_inv_h;
             const R dW = coef_h * rr * (a * a * a);
-            const Q4<R> vj = rj.q[NR - 1];
+            const Q4<R> vj = rj.q[NR - 2];
             const int phj = Geo<R>::phase(gj);
             // packed: rho_j from the pressure, V_j = m_j / rho_j folded into the
             // one reciprocal below
@@ -2044,9 +2084,9 @@ __global__ __launch_bounds__(kBlock) void k_force(DevArrays A)
                 pR = vj.w;
                 mR = fpr.m(phj);
             } else {
-                rhoR = rj.q[1].x;
-                pR = rj.q[1].z;
-                Vj = rj.q[1].y;
+                rhoR = rj.q[0].x;
+                pR = rj.q[0].z;
+                Vj = rj.q[0].y;
             }
             // Eq. 10 states (U = -v . e), Eq. 11 limiter, Eqs. 8 and 12:
             // U_L - U_R = (v_j - v_i) . e
@@ -2230,11 +2270,12 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
         if (idle) return;
     }
     // loads that need only the slot, issued together
-    const Q4<R>* geo = (const Q4<R>*)A.geo;
+    using GT = typename GeoT<R, D>::T;
+    const GT* geo = (const GT*)A.geo;
     NbrList<G, PassChunk<R, D, Pass::Continuity>::N> nl;
     nl.start(A, i, g);
     const int cnt_i = A.ncount[i];
-    const Q4<R> gi_i = geo[i];
+    const GT gi_i = geo[i];
     // FP64 state of the particle for the update that follows the sum
     const double rho_i = A.rho[i], mass_i = A.mass[i];
     double pos_i[3] = {0.0, 0.0, 0.0}, vel_i[3] = {0.0, 0.0, 0.0};
@@ -2285,7 +2326,7 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
     R cellr[3] = {(R)S.cell[0], (R)S.cell[1], (R)S.cell[2]};
     const R inv_h = (R)S.inv_h, coef = (R)S.dw_coef;
     const R inv_c0 = (R)S.inv_c0;
-    const Q4<R> gi = c.lane ? gi_i : Q4<R>{0, 0, 0, 0};
+    const GT gi = c.lane ? gi_i : GT{};
     Q4<R> ti{1, 0, 0, 0}, vi{0, 0, 0, 0};
     if (c.lane) {
         vi = vk[i];
@@ -2299,17 +2340,17 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
     nl.run(
         g, cnt,
         [&](uint32_t j) {
-            if constexpr (PK) return Recs<R, 2>{{geo[j], vk[j]}};
-            else return Recs<R, 3>{{geo[j], th[j], vk[j]}};
+            if constexpr (PK) return GRecs<GT, R, 1>{geo[j], {vk[j]}};
+            else return GRecs<GT, R, 2>{geo[j], {th[j], vk[j]}};
         },
-        [&](uint32_t ent, const Recs<R, NR>& rj) {
-            const Q4<R> gj = rj.q[0];
+        [&](uint32_t ent, const GRecs<GT, R, NR - 1>& rj) {
+            const GT gj = rj.g;
             R r[3];
             Geo<R>::template rij<D>(gi, gj, ent, S, cellr, r);
             const R r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
             const R inv_r = rsqrt_dist<R>(r2);
             const R dW = wendland_dw<R>(r2 * inv_r * inv_h, coef);
-            const Q4<R> vj = rj.q[NR - 1];
+            const Q4<R> vj = rj.q[NR - 2];
             const int phj = Geo<R>::phase(gj);
             const R vie = (vi.x * r[0] + vi.y * r[1] + vi.z * r[2]) * inv_r;
             const R vje = (vj.x * r[0] + vj.y * r[1] + vj.z * r[2]) * inv_r;
@@ -2328,9 +2369,9 @@ __global__ __launch_bounds__(kBlock) void k_continuity(DevArrays A, int64_t grou
                 pj = vj.w;
                 q = fpr.m(phj) * recip<R>((ti.x + rhoj) * rhoj);
             } else {
-                rhoj = rj.q[1].x;
-                pj = rj.q[1].z;
-                q = rj.q[1].y * recip<R>(ti.x + rhoj);
+                rhoj = rj.q[0].x;
+                pj = rj.q[0].z;
+                q = rj.q[0].y * recip<R>(ti.x + rhoj);
             }
             s += (rhoj * (vie - vje) + (ti.z - pj) * inv_c0) * q * dW;
         });
