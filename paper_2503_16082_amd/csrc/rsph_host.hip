@@ -358,6 +358,7 @@ size_t plan_arrays(Mem& M, int dim, int precision, DevArrays& A, int32_t*& mask,
     A.nbr = M.template take<uint32_t>(Pc * (size_t)A.kmax);
     A.ncount = M.template take<int32_t>(Pc);
     A.xd = M.template take<double>(Pc * (dim == 2 ? 2 : 4));
+    A.xq = M.template take<uint32_t>(dim == 3 ? 3 * Pc : 1);
     A.r_acc = M.template take<double>(3 * Pc);
     A.r_accp = M.template take<double>(3 * Pc);
     A.r_accs = M.template take<double>(3 * Pc);

@@ -205,6 +205,8 @@ struct DevArrays {
     int32_t* ncount;
     double* xd;      // frozen FP64 position per slot (D doubles, phase in the signs of x and y),
                      // read by the neighbour build and the density summation
+    uint32_t* xq;    // 3D: fixed-point offsets from the cell corner (3 per slot, 31 bits and a
+                     // phase bit each), read by the mixed form's density summation
     // rates written by an evaluation (FP64, slot order)
     double* r_acc;    // 3 * P
     double* r_accp;

@@ -117,6 +117,27 @@ __device__ __forceinline__ void store_pos(const DevArrays& A, int64_t j, const d
     else ((double4*)A.xd)[j] = double4{x0, x1, x[2], 0.0};
 }
 
+// The fixed-point offset of slot j from its cell corner along each axis, in
+// units of cell / 2^31 (31 bits, within 5e-10 of a cell of the FP64 value),
+// with phase bit 0 and 1 in bit 31 of the x and y words: 12 bytes that give a
+// pair distance to FP64 precision of about 1e-9 h, the mixed form's input to
+// the 3D density summation.
+struct U3 {
+    uint32_t x, y, z;
+};
+
+__device__ __forceinline__ int cell_of(double x, const SysConst& S, int a);
+
+__device__ __forceinline__ void store_xq(const DevArrays& A, int64_t j, const double* x, int ph, const SysConst& S)
+{
+    uint32_t u[3];
+    for (int a = 0; a < 3; ++a) {
+        const double t = (x[a] - (double)cell_of(x[a], S, a) * S.cell[a]) * (2147483648.0 * S.inv_cell[a]);
+        u[a] = (uint32_t)fmin(fmax(rint(t), 0.0), 2147483647.0);
+    }
+    ((U3*)A.xq)[j] = U3{u[0] | ((uint32_t)(ph & 1) << 31), u[1] | ((uint32_t)(ph & 2) << 30), u[2]};
+}
+
 // FP64 position of slot j from its packed record, and its phase
 template <int D>
 __device__ __forceinline__ void load_pos(const DevArrays& A, int64_t j, double* x, int* ph = nullptr)
@@ -830,6 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevArrays A, int64_t clear_n)
             v2 += v[a] * v[a];
         }
         store_pos<D>(A, d, x, ph);
+        if constexpr (D == 3) store_xq(A, d, x, ph, S);
         A.rho[d] = rho;
         A.drho[d] = drho;
         A.mass[d] = mass;
@@ -1166,6 +1188,31 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
     int coincident = 0, close = 0, cross = 0;
     // in 2D every lane's few entries are gathered at once
     constexpr int CH = D == 2 ? 4 : Chunk<R, D>::N;
+    if constexpr (D == 3 && sizeof(R) == 4) {
+        // mixed form: r_ij from the fixed-point offsets and the cell
+        // difference of the list entry, (u_i - u_j - dx 2^31) cell / 2^31,
+        // exact but for the one rounding of the product
+        const U3* xq = (const U3*)A.xq;
+        const U3 ui = xq[i];
+        const double qc[3] = {S.cell[0] * 0x1p-31, S.cell[1] * 0x1p-31, S.cell[2] * 0x1p-31};
+        for_neighbours<G, CH>(
+            A, i, g, live ? cnt : 0, [&](uint32_t j) { return xq[j]; },
+            [&](uint32_t e, const U3& q) {
+                const int phj = (int)((q.x >> 31) | ((q.y >> 30) & 2u));
+                cross |= phj != ph && phj != kWall;  // walls carry no colour
+                const uint32_t f = e ^ 0x54000000u;
+                const double rx = ((double)(int32_t)((ui.x & 0x7fffffffu) - (q.x & 0x7fffffffu)) -
+                                   (double)((int32_t)(f << 4) >> 30) * 2147483648.0) * qc[0];
+                const double ry = ((double)(int32_t)((ui.y & 0x7fffffffu) - (q.y & 0x7fffffffu)) -
+                                   (double)((int32_t)(f << 2) >> 30) * 2147483648.0) * qc[1];
+                const double rz = ((double)(int32_t)(ui.z - q.z) - (double)((int32_t)f >> 30) * 2147483648.0) *
+                                  qc[2];
+                const double r2 = rx * rx + ry * ry + rz * rz;
+                wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
+                coincident |= r2 < S.coincident2;
+                close |= r2 < S.close2;
+            });
+    } else
     for_neighbours<G, CH>(
         A, i, g, live ? cnt : 0,
         [&](uint32_t j) {
