@@ -1208,7 +1208,13 @@ __device__ __forceinline__ bool density_summation(const DevArrays& A, const SysC
                 const double rz = ((double)(int32_t)(ui.z - q.z) - (double)((int32_t)f >> 30) * 2147483648.0) *
                                   qc[2];
                 const double r2 = rx * rx + ry * ry + rz * rz;
-                wsum += wendland_w(sqrt(r2) * S.inv_h, S.w_alpha);
+                // r to about 1e-13: the hardware reciprocal square root
+                // (about 2^-22) and one Newton step, far inside the 1e-9 h of
+                // the offsets; r = 0 (a flagged coincident pair) kept exact
+                const double y0 = __builtin_amdgcn_rsq(r2);
+                const double y1 = y0 * (1.5 - 0.5 * r2 * y0 * y0);
+                const double r = r2 > 0.0 ? r2 * y1 : 0.0;
+                wsum += wendland_w(r * S.inv_h, S.w_alpha);
                 coincident |= r2 < S.coincident2;
                 close |= r2 < S.close2;
             });
