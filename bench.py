@@ -57,13 +57,14 @@ CONT_OPS = {2: 37, 3: 46}
 # Algorithmic HBM bytes of one force-pass launch (the packed form, which every
 # workload here takes: one particle mass per fluid): each particle's own
 # records read once (frozen position, {velocity, pressure}, viscous
-# acceleration: 16 B each in the mixed form, 32 B in FP64), count and flags
+# acceleration: 16 B each in the mixed form, but 12 B for the 3D frozen
+# position, 32 B each in FP64), count and flags
 # (5 B), the FP64 velocity read and written (2 x 8d B) and the kicked
 # {velocity, pressure} record written; 4 B of neighbour index per pair; the
 # colour record of near-interface particles.  Neighbour records gathered per
 # pair are cache traffic.
 FORCE_BYTES = {  # (per particle, per pair, per near-interface particle)
-    (2, "mixed"): (101, 4, 16), (3, "mixed"): (117, 4, 16),
+    (2, "mixed"): (101, 4, 16), (3, "mixed"): (113, 4, 16),
     (2, "fp64"): (165, 4, 32), (3, "fp64"): (181, 4, 32),
 }
 
