@@ -31,7 +31,7 @@ constexpr int kBlock = 256;
 constexpr int64_t kFuseDtEntries = 1024;
 constexpr int kKmax2 = 64;   // neighbour capacity per particle, 2D (20 on a lattice)
 constexpr int kKmax3 = 192;  // 3D (80 on a lattice)
-constexpr int kMaxCellsPerAxis = 512;  // 9 bits per axis in the mixed-form geometry tag
+constexpr int kMaxCellsPerAxis = 512;  // a system's cell keys then stay below 2^27
 constexpr int kMaxLanes = 16;  // lanes per particle slot in the pair passes (at most)
 constexpr int kNbrIndexBits = 26;
 constexpr uint32_t kNbrIndexMask = (1u << kNbrIndexBits) - 1u;
