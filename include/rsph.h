@@ -64,7 +64,9 @@ typedef enum {
 enum {
     RSPH_FP64 = 0, /* every operation in FP64: the reference form */
     RSPH_MIXED = 1 /* FP32 pair loops on split (cell index + FP32 offset) positions,
-                      FP64 state, integrator, reductions and diagnostics */
+                      FP64 state, integrator, reductions and diagnostics; the
+                      density summation in FP64 (in 3D on distances from 31-bit
+                      fixed-point cell offsets, within about 1e-9 h) */
 };
 
 /* method switches (rsph_params.flags) */
